@@ -1,0 +1,419 @@
+/*
+ * kc_oracle.c -- reference (oracle) implementation of the kappa-cycle method.
+ *
+ * TEST INFRASTRUCTURE ONLY: a plain, slow, single-threaded CPU implementation
+ * written from the paper (Avnat & Yavneh, "On the recursive structure of
+ * multigrid cycles").  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.  It shares no code with the GPU library.
+ *
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared (no fused
+ * multiply-add anywhere: every product and sum is rounded on its own).
+ *
+ * What each part follows:
+ *   - fine operator: the nine-point stencil table of Section 4;
+ *   - coarse operators: Galerkin A_{l+1} = R A_l P with full weighting R and
+ *     bilinear prolongation P (Section 4, the Galerkin solvers; R is the
+ *     adjoint of P as stated in the symmetry discussion of Section 4);
+ *   - relaxation: damped Jacobi, simultaneous update (Section 4);
+ *   - cycles: Algorithm 1 (gamma-cycle), Algorithm 2 (F-cycle) and
+ *     Algorithm 3 (kappa-cycle), recursion exactly as printed, including the
+ *     redundant second call at the level above the coarsest (Section 1);
+ *   - drivers: the stand-alone cycle and CG preconditioned by one cycle per
+ *     iteration (Section 4, solvers one and two).
+ */
+#include "kc_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t* buf;
+    int64_t cap;
+    int64_t len;
+} or_tr;
+
+static void tr_push(or_tr* t, int op, int level, int counter)
+{
+    if (!t) return;
+    if (t->buf && t->len < t->cap) {
+        int c = counter < 0 ? 0 : (counter > 0xffff ? 0xffff : counter);
+        t->buf[t->len] = (int32_t)(((uint32_t)op << 24) | ((uint32_t)level << 16) | (uint32_t)c);
+    }
+    t->len++;
+}
+
+#define REAL double
+#define SFX(x) x##_d
+#include "kc_oracle_levels.inc"
+#undef REAL
+#undef SFX
+
+#define REAL float
+#define SFX(x) x##_s
+#include "kc_oracle_levels.inc"
+#undef REAL
+#undef SFX
+
+struct or_hier {
+    lv_d d;          /* FP64 hierarchy                                  */
+    lv_s s;          /* FP32 copy used by the FP32 cycle                */
+    double theta, eps, omega;
+    double* fine_v;  /* owned fine-level storage when no user array is bound */
+    double* fine_f;
+    float* fine_v32;
+    float* fine_f32;
+};
+
+/* ------------------------------------------------------------------ */
+/* discrete problem (Section 4)                                         */
+/* ------------------------------------------------------------------ */
+
+void or_fine_stencil(double theta, double eps, double s[9])
+{
+    double C = cos(theta), S = sin(theta);
+    double cross = 0.5 * (1.0 - eps) * C * S;
+    double we = -(C * C + eps * S * S);    /* west / east      */
+    double sn = -(eps * C * C + S * S);    /* south / north    */
+    s[0] = -cross; s[1] = sn;                s[2] = cross;    /* SW  S  SE */
+    s[3] = we;     s[4] = 2.0 * (1.0 + eps); s[5] = we;       /* W   C  E  */
+    s[6] = cross;  s[7] = sn;                s[8] = -cross;   /* NW  N  NE */
+}
+
+void or_fine_stencil_derivs(double theta, double eps, double dth[9], double deps[9])
+{
+    double C = cos(theta), S = sin(theta);
+    /* d/dtheta: C' = -S, S' = C */
+    double d_cross = 0.5 * (1.0 - eps) * (C * C - S * S);
+    double d_we = 2.0 * (1.0 - eps) * C * S;
+    double d_sn = -2.0 * (1.0 - eps) * C * S;
+    dth[0] = -d_cross; dth[1] = d_sn; dth[2] = d_cross;
+    dth[3] = d_we;     dth[4] = 0.0;  dth[5] = d_we;
+    dth[6] = d_cross;  dth[7] = d_sn; dth[8] = -d_cross;
+    /* d/deps */
+    double e_cross = -0.5 * C * S;
+    double e_we = -S * S;
+    double e_sn = -C * C;
+    deps[0] = -e_cross; deps[1] = e_sn; deps[2] = e_cross;
+    deps[3] = e_we;     deps[4] = 2.0;  deps[5] = e_we;
+    deps[6] = e_cross;  deps[7] = e_sn; deps[8] = -e_cross;
+}
+
+void or_apply_stencil(int n, const double s[9], const double* x, double* y)
+{
+    apply_d(n, s, 1.0, x, y);
+}
+
+void or_restrict_fw(int n, const double* r, double* fc) { restr_d(n, r, fc); }
+
+void or_prolong(int nc, const double* vc, double* e) { prol_d(nc, vc, e); }
+
+/* Galerkin coarse stencil: with A = S/h^2 on each level and h_c = 2h,
+ * S_c = h_c^2 R (S/h^2) P = 4 R S P.  It is read off by applying R S P to a
+ * coarse unit vector on a 5x5 coarse grid (11x11 fine), far enough from the
+ * boundary that no term is cut off. */
+void or_galerkin_stencil(const double sf[9], double sc[9])
+{
+    enum { NC = 5, NF = 11 };
+    double ec[NC * NC], e[NF * NF], ae[NF * NF], rc[NC * NC];
+    memset(ec, 0, sizeof ec);
+    ec[2 * NC + 2] = 1.0;
+    prol_d(NC, ec, e);
+    apply_d(NF, sf, 1.0, e, ae);
+    restr_d(NF, ae, rc);
+    for (int b = -1; b <= 1; ++b)
+        for (int a = -1; a <= 1; ++a)
+            sc[3 * (b + 1) + (a + 1)] = 4.0 * rc[(2 + b) * NC + (2 + a)];
+}
+
+/* ------------------------------------------------------------------ */
+/* hierarchy                                                            */
+/* ------------------------------------------------------------------ */
+
+static int is_pow2(long x) { return x > 0 && (x & (x - 1)) == 0; }
+
+void or_hier_free(or_hier* h)
+{
+    if (!h) return;
+    for (int k = 0; k < OR_MAXL; ++k) {
+        if (k > 0) {
+            free(h->d.v[k]); free(h->d.f[k]);
+            free(h->s.v[k]); free(h->s.f[k]);
+        }
+        free(h->d.t[k]);
+        free(h->s.t[k]);
+    }
+    free(h->fine_v); free(h->fine_f); free(h->fine_v32); free(h->fine_f32);
+    free(h->d.chol);
+    free(h->s.chol);
+    free(h);
+}
+
+int or_hier_new(int n, double theta, double eps, int n_coarsest, double omega, or_hier** out)
+{
+    *out = NULL;
+    if (n < 1 || n_coarsest < 1 || n_coarsest > n) return OR_ERR_ARG;
+    if (!is_pow2((long)n + 1) || !is_pow2((long)n_coarsest + 1)) return OR_ERR_ARG;
+    int L = 1;
+    while (((n + 1) >> (L - 1)) > n_coarsest + 1) ++L;
+    if (L > OR_MAXL) return OR_ERR_ARG;
+
+    or_hier* h = (or_hier*)calloc(1, sizeof(or_hier));
+    if (!h) return OR_ERR_ARG;
+    h->theta = theta; h->eps = eps; h->omega = omega;
+    h->d.L = h->s.L = L;
+    for (int k = 0; k < L; ++k) {
+        int nk = ((n + 1) >> k) - 1;
+        size_t m = (size_t)nk * nk;
+        h->d.n[k] = h->s.n[k] = nk;
+        h->d.h2inv[k] = (double)(nk + 1) * (double)(nk + 1);
+        if (k == 0) or_fine_stencil(theta, eps, h->d.s[0]);
+        else or_galerkin_stencil(h->d.s[k - 1], h->d.s[k]);
+        h->d.wjac[k] = omega / (h->d.s[k][4] * h->d.h2inv[k]);
+        h->d.t[k] = (double*)calloc(m, sizeof(double));
+        h->s.t[k] = (float*)calloc(m, sizeof(float));
+        if (k > 0) {
+            h->d.v[k] = (double*)calloc(m, sizeof(double));
+            h->d.f[k] = (double*)calloc(m, sizeof(double));
+            h->s.v[k] = (float*)calloc(m, sizeof(float));
+            h->s.f[k] = (float*)calloc(m, sizeof(float));
+            if (!h->d.v[k] || !h->d.f[k] || !h->s.v[k] || !h->s.f[k]) { or_hier_free(h); return OR_ERR_ARG; }
+        }
+        if (!h->d.t[k] || !h->s.t[k]) { or_hier_free(h); return OR_ERR_ARG; }
+        /* FP32 copy: every coefficient rounded once from its FP64 value */
+        for (int q = 0; q < 9; ++q) h->s.s[k][q] = (float)h->d.s[k][q];
+        h->s.h2inv[k] = (float)h->d.h2inv[k];
+        h->s.wjac[k] = (float)h->d.wjac[k];
+    }
+    if (factor_coarsest_d(&h->d) != OR_OK || factor_coarsest_s(&h->s) != OR_OK) {
+        or_hier_free(h);
+        return OR_BREAKDOWN;
+    }
+    size_t m0 = (size_t)n * n;
+    h->fine_v = (double*)calloc(m0, sizeof(double));
+    h->fine_f = (double*)calloc(m0, sizeof(double));
+    h->fine_v32 = (float*)calloc(m0, sizeof(float));
+    h->fine_f32 = (float*)calloc(m0, sizeof(float));
+    if (!h->fine_v || !h->fine_f || !h->fine_v32 || !h->fine_f32) { or_hier_free(h); return OR_ERR_ARG; }
+    *out = h;
+    return OR_OK;
+}
+
+int or_hier_info(const or_hier* h, int* nlevels, int* sizes, double* stencils)
+{
+    *nlevels = h->d.L;
+    for (int k = 0; k < h->d.L; ++k) {
+        if (sizes) sizes[k] = h->d.n[k];
+        if (stencils) memcpy(stencils + 9 * k, h->d.s[k], 9 * sizeof(double));
+    }
+    return OR_OK;
+}
+
+void or_hier_apply(const or_hier* h, const double* x, double* y)
+{
+    apply_d(h->d.n[0], h->d.s[0], h->d.h2inv[0], x, y);
+}
+
+/* ------------------------------------------------------------------ */
+/* cycles                                                               */
+/* ------------------------------------------------------------------ */
+
+int64_t or_cycle(or_hier* h, int kind, int param, int nu1, int nu2,
+                 double* v, const double* f, int32_t* tr, int64_t cap)
+{
+    or_tr t = {tr, cap, 0};
+    h->d.v[0] = v;
+    h->d.f[0] = (double*)f;
+    if (kind == 0) kcycle_d(&h->d, 1, param, nu1, nu2, &t);
+    else if (kind == 1) gcycle_d(&h->d, 1, param, nu1, nu2, &t);
+    else fcycle_d(&h->d, 1, nu1, nu2, &t);
+    h->d.v[0] = NULL;
+    h->d.f[0] = NULL;
+    return t.len;
+}
+
+void or_kcycle_f32(or_hier* h, int kappa, int nu1, int nu2, float* v, const float* f)
+{
+    h->s.v[0] = v;
+    h->s.f[0] = (float*)f;
+    kcycle_s(&h->s, 1, kappa, nu1, nu2, NULL);
+    h->s.v[0] = NULL;
+    h->s.f[0] = NULL;
+}
+
+/* ------------------------------------------------------------------ */
+/* drivers                                                              */
+/* ------------------------------------------------------------------ */
+
+static double sumsq(const double* x, size_t m)
+{
+    double acc = 0.0;
+    for (size_t k = 0; k < m; ++k) acc += x[k] * x[k];
+    return acc;
+}
+
+static double dot(const double* x, const double* y, size_t m)
+{
+    double acc = 0.0;
+    for (size_t k = 0; k < m; ++k) acc += x[k] * y[k];
+    return acc;
+}
+
+/* residual of the fine FP64 problem and its squared 2-norm */
+static double fine_residual(or_hier* h, const double* u, const double* f, double* r)
+{
+    resid_d(h->d.n[0], h->d.s[0], h->d.h2inv[0], u, f, r);
+    return sumsq(r, (size_t)h->d.n[0] * h->d.n[0]);
+}
+
+int or_solve(or_hier* h, int kappa, int nu1, int nu2, double* u, const double* f,
+             double tol, int maxit, int mode, int* iters, double* hist)
+{
+    size_t m = (size_t)h->d.n[0] * h->d.n[0];
+    double* r = h->fine_f;   /* scratch: residual */
+    double denom, ratio0 = 0.0;
+    *iters = 0;
+    if (kappa < 1 || nu1 < 0 || nu2 < 0 || maxit < 0) return OR_ERR_ARG;
+    if (mode == 0) denom = sqrt(sumsq(f, m));
+    else denom = sqrt(sumsq(u, m));
+    if (!isfinite(denom)) return OR_ERR_NONFINITE;
+    for (int k = 0;; ++k) {
+        double num = (mode == 0) ? sqrt(fine_residual(h, u, f, r)) : sqrt(sumsq(u, m));
+        double ratio = (denom > 0.0) ? num / denom : 0.0;
+        if (hist) hist[k] = ratio;
+        *iters = k;
+        if (!isfinite(ratio)) return OR_ERR_NONFINITE;
+        if (k == 0) ratio0 = ratio;
+        if (ratio < tol) return OR_OK;
+        if (ratio > 1e3 * ratio0) return OR_DIVERGED;
+        if (k == maxit) return OR_NOT_CONVERGED;
+        or_cycle(h, 0, kappa, nu1, nu2, u, f, NULL, 0);
+    }
+}
+
+double or_ir_scale(double ss, int64_t npoints)
+{
+    if (!(ss > 0.0) || !isfinite(ss)) return 1.0;
+    int e = ilogb(ss / (double)npoints);
+    int k = (int)floor((double)e / 2.0);
+    return ldexp(1.0, -k);
+}
+
+/* e = B r with B one zero-guess kappa-cycle in FP32:  the residual is scaled
+ * by a power of two, rounded to FP32, cycled, and scaled back in FP64 */
+static void precond_f32(or_hier* h, int kappa, int nu1, int nu2, const double* r,
+                        double ss, double* z)
+{
+    size_t m = (size_t)h->d.n[0] * h->d.n[0];
+    double sc = or_ir_scale(ss, (int64_t)m);
+    for (size_t q = 0; q < m; ++q) {
+        h->fine_f32[q] = (float)(sc * r[q]);
+        h->fine_v32[q] = 0.0f;
+    }
+    or_kcycle_f32(h, kappa, nu1, nu2, h->fine_v32, h->fine_f32);
+    for (size_t q = 0; q < m; ++q) z[q] = (double)h->fine_v32[q] / sc;
+}
+
+int or_ir_solve(or_hier* h, int kappa, int nu1, int nu2, double* u, const double* f,
+                double tol, int maxit, int* iters, double* hist)
+{
+    size_t m = (size_t)h->d.n[0] * h->d.n[0];
+    double* r = h->fine_f;
+    double* e = h->fine_v;
+    double normf = sqrt(sumsq(f, m)), ratio0 = 0.0;
+    *iters = 0;
+    if (kappa < 1 || nu1 < 0 || nu2 < 0 || maxit < 0) return OR_ERR_ARG;
+    if (!isfinite(normf)) return OR_ERR_NONFINITE;
+    for (int k = 0;; ++k) {
+        double ss = fine_residual(h, u, f, r);
+        double ratio = (normf > 0.0) ? sqrt(ss) / normf : 0.0;
+        if (hist) hist[k] = ratio;
+        *iters = k;
+        if (!isfinite(ratio)) return OR_ERR_NONFINITE;
+        if (k == 0) ratio0 = ratio;
+        if (ratio < tol) return OR_OK;
+        if (ratio > 1e3 * ratio0) return OR_DIVERGED;
+        if (k == maxit) return OR_NOT_CONVERGED;
+        precond_f32(h, kappa, nu1, nu2, r, ss, e);
+        for (size_t q = 0; q < m; ++q) u[q] = u[q] + e[q];
+    }
+}
+
+int or_pcg(or_hier* h, int kappa, int nu1, int nu2, int precond_f32_flag,
+           double* u, const double* f, double tol, int maxit, int* iters, double* hist)
+{
+    size_t m = (size_t)h->d.n[0] * h->d.n[0];
+    int rc = OR_OK;
+    *iters = 0;
+    if (kappa < 1 || nu1 < 0 || nu2 < 0 || maxit < 0) return OR_ERR_ARG;
+    double* r = (double*)malloc(m * sizeof(double));
+    double* z = (double*)malloc(m * sizeof(double));
+    double* p = (double*)malloc(m * sizeof(double));
+    double* q = (double*)malloc(m * sizeof(double));
+    if (!r || !z || !p || !q) { rc = OR_ERR_ARG; goto done; }
+
+    /* x_0 = 0, r_0 = f */
+    for (size_t k = 0; k < m; ++k) { u[k] = 0.0; r[k] = f[k]; }
+    double normf = sqrt(sumsq(f, m));
+    if (!isfinite(normf)) { rc = OR_ERR_NONFINITE; goto done; }
+    double ssr = sumsq(r, m);
+    double ratio = (normf > 0.0) ? sqrt(ssr) / normf : 0.0;
+    if (hist) hist[0] = ratio;
+    if (!isfinite(ratio)) { rc = OR_ERR_NONFINITE; goto done; }
+    if (ratio < tol) goto done;
+
+    double rz = 0.0;
+    for (int it = 0;; ++it) {
+        if (it == maxit) { rc = OR_NOT_CONVERGED; break; }
+        /* z = B r */
+        if (precond_f32_flag) {
+            precond_f32(h, kappa, nu1, nu2, r, ssr, z);
+        } else {
+            memset(z, 0, m * sizeof(double));
+            or_cycle(h, 0, kappa, nu1, nu2, z, r, NULL, 0);
+        }
+        double rz_new = dot(r, z, m);
+        if (it == 0) {
+            memcpy(p, z, m * sizeof(double));
+        } else {
+            double beta = rz_new / rz;   /* Fletcher-Reeves */
+            for (size_t k = 0; k < m; ++k) p[k] = z[k] + beta * p[k];
+        }
+        rz = rz_new;
+        apply_d(h->d.n[0], h->d.s[0], h->d.h2inv[0], p, q);
+        double pq = dot(p, q, m);
+        if (!(pq > 0.0) || !isfinite(pq)) { rc = isfinite(pq) ? OR_BREAKDOWN : OR_ERR_NONFINITE; break; }
+        double alpha = rz / pq;
+        for (size_t k = 0; k < m; ++k) {
+            u[k] = u[k] + alpha * p[k];
+            r[k] = r[k] - alpha * q[k];
+        }
+        ssr = sumsq(r, m);
+        ratio = sqrt(ssr) / normf;
+        *iters = it + 1;
+        if (hist) hist[it + 1] = ratio;
+        if (!isfinite(ratio)) { rc = OR_ERR_NONFINITE; break; }
+        if (ratio < tol) break;
+    }
+done:
+    free(r); free(z); free(p); free(q);
+    return rc;
+}
+
+void or_grad_params(const or_hier* h, double theta, double eps, const double* lam,
+                    const double* u, double* dtheta, double* deps)
+{
+    int n = h->d.n[0];
+    size_t m = (size_t)n * n;
+    double dth[9], de[9];
+    or_fine_stencil_derivs(theta, eps, dth, de);
+    double* y = (double*)malloc(m * sizeof(double));
+    apply_d(n, dth, h->d.h2inv[0], u, y);
+    *dtheta = -dot(lam, y, m);
+    apply_d(n, de, h->d.h2inv[0], u, y);
+    *deps = -dot(lam, y, m);
+    free(y);
+}
+
+/* the FP32 instantiation only needs the kappa-cycle */
+static void (*const or_unused_fcycle_s)(lv_s*, int, int, int, or_tr*) __attribute__((unused)) = fcycle_s;
