@@ -1,0 +1,173 @@
+/*
+ * kcycle.h -- C-ABI of libkcycle.so, an MI355X (gfx950) implementation of the
+ * kappa-cycle multigrid method of Avnat & Yavneh, "On the recursive structure
+ * of multigrid cycles", for the 2D rotated anisotropic diffusion equation.
+ *
+ * Problem (Section 4): -div(D grad u) = f on the unit square, u = 0 on the
+ * boundary, D = R(theta) diag(1, eps) R(theta)^T, discretised with the
+ * nine-point stencil table of Section 4 on an n x n interior grid
+ * (h = 1/(n+1)), n = 2^L - 1.  The operator is A = S / h^2.
+ *
+ * Array layout (every u, f, x, y, lam argument): row-major, element (j, i) at
+ * p[j * ld + i], row j along +y, column i along +x, interior points only,
+ * ld >= n.  Arrays are caller-owned device memory (e.g. torch tensors).
+ *
+ * Hierarchy: levels l = 1..L with n_l = 2^(L-l+1) - 1 down to n_coarsest
+ * (1, 3 or 7); coarse operators are Galerkin, A_{l+1} = R A_l P with bilinear
+ * prolongation P and full weighting R = P^T / 4 (Section 4).
+ *
+ * Streams: every call is ordered on the hip stream given to kc_create.  Calls
+ * that return host values (kc_solve, kc_pcg, kc_grad_params, kc_stats)
+ * synchronise that stream before returning.
+ *
+ * Batches: a hierarchy may hold `count` independent instances of different
+ * sizes, angles and anisotropies.  Every array argument is then a host array
+ * of `count` device pointers and every ld / iters / relres argument a host
+ * array of `count` entries.  All instances advance together, one kernel
+ * launch per cycle stage (the call tree of an n-level instance is the top of
+ * a deeper instance's call tree, Proposition 2).
+ *
+ * Errors: every function returns kc_status.  Negative values are errors (the
+ * arrays keep their input values unless stated); positive values are
+ * algorithmic outcomes and leave the result arrays valid.  kc_last_error()
+ * gives a thread-local message for the last failing call.
+ *
+ * Memory: the library allocates no device memory of its own.  The caller asks
+ * kc_workspace_bytes for a size and passes a device buffer of that size
+ * (256-byte aligned) to kc_create; it must outlive the hierarchy.  Host-side
+ * allocations (tables, graphs, pinned staging) are owned by the handle.
+ * A handle is not thread-safe; use one per host thread.
+ */
+#ifndef KCYCLE_H
+#define KCYCLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KC_OK = 0,
+    KC_NOT_CONVERGED = 1,   /* maxit reached; result valid, relres filled        */
+    KC_DIVERGED = 2,        /* relres grew beyond 1e3 x its initial value         */
+    KC_BREAKDOWN = 3,       /* PCG: p^T A p <= 0 (indefinite preconditioner)      */
+    KC_ERR_ARG = -1,        /* invalid argument (size, counter, null pointer ...) */
+    KC_ERR_HIP = -2,        /* a HIP runtime call failed                          */
+    KC_ERR_WORKSPACE = -3,  /* workspace missing, too small or misaligned         */
+    KC_ERR_NONFINITE = -4,  /* NaN or Inf met in f or in a residual               */
+    KC_ERR_STATE = -5       /* call not valid for this hierarchy (e.g. precision) */
+} kc_status;
+
+typedef enum {
+    KC_F64 = 0,             /* cycles, vectors and norms in FP64                          */
+    KC_F32_CYCLE = 1        /* cycles in FP32; residuals, updates, CG recurrences in FP64 */
+} kc_precision;
+
+/* one problem instance: n = 2^L - 1 points per side; n_coarsest in {1, 3, 7}
+ * and n_coarsest <= n; 0 < eps; omega is the Jacobi damping factor */
+typedef struct {
+    int32_t n;
+    int32_t n_coarsest;
+    double theta;
+    double eps;
+} kc_problem;
+
+#define KC_KAPPA_W INT32_MAX   /* any kappa >= L gives the W-cycle (Proposition 1) */
+
+/* cycle parameters (Algorithm 3): counter kappa >= 1, nu1/nu2 >= 0 damped
+ * Jacobi sweeps before/after the coarse-grid correction, damping omega > 0 */
+typedef struct {
+    int32_t kappa;
+    int32_t nu1;
+    int32_t nu2;
+    int32_t reserved;
+    double omega;
+} kc_cycle_params;
+
+/* execution options; kc_exec_default fills the defaults */
+typedef struct {
+    int32_t mode;           /* 0 = fused kernels + persistent coarse subtree (default);
+                               1 = one kernel per operation of Algorithm 4 ("paper-structured") */
+    int32_t use_graph;      /* 1 = capture one cycle as a hipGraph and replay it (default) */
+    int32_t coarse_cutover; /* levels with n <= cutover run in the persistent kernel (31 or 63; default 63) */
+    int32_t coarse_threads; /* threads of the persistent kernel (256, 512 or 1024; default 512) */
+    int32_t poll_every;     /* cycles launched between host polls of the stop flags (default 0 = adaptive) */
+    int32_t reserved[3];
+} kc_exec;
+
+typedef struct kc_hier kc_hier;
+
+/* defaults for kc_exec */
+void kc_exec_default(kc_exec* e);
+
+/* bytes of device workspace for `count` instances (Section 3.1: all data are
+ * resident on the GPU after setup); no device work, no GPU needed */
+kc_status kc_workspace_bytes(const kc_problem* probs, int32_t count, kc_precision prec, size_t* bytes);
+
+/* build the hierarchies (fine stencil, Galerkin coarse stencils, coarsest
+ * inverse) on the host and copy them into the workspace; `exec` may be NULL
+ * for the defaults; `hip_stream` is a hipStream_t (NULL = default stream) */
+kc_status kc_create(const kc_problem* probs, int32_t count, kc_precision prec, const kc_exec* exec,
+                    void* d_workspace, size_t bytes, void* hip_stream, kc_hier** out);
+
+kc_status kc_destroy(kc_hier* h);
+
+/* change execution options (drops captured graphs) */
+kc_status kc_set_exec(kc_hier* h, const kc_exec* exec);
+
+/* one kappa-cycle (Algorithm 3) on every instance: v <- cycle(v, f), FP64
+ * arrays, asynchronous on the stream.  KC_ERR_STATE on an FP32 hierarchy. */
+kc_status kc_cycle(kc_hier* h, double* const* d_v, const int64_t* ldv, const double* const* d_f,
+                   const int64_t* ldf, const kc_cycle_params* c);
+
+/* stand-alone solver (Section 4, first solver): u holds the initial guess and
+ * receives the result.  Repeats kappa-cycles until ||f - A u_k|| / ||f|| < tol
+ * (relres checked before every cycle) or maxit cycles.  FP32 hierarchies run
+ * FP32 cycles inside FP64 iterative refinement.  iters[i] = cycles done,
+ * relres[i] = final relative residual.  The return value is the worst
+ * instance status.  Synchronises. */
+kc_status kc_solve(kc_hier* h, double* const* d_u, const int64_t* ldu, const double* const* d_f,
+                   const int64_t* ldf, const kc_cycle_params* c, double tol, int32_t maxit,
+                   int32_t* iters, double* relres, int32_t* status);
+
+/* conjugate gradients preconditioned by one zero-guess kappa-cycle per
+ * iteration (Section 4, second solver), x_0 = 0, Fletcher-Reeves beta, stop
+ * on the recurrence residual ||r_k|| / ||f|| < tol.  Vectors and dot products
+ * in FP64; the cycle in FP32 on FP32 hierarchies.  Synchronises. */
+kc_status kc_pcg(kc_hier* h, double* const* d_u, const int64_t* ldu, const double* const* d_f,
+                 const int64_t* ldf, const kc_cycle_params* c, double tol, int32_t maxit,
+                 int32_t* iters, double* relres, int32_t* status);
+
+/* y = A x on every instance's fine level (FP64), asynchronous */
+kc_status kc_apply_A(kc_hier* h, double* const* d_y, const int64_t* ldy, const double* const* d_x,
+                     const int64_t* ldx);
+
+/* parameter gradients of a scalar loss through u = A(theta, eps)^{-1} f:
+ * dtheta[i] = -lam_i^T (dA/dtheta) u_i and deps[i] = -lam_i^T (dA/deps) u_i,
+ * lam the adjoint solution (A is symmetric).  FP64.  Synchronises. */
+kc_status kc_grad_params(kc_hier* h, const double* const* d_lam, const int64_t* ldl, const double* const* d_u,
+                         const int64_t* ldu, double* dtheta, double* deps);
+
+/* host-only: the h^2-scaled 3x3 stencils of every level of one problem,
+ * s[9*l + 3*(b+1) + (a+1)] for offset (a, b) in (x, y); no GPU needed */
+kc_status kc_level_stencils(const kc_problem* p, int32_t max_levels, int32_t* nlevels, double* stencils);
+
+/* host-only: the flattened stage schedule of one cycle, as launches per cycle
+ * (grid kernels, persistent-kernel launches, persistent-kernel stages);
+ * no GPU needed */
+kc_status kc_schedule_counts(const kc_problem* probs, int32_t count, const kc_exec* exec,
+                             const kc_cycle_params* c, int64_t* grid_launches, int64_t* subtree_launches,
+                             int64_t* subtree_stages);
+
+/* JSON summary: sizes, launches per cycle, last solve's timings */
+kc_status kc_stats(const kc_hier* h, char* out, size_t cap);
+
+const char* kc_status_string(kc_status s);
+const char* kc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -320,7 +320,11 @@ int or_ir_solve(or_hier* h, int kappa, int nu1, int nu2, double* u, const double
     size_t m = (size_t)h->d.n[0] * h->d.n[0];
     double* r = h->fine_f;
     double* e = h->fine_v;
-    double normf = sqrt(sumsq(f, m)), ratio0 = 0.0;
+    double ssf = sumsq(f, m);
+    double normf = sqrt(ssf), ratio0 = 0.0;
+    /* the FP32 right-hand side of refinement step k is scaled by a power of
+     * two taken from the previous residual (from f for the first step) */
+    double ss_prev = ssf;
     *iters = 0;
     if (kappa < 1 || nu1 < 0 || nu2 < 0 || maxit < 0) return OR_ERR_ARG;
     if (!isfinite(normf)) return OR_ERR_NONFINITE;
@@ -334,7 +338,8 @@ int or_ir_solve(or_hier* h, int kappa, int nu1, int nu2, double* u, const double
         if (ratio < tol) return OR_OK;
         if (ratio > 1e3 * ratio0) return OR_DIVERGED;
         if (k == maxit) return OR_NOT_CONVERGED;
-        precond_f32(h, kappa, nu1, nu2, r, ss, e);
+        precond_f32(h, kappa, nu1, nu2, r, ss_prev, e);
+        ss_prev = ss;
         for (size_t q = 0; q < m; ++q) u[q] = u[q] + e[q];
     }
 }

@@ -1,0 +1,158 @@
+// kc_internal.h -- device-visible tables and kernel launch interface shared by
+// the host runtime (kc_runtime.cpp) and the HIP kernels (kc_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kc {
+
+constexpr int MAXL = 16;          // levels per instance
+constexpr int TX = 64;            // grid-kernel tile width  (one wave64 row)
+constexpr int TY = 32;            // grid-kernel tile height
+constexpr int GRID_THREADS = 256; // threads of the grid-wide kernels
+constexpr int HIST_CAP = 8192;    // relres history entries kept per instance
+
+// one level of one instance; arrays are row-major with leading dimension ld.
+// A holds the current estimate between calls, B is the second sweep buffer,
+// F the right-hand side.  Element type is double or float by precision.
+struct LevelDev {
+    void* A;
+    void* B;
+    void* F;
+    int32_t n;
+    int32_t ld;
+    double fscale;   // F is multiplied by fscale when loaded (h^2 for a user f, else 1)
+};
+
+struct InstDev {
+    int32_t L;           // number of levels
+    int32_t cut;         // first depth handled by the persistent coarse kernel
+    int32_t nc2;         // order of the coarsest matrix
+    int32_t sub_lds;     // LDS elements used by the persistent kernel
+    double s64[MAXL][9]; // h^2-scaled stencils, s[3*(b+1)+(a+1)] for offset (a, b)
+    float s32[MAXL][9];
+    double w64[MAXL];    // omega / s[4]
+    float w32[MAXL];
+    LevelDev lev[MAXL];  // cycle levels (level 0 may alias user arrays)
+    const double* cinv64;  // coarsest inverse, nc2 x nc2 row-major, h^2-scaled system
+    const float* cinv32;
+    int32_t lds_off[MAXL]; // persistent kernel: element offset of level d's v in LDS (F follows)
+    int32_t ops_off[MAXL + 2]; // persistent kernel op lists by counter 1..MAXL+1
+    const uint32_t* ops;       // op list storage
+    // FP64 vectors of the drivers (refinement / PCG); fine level, ld = ldv
+    double* u;           // user solution
+    const double* f;     // user right-hand side (unscaled)
+    int32_t ldu, ldf;
+    double* r;           // PCG residual
+    double* z;           // PCG preconditioned residual
+    double* p;           // PCG search direction
+    double* q;           // PCG A p
+    int32_t ldv;         // leading dimension of r, z, p, q
+    int32_t n0;          // fine size
+    double h2;           // fine h^2
+    double h2inv;        // fine 1/h^2
+    double ds_th[9];     // d stencil / d theta (fine, unscaled coefficients)
+    double ds_ep[9];     // d stencil / d eps
+};
+
+// per-instance solver state, written by the finalising block of reductions
+struct InstState {
+    double ssf;        // ||F||^2 (scaled units)
+    double relres;     // last relative residual
+    double relres0;    // first relative residual
+    double scale;      // power-of-two scale of the FP32 right-hand side
+    double rz;         // PCG r.z
+    double pq;         // PCG p.q
+    double alpha, beta;
+    double tol;
+    double dth, deps;  // gradient results
+    int32_t iters;     // completed cycles / iterations
+    int32_t status;    // kc_status of this instance once done
+    int32_t done;      // nonzero: every kernel skips this instance
+    int32_t maxit;
+    int32_t counter;   // blocks arrived at the current reduction (last one finalises)
+    int32_t pad[3];
+};
+
+// reduction kinds finalised by the last block of a kernel
+enum Finalize : int32_t {
+    FIN_NONE = 0,
+    FIN_SSF = 1,        // ssf = sum; relres0 bookkeeping reset
+    FIN_STOP = 2,       // stand-alone stop test on sum = ||F - S v||^2
+    FIN_STOP_IR = 3,    // same, plus the FP32 scale for the next cycle
+    FIN_PQ = 4,         // pq = sum; alpha = rz / pq (breakdown check)
+    FIN_PCG_R = 5,      // PCG residual test on sum = ||r||^2, plus FP32 scale
+    FIN_RZ = 6,         // rz_new = sum; beta = rz_new / rz
+    FIN_GRAD = 7,       // dth, deps = sums
+};
+
+// persistent coarse kernel operations
+enum SubOp : uint32_t {
+    SOP_PRE = 1,      // nu1 sweeps (zero guess flag) + residual + full weighting to depth+1
+    SOP_POST = 2,     // prolong-add from depth+1 + nu2 sweeps
+    SOP_SOLVE = 3,    // coarsest direct solve
+};
+__host__ __device__ inline uint32_t sop_make(uint32_t op, uint32_t depth, uint32_t zg)
+{
+    return op | (depth << 4) | (zg << 12);
+}
+
+// arguments of a grid-wide stage launch
+struct StageArgs {
+    const InstDev* inst;
+    InstState* st;
+    const int32_t* tile_off;  // prefix sums over instances of tiles at this depth (count + 1)
+    double* partial;          // one or two doubles per block
+    double* hist;             // relres history, HIST_CAP per instance
+    int32_t count;
+    int32_t depth;
+    int32_t zg;               // current estimate is zero on entry
+    int32_t fin;              // Finalize kind of this launch's reduction
+    int32_t nu;               // sweeps for fused pre/post kernels
+    int32_t src, dst;         // buffer selectors for unfused kernels (0 = A, 1 = B)
+    int32_t flags;
+};
+
+// arguments of a persistent coarse-kernel launch
+struct SubArgs {
+    const InstDev* inst;
+    InstState* st;
+    const int32_t* list;      // instance ids handled (one workgroup each)
+    int32_t count;
+    int32_t depth;            // depth of the calls
+    int32_t kappa;            // counter of the first call
+    int32_t pair;             // 1: call(kappa) then call(kappa-1) from zero; 0: one call from A
+    int32_t nu1, nu2;
+};
+
+// kernel launchers (kc_kernels.hip)
+enum GridKernel : int32_t {
+    GK_SWEEP = 1,      // unfused: dst = src + w (F - S src)
+    GK_RESID = 2,      // unfused: dst = F - S src
+    GK_RESTRICT = 3,   // unfused: F[d+1] = P^T src
+    GK_ZERO = 4,       // unfused: A[d] = 0
+    GK_PROLONG = 5,    // unfused: dst = P A[d+1]
+    GK_ADD = 6,        // unfused: src += dst
+    GK_COPY = 7,       // unfused: dst = src
+    GK_NORM = 8,       // ||F - S A||^2 with finalize
+    GK_PRE = 9,        // fused pre-smoothing + residual + restriction (optional input norm)
+    GK_POST = 10,      // fused prolong-add + post-smoothing
+    GK_SSF = 11,       // ||F||^2 at level 0
+    GK_IR_RESID = 12,  // r = F - S u (FP64), norm, F32 = scale * r
+    GK_IR_UPDATE = 13, // u += A32 / scale
+    GK_PCG_INIT = 14,  // u = 0, r = F, ||r||^2
+    GK_PCG_PRECIN = 15,// level-0 cycle input from r (FP32 scaled copy or FP64 alias)
+    GK_PCG_RZ = 16,    // z from the cycle (FP32 -> FP64 unscale), r.z, beta, p = z + beta p
+    GK_PCG_AP = 17,    // q = S p, p.q, alpha
+    GK_PCG_UPD = 18,   // u += alpha p, r -= alpha q, ||r||^2
+    GK_APPLY = 19,     // y = S x / h^2
+    GK_GRAD = 20,      // -lam^T dS u / h^2 for theta and eps
+};
+
+hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nblocks, hipStream_t s);
+hipError_t launch_subtree(bool f32, const SubArgs& a, int32_t threads, int32_t lds_bytes, hipStream_t s);
+hipError_t launch_coarsest(bool f32, const SubArgs& a, hipStream_t s);
+int32_t max_lds_bytes();
+
+}  // namespace kc
