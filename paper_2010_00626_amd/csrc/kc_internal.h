@@ -21,8 +21,8 @@ struct LevelDev {
     void* B;
     void* F;
     int32_t n;
-    int32_t ld;
-    double fscale;   // F is multiplied by fscale when loaded (h^2 for a user f, else 1)
+    int32_t lda, ldb, ldf;   // leading dimensions of A, B and F
+    double fscale;           // F is multiplied by fscale when loaded (h^2 for a user f, else 1)
 };
 
 struct InstDev {
@@ -35,10 +35,12 @@ struct InstDev {
     double w64[MAXL];    // omega / s[4]
     float w32[MAXL];
     LevelDev lev[MAXL];  // cycle levels (level 0 may alias user arrays)
-    const double* cinv64;  // coarsest inverse, nc2 x nc2 row-major, h^2-scaled system
-    const float* cinv32;
+    const double* chol64;  // lower Cholesky factor of the coarsest matrix, nc2 x nc2 row-major (scaled system)
+    const float* chol32;
     int32_t lds_off[MAXL]; // persistent kernel: element offset of level d's v in LDS (F follows)
-    int32_t ops_off[MAXL + 2]; // persistent kernel op lists by counter 1..MAXL+1
+    int32_t lds_tmp;       // persistent kernel: element offset of the shared sweep buffer
+    int32_t ops_beg[MAXL + 1]; // persistent kernel op list of a call with counter k = 1..MAXL+1
+    int32_t ops_len[MAXL + 1];
     const uint32_t* ops;       // op list storage
     // FP64 vectors of the drivers (refinement / PCG); fine level, ld = ldv
     double* u;           // user solution
@@ -52,6 +54,9 @@ struct InstDev {
     int32_t n0;          // fine size
     double h2;           // fine h^2
     double h2inv;        // fine 1/h^2
+    const double* x;     // generic FP64 input of apply / gradient (x or lam)
+    double* y;           // generic FP64 output of apply, second input (u) of gradient
+    int32_t ldx, ldy;
     double ds_th[9];     // d stencil / d theta (fine, unscaled coefficients)
     double ds_ep[9];     // d stencil / d eps
 };
@@ -61,7 +66,8 @@ struct InstState {
     double ssf;        // ||F||^2 (scaled units)
     double relres;     // last relative residual
     double relres0;    // first relative residual
-    double scale;      // power-of-two scale of the FP32 right-hand side
+    double scale;      // power-of-two scale for the next FP32 right-hand side
+    double scale_used; // scale applied to the current FP32 right-hand side
     double rz;         // PCG r.z
     double pq;         // PCG p.q
     double alpha, beta;
@@ -72,7 +78,7 @@ struct InstState {
     int32_t done;      // nonzero: every kernel skips this instance
     int32_t maxit;
     int32_t counter;   // blocks arrived at the current reduction (last one finalises)
-    int32_t pad[3];
+    int32_t pad;
 };
 
 // reduction kinds finalised by the last block of a kernel
@@ -85,6 +91,7 @@ enum Finalize : int32_t {
     FIN_PCG_R = 5,      // PCG residual test on sum = ||r||^2, plus FP32 scale
     FIN_RZ = 6,         // rz_new = sum; beta = rz_new / rz
     FIN_GRAD = 7,       // dth, deps = sums
+    FIN_PCG_INIT = 8,   // ssf = ||r_0||^2, first residual test, FP32 scale
 };
 
 // persistent coarse kernel operations
@@ -124,6 +131,9 @@ struct SubArgs {
     int32_t kappa;            // counter of the first call
     int32_t pair;             // 1: call(kappa) then call(kappa-1) from zero; 0: one call from A
     int32_t nu1, nu2;
+    int32_t zg;               // single call: estimate is zero on entry
+    int32_t fin;              // single call: FIN_STOP computes the stop test first
+    double* hist;
 };
 
 // kernel launchers (kc_kernels.hip)
@@ -143,16 +153,19 @@ enum GridKernel : int32_t {
     GK_IR_UPDATE = 13, // u += A32 / scale
     GK_PCG_INIT = 14,  // u = 0, r = F, ||r||^2
     GK_PCG_PRECIN = 15,// level-0 cycle input from r (FP32 scaled copy or FP64 alias)
-    GK_PCG_RZ = 16,    // z from the cycle (FP32 -> FP64 unscale), r.z, beta, p = z + beta p
+    GK_PCG_RZ = 16,    // z from the cycle (FP32 -> FP64 unscale), r.z, beta
+    GK_PCG_P = 21,     // p = z + beta p
     GK_PCG_AP = 17,    // q = S p, p.q, alpha
     GK_PCG_UPD = 18,   // u += alpha p, r -= alpha q, ||r||^2
     GK_APPLY = 19,     // y = S x / h^2
     GK_GRAD = 20,      // -lam^T dS u / h^2 for theta and eps
+    GK_ZERO_SELF = 22, // unfused: A[d] = 0 on the launch's own level
 };
 
 hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nblocks, hipStream_t s);
 hipError_t launch_subtree(bool f32, const SubArgs& a, int32_t threads, int32_t lds_bytes, hipStream_t s);
 hipError_t launch_coarsest(bool f32, const SubArgs& a, hipStream_t s);
+hipError_t prepare_subtree(bool f32, int32_t lds_bytes);
 int32_t max_lds_bytes();
 
 }  // namespace kc

@@ -1,0 +1,1313 @@
+// kc_runtime.cpp -- host runtime of libkcycle.so: hierarchy setup, workspace
+// layout, the flattened kappa-cycle schedule, hipGraph capture and replay, the
+// stand-alone / refinement / PCG drivers and the C-ABI (include/kcycle.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/kcycle.h"
+#include "kc_internal.h"
+
+using namespace kc;
+
+namespace {
+
+thread_local std::string g_err;
+
+kc_status fail(kc_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess) return fail(KC_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+constexpr int OPS_CAP = 4096;          // op words reserved per instance
+constexpr int KMAX = MAXL + 1;         // counters above this all give the W-cycle
+
+size_t align_up(size_t x, size_t a = ALIGN) { return (x + a - 1) / a * a; }
+int ld_of(int n) { return (n + 63) / 64 * 64; }
+bool is_pow2(long x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// ---------------------------------------------------------------------------
+// discrete problem on the host (Section 4): fine stencil, its derivatives,
+// Galerkin coarse stencils and the coarsest inverse
+// ---------------------------------------------------------------------------
+void fine_stencil(double theta, double eps, double s[9])
+{
+    const double C = std::cos(theta), S = std::sin(theta);
+    const double cross = 0.5 * (1.0 - eps) * C * S;
+    const double we = -(C * C + eps * S * S);
+    const double sn = -(eps * C * C + S * S);
+    const double t[9] = {-cross, sn, cross, we, 2.0 * (1.0 + eps), we, cross, sn, -cross};
+    std::memcpy(s, t, sizeof t);
+}
+
+void fine_stencil_derivs(double theta, double eps, double dth[9], double deps[9])
+{
+    const double C = std::cos(theta), S = std::sin(theta);
+    const double xc = 0.5 * (1.0 - eps) * (C * C - S * S), xw = 2.0 * (1.0 - eps) * C * S;
+    const double a[9] = {-xc, -xw, xc, xw, 0.0, xw, xc, -xw, -xc};
+    std::memcpy(dth, a, sizeof a);
+    const double ec = -0.5 * C * S, ew = -S * S, en = -C * C;
+    const double b[9] = {-ec, en, ec, ew, 2.0, ew, ec, en, -ec};
+    std::memcpy(deps, b, sizeof b);
+}
+
+double w1(int a) { return a == 0 ? 1.0 : 0.5; }
+
+// Galerkin coarse stencil, A_c = R A P with R = P^T / 4 (bilinear P): with
+// h_c = 2h the h^2-scaled stencil is S_c = 4 R S P.  It is read off by applying
+// P, then S, then R to a coarse unit vector on a 5 x 5 coarse grid (11 x 11
+// fine), far enough from the boundary that nothing is cut off.  Every sum runs
+// south to north, west to east, so each entry is rounded exactly as the
+// level operators of the definition round it.
+void galerkin(const double sf[9], double sc[9])
+{
+    constexpr int NC = 5, NF = 11;
+    double e[NF * NF], ae[NF * NF];
+    auto ec = [](int J, int I) { return (J == 2 && I == 2) ? 1.0 : 0.0; };
+    for (int j = 0; j < NF; ++j)          // e = P e_c (gather)
+        for (int i = 0; i < NF; ++i) {
+            double acc = 0.0;
+            for (int J = (j - 1) / 2 - 1; J <= j / 2; ++J) {
+                const int dy = j - (2 * J + 1);
+                if (dy < -1 || dy > 1) continue;
+                for (int I = (i - 1) / 2 - 1; I <= i / 2; ++I) {
+                    const int dx = i - (2 * I + 1);
+                    if (dx < -1 || dx > 1) continue;
+                    const double v = (J < 0 || J >= NC || I < 0 || I >= NC) ? 0.0 : ec(J, I);
+                    acc += (w1(dx) * w1(dy)) * v;
+                }
+            }
+            e[j * NF + i] = acc;
+        }
+    for (int j = 0; j < NF; ++j)          // ae = S e
+        for (int i = 0; i < NF; ++i) {
+            double acc = 0.0;
+            for (int b = -1; b <= 1; ++b)
+                for (int a = -1; a <= 1; ++a) {
+                    const int jj = j + b, ii = i + a;
+                    const double x = (jj < 0 || jj >= NF || ii < 0 || ii >= NF) ? 0.0 : e[jj * NF + ii];
+                    acc += sf[3 * (b + 1) + (a + 1)] * x;
+                }
+            ae[j * NF + i] = acc * 1.0;
+        }
+    for (int b0 = -1; b0 <= 1; ++b0)      // S_c = 4 R ae around coarse (2, 2)
+        for (int a0 = -1; a0 <= 1; ++a0) {
+            const int J = 2 + b0, I = 2 + a0;
+            double acc = 0.0;
+            for (int b = -1; b <= 1; ++b)
+                for (int a = -1; a <= 1; ++a)
+                    acc += (w1(a) * w1(b) / 4.0) * ae[(2 * J + 1 + b) * NF + (2 * I + 1 + a)];
+            sc[3 * (b0 + 1) + (a0 + 1)] = 4.0 * acc;
+        }
+}
+
+// lower Cholesky factor (row-major) of the coarsest matrix of stencil s on an
+// nc x nc grid, in the arithmetic type R; the h^2 scaling of the system is a
+// power of four, so this factor is the unscaled one times a power of two
+template <typename R>
+bool coarse_cholesky(int nc, const double s64[9], std::vector<R>& Lc)
+{
+    const int m = nc * nc;
+    Lc.assign((size_t)m * m, R(0));
+    std::vector<R>& A = Lc;
+    for (int j = 0; j < nc; ++j)
+        for (int i = 0; i < nc; ++i)
+            for (int b = -1; b <= 1; ++b)
+                for (int a = -1; a <= 1; ++a) {
+                    const int jj = j + b, ii = i + a;
+                    if (jj < 0 || jj >= nc || ii < 0 || ii >= nc) continue;
+                    A[(size_t)(j * nc + i) * m + (jj * nc + ii)] = (R)s64[3 * (b + 1) + (a + 1)];
+                }
+    for (int p = 0; p < m; ++p) {
+        for (int q = 0; q <= p; ++q) {
+            R acc = A[(size_t)p * m + q];
+            for (int k = 0; k < q; ++k) acc -= A[(size_t)p * m + k] * A[(size_t)q * m + k];
+            if (p == q) {
+                if (!(acc > R(0))) return false;
+                A[(size_t)p * m + p] = (R)std::sqrt((double)acc);
+            } else {
+                A[(size_t)p * m + q] = acc / A[(size_t)q * m + q];
+            }
+        }
+        for (int q = p + 1; q < m; ++q) A[(size_t)p * m + q] = R(0);
+    }
+    return true;
+}
+
+kc_status check_problem(const kc_problem& p, int& L)
+{
+    if (p.n < 1 || p.n_coarsest < 1 || p.n_coarsest > p.n || !is_pow2((long)p.n + 1) ||
+        !is_pow2((long)p.n_coarsest + 1) || p.n_coarsest > 7)
+        return fail(KC_ERR_ARG, "n and n_coarsest must be 2^k - 1 with n_coarsest in {1, 3, 7} and <= n");
+    if (!(p.eps > 0.0) || !std::isfinite(p.eps) || !std::isfinite(p.theta))
+        return fail(KC_ERR_ARG, "eps must be positive and theta finite");
+    L = 1;
+    while (((p.n + 1) >> (L - 1)) > p.n_coarsest + 1) ++L;
+    if (L > MAXL) return fail(KC_ERR_ARG, "too many levels");
+    return KC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout (independent of execution options)
+// ---------------------------------------------------------------------------
+struct InstLayout {
+    int L = 0;
+    int n[MAXL] = {}, ld[MAXL] = {};
+    size_t A[MAXL] = {}, B[MAXL] = {}, F[MAXL] = {};   // cycle arrays by level (A, F of level 0 unused in F64)
+    size_t chol64 = 0, chol32 = 0, ops = 0;
+    size_t r = 0, z = 0, p = 0, q = 0;
+};
+
+struct Layout {
+    size_t inst = 0, state = 0, tiles = 0, lists = 0, partial = 0, hist = 0;
+    size_t total = 0;
+    int ntables = 0;       // (1 + 2 MAXL) tile tables of (count + 1)
+    int total_tiles0 = 0;
+    std::vector<InstLayout> il;
+};
+
+int tiles_of(int n) { return ((n + TX - 1) / TX) * ((n + TY - 1) / TY); }
+
+kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Layout& lay)
+{
+    if (!probs || count < 1) return fail(KC_ERR_ARG, "need at least one problem");
+    if (prec != KC_F64 && prec != KC_F32_CYCLE) return fail(KC_ERR_ARG, "unknown precision");
+    const size_t T = (prec == KC_F64) ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    lay.il.assign(count, InstLayout());
+    lay.inst = take(sizeof(InstDev) * count);
+    lay.state = take(sizeof(InstState) * count);
+    lay.ntables = 1 + 2 * MAXL;
+    lay.tiles = take(sizeof(int32_t) * (size_t)lay.ntables * (count + 1));
+    lay.lists = take(sizeof(int32_t) * (size_t)2 * MAXL * count);
+    int tiles0 = 0;
+    for (int i = 0; i < count; ++i) {
+        int L;
+        kc_status st = check_problem(probs[i], L);
+        if (st != KC_OK) return st;
+        tiles0 += tiles_of(probs[i].n);
+    }
+    lay.total_tiles0 = tiles0;
+    lay.partial = take(sizeof(double) * 2 * (size_t)tiles0);
+    lay.hist = take(sizeof(double) * (size_t)HIST_CAP * count);
+    for (int i = 0; i < count; ++i) {
+        InstLayout& il = lay.il[i];
+        check_problem(probs[i], il.L);
+        for (int d = 0; d < il.L; ++d) {
+            il.n[d] = ((probs[i].n + 1) >> d) - 1;
+            il.ld[d] = ld_of(il.n[d]);
+            const size_t bytes = (size_t)il.n[d] * il.ld[d] * T;
+            il.B[d] = take(bytes);
+            if (d > 0 || prec == KC_F32_CYCLE) {
+                il.A[d] = take(bytes);
+                il.F[d] = take(bytes);
+            }
+        }
+        const int m = probs[i].n_coarsest * probs[i].n_coarsest;
+        il.chol64 = take(sizeof(double) * m * m);
+        il.chol32 = take(sizeof(float) * m * m);
+        il.ops = take(sizeof(uint32_t) * OPS_CAP);
+        const size_t v64 = (size_t)il.n[0] * il.ld[0] * 8;
+        il.r = take(v64);
+        il.z = take(v64);
+        il.p = take(v64);
+        il.q = take(v64);
+    }
+    lay.total = off;
+    return KC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// schedule
+// ---------------------------------------------------------------------------
+enum LaunchType { L_GRID, L_SUB, L_COARSEST };
+
+struct Launch {
+    LaunchType type;
+    GridKernel gk;
+    bool f32;
+    StageArgs sa;
+    int nblocks;
+    SubArgs ba;
+    int threads;
+    int lds;
+};
+
+struct HostInst {
+    kc_problem p;
+    InstLayout il;
+    int cut = 0;
+    double s[MAXL][9];
+    std::vector<uint32_t> ops;
+    int ops_beg[KMAX] = {}, ops_len[KMAX] = {};
+    int lds_off[MAXL] = {}, lds_tmp = 0, lds_elems = 0;
+};
+
+// op list of one call at depth d with counter k (Algorithm 3), levels in LDS
+void gen_sub_call(const HostInst& h, int d, int k, bool zg, std::vector<uint32_t>& out)
+{
+    if (d == h.il.L - 1) {
+        out.push_back(sop_make(SOP_SOLVE, d, 0));
+        return;
+    }
+    out.push_back(sop_make(SOP_PRE, d, zg ? 1 : 0));
+    gen_sub_call(h, d + 1, k, true, out);
+    if (k > 1) gen_sub_call(h, d + 1, k - 1, false, out);
+    out.push_back(sop_make(SOP_POST, d, 0));
+}
+
+}  // namespace
+
+struct kc_hier {
+    int count = 0;
+    kc_precision prec = KC_F64;
+    kc_exec ex{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t user_stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, t0 = nullptr, t1 = nullptr;
+    hipEvent_t ev_upload = nullptr;   // last copy out of the pinned mirrors
+    bool upload_pending = false;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout lay;
+    std::vector<HostInst> hi;
+    InstDev* h_inst = nullptr;   // pinned mirrors
+    InstState* h_st = nullptr;
+    InstDev* d_inst = nullptr;
+    InstState* d_st = nullptr;
+    int32_t* d_tiles = nullptr;
+    int32_t* d_lists = nullptr;
+    double* d_partial = nullptr;
+    double* d_hist = nullptr;
+    std::vector<std::vector<int32_t>> tiles;   // host copies of the tile tables
+    std::vector<std::vector<int32_t>> lists;   // host copies of the instance lists
+    int max_cut = 0, max_L = 0;
+    int sub_lds = 0;
+    std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> graphs;
+    double omega_set = -1.0;
+    // stats
+    int64_t last_grid = 0, last_sub = 0, last_sub_stages = 0, last_cycles = 0, last_launched = 0;
+    double last_ms = 0.0;
+    std::string last_driver;
+};
+
+namespace {
+
+// tile table indices
+int tt_all0() { return 0; }
+int tt_cut(int d) { return 1 + d; }          // instances with cut > d
+int tt_lvl(int d) { return 1 + MAXL + d; }   // instances with L - 1 > d
+int lt_sub(int d) { return d; }              // instances with cut == d
+int lt_coarse(int d) { return MAXL + d; }    // instances with L - 1 == d
+
+const int32_t* dev_tiles(kc_hier* h, int t) { return h->d_tiles + (size_t)t * (h->count + 1); }
+const int32_t* dev_list(kc_hier* h, int t) { return h->d_lists + (size_t)t * h->count; }
+int ntiles(kc_hier* h, int t) { return h->tiles[t][h->count]; }
+int nlist(kc_hier* h, int t) { return (int)h->lists[t].size(); }
+
+StageArgs base_args(kc_hier* h, int table)
+{
+    StageArgs a{};
+    a.inst = h->d_inst;
+    a.st = h->d_st;
+    a.tile_off = dev_tiles(h, table);
+    a.partial = h->d_partial;
+    a.hist = h->d_hist;
+    a.count = h->count;
+    return a;
+}
+
+Launch grid(kc_hier* h, GridKernel gk, bool f32, int table, int depth)
+{
+    Launch L{};
+    L.type = L_GRID;
+    L.gk = gk;
+    L.f32 = f32;
+    L.sa = base_args(h, table);
+    L.sa.depth = depth;
+    L.nblocks = ntiles(h, table);
+    return L;
+}
+
+Launch sub(kc_hier* h, bool f32, int depth, int kappa, bool pair, int nu1, int nu2, bool zg, int fin)
+{
+    Launch L{};
+    L.type = L_SUB;
+    L.f32 = f32;
+    L.ba.inst = h->d_inst;
+    L.ba.st = h->d_st;
+    L.ba.list = dev_list(h, lt_sub(depth));
+    L.ba.count = nlist(h, lt_sub(depth));
+    L.ba.depth = depth;
+    L.ba.kappa = kappa;
+    L.ba.pair = pair ? 1 : 0;
+    L.ba.nu1 = nu1;
+    L.ba.nu2 = nu2;
+    L.ba.zg = zg ? 1 : 0;
+    L.ba.fin = fin;
+    L.ba.hist = h->d_hist;
+    L.threads = h->ex.coarse_threads;
+    L.lds = h->sub_lds;
+    return L;
+}
+
+// fused schedule of one cycle: grid-wide PRE/POST above each instance's cut,
+// one persistent launch per parent node for the pair of calls at the cut
+void gen_fused(kc_hier* h, int d, int k, bool zg, int fin, const kc_cycle_params& c, bool f32,
+               std::vector<Launch>& out)
+{
+    Launch pre = grid(h, GK_PRE, f32, tt_cut(d), d);
+    pre.sa.zg = zg ? 1 : 0;
+    pre.sa.fin = fin;
+    pre.sa.nu = c.nu1;
+    out.push_back(pre);
+    if (nlist(h, lt_sub(d + 1)) > 0) out.push_back(sub(h, f32, d + 1, k, true, c.nu1, c.nu2, false, FIN_NONE));
+    if (d + 1 < h->max_cut) {
+        gen_fused(h, d + 1, k, true, FIN_NONE, c, f32, out);
+        if (k > 1) gen_fused(h, d + 1, k - 1, false, FIN_NONE, c, f32, out);
+    }
+    Launch post = grid(h, GK_POST, f32, tt_cut(d), d);
+    post.sa.nu = c.nu2;
+    out.push_back(post);
+}
+
+void cycle_fused(kc_hier* h, const kc_cycle_params& c, int kappa, bool zg, int fin, bool f32, std::vector<Launch>& out)
+{
+    if (nlist(h, lt_sub(0)) > 0) out.push_back(sub(h, f32, 0, kappa, false, c.nu1, c.nu2, zg, fin));
+    if (h->max_cut > 0) gen_fused(h, 0, kappa, zg, fin, c, f32, out);
+}
+
+// Algorithm 4: one launch per operation; cur[d] tracks which buffer holds v_d
+void gen_paper(kc_hier* h, int d, int k, const kc_cycle_params& c, bool f32, int cur[], std::vector<Launch>& out)
+{
+    if (nlist(h, lt_coarse(d)) > 0) {
+        Launch L{};
+        L.type = L_COARSEST;
+        L.f32 = f32;
+        L.ba.inst = h->d_inst;
+        L.ba.st = h->d_st;
+        L.ba.list = dev_list(h, lt_coarse(d));
+        L.ba.count = nlist(h, lt_coarse(d));
+        L.ba.depth = d;
+        out.push_back(L);
+        cur[d] = 0;
+    }
+    if (ntiles(h, tt_lvl(d)) == 0) return;
+    auto op = [&](GridKernel gk, int src, int dst) {
+        Launch L = grid(h, gk, f32, tt_lvl(d), d);
+        L.sa.src = src;
+        L.sa.dst = dst;
+        out.push_back(L);
+    };
+    for (int s = 0; s < c.nu1; ++s) { op(GK_SWEEP, cur[d], cur[d] ^ 1); cur[d] ^= 1; }
+    op(GK_RESID, cur[d], cur[d] ^ 1);
+    op(GK_RESTRICT, cur[d] ^ 1, 0);
+    op(GK_ZERO, 0, 0);
+    cur[d + 1] = 0;
+    gen_paper(h, d + 1, k, c, f32, cur, out);
+    if (k > 1) gen_paper(h, d + 1, k - 1, c, f32, cur, out);
+    {
+        Launch L = grid(h, GK_PROLONG, f32, tt_lvl(d), d);
+        L.sa.src = cur[d + 1];
+        L.sa.dst = cur[d] ^ 1;
+        out.push_back(L);
+    }
+    op(GK_ADD, cur[d], cur[d] ^ 1);
+    for (int s = 0; s < c.nu2; ++s) { op(GK_SWEEP, cur[d], cur[d] ^ 1); cur[d] ^= 1; }
+}
+
+void cycle_paper(kc_hier* h, const kc_cycle_params& c, int kappa, bool zg, bool f32, std::vector<Launch>& out)
+{
+    int cur[MAXL + 1] = {};
+    if (zg) out.push_back(grid(h, GK_ZERO_SELF, f32, tt_all0(), 0));   // v_1 <- 0 for a zero-guess call
+    gen_paper(h, 0, kappa, c, f32, cur, out);
+    if (cur[0] != 0) {
+        Launch L = grid(h, GK_COPY, f32, tt_lvl(0), 0);
+        L.sa.src = cur[0];
+        L.sa.dst = 0;
+        out.push_back(L);
+    }
+}
+
+int clamp_kappa(kc_hier* h, int kappa) { return std::min(kappa, h->max_L + 1); }
+
+hipError_t run(kc_hier* h, const std::vector<Launch>& ls)
+{
+    for (const Launch& L : ls) {
+        hipError_t e = hipSuccess;
+        if (L.type == L_GRID) e = launch_grid(L.gk, L.f32, L.sa, L.nblocks, h->stream);
+        else if (L.type == L_SUB) e = launch_subtree(L.f32, L.ba, L.threads, L.lds, h->stream);
+        else e = launch_coarsest(L.f32, L.ba, h->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void count_launches(const std::vector<Launch>& ls, int64_t& grid_n, int64_t& sub_n)
+{
+    grid_n = sub_n = 0;
+    for (const Launch& L : ls) {
+        if (L.type == L_SUB) { if (L.ba.count > 0) ++sub_n; }
+        else if (L.type == L_COARSEST) { if (L.ba.count > 0) ++grid_n; }
+        else if (L.nblocks > 0) ++grid_n;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// execution plan (depends on the exec options): cut depths, op lists, LDS
+// ---------------------------------------------------------------------------
+kc_status plan_exec(kc_hier* h)
+{
+    const size_t T = (h->prec == KC_F64) ? 8 : 4;
+    const int cutover = h->ex.coarse_cutover;
+    h->max_cut = 0;
+    h->max_L = 0;
+    h->sub_lds = 0;
+    for (int i = 0; i < h->count; ++i) {
+        HostInst& hi = h->hi[i];
+        const int L = hi.il.L;
+        int cut = L - 1;
+        for (int d = 0; d < L; ++d)
+            if (hi.il.n[d] <= cutover) { cut = d; break; }
+        if (h->ex.mode == 1) cut = L;   // paper-structured mode never uses the persistent kernel
+        hi.cut = cut;
+        h->max_cut = std::max(h->max_cut, std::min(cut, L));
+        h->max_L = std::max(h->max_L, L);
+        hi.ops.clear();
+        for (int k = 1; k <= KMAX; ++k) {
+            hi.ops_beg[k - 1] = (int)hi.ops.size();
+            if (cut < L) {
+                const int below = L - cut;
+                if (k <= below + 1 || k == 1) gen_sub_call(hi, cut, k, false, hi.ops);
+                else {   // same as the W-cycle list
+                    hi.ops_beg[k - 1] = hi.ops_beg[below];
+                    hi.ops_len[k - 1] = hi.ops_len[below];
+                    continue;
+                }
+            }
+            hi.ops_len[k - 1] = (int)hi.ops.size() - hi.ops_beg[k - 1];
+        }
+        if ((int)hi.ops.size() > OPS_CAP) return fail(KC_ERR_ARG, "coarse cutover too large for the op buffer");
+        int off = 0;
+        for (int d = 0; d < MAXL; ++d) hi.lds_off[d] = 0;
+        if (cut < L) {
+            for (int d = cut; d < L; ++d) {
+                hi.lds_off[d] = off;
+                off += 2 * hi.il.n[d] * hi.il.n[d];
+            }
+            hi.lds_tmp = off;
+            off += hi.il.n[cut] * hi.il.n[cut];
+        }
+        hi.lds_elems = off;
+        h->sub_lds = std::max(h->sub_lds, (int)(off * T));
+    }
+    if (h->sub_lds > 0 && h->d_tiles) {
+        const int maxl = max_lds_bytes();
+        if (h->sub_lds > maxl)
+            return fail(KC_ERR_ARG, "coarse cutover needs " + std::to_string(h->sub_lds) + " B of LDS, device allows " +
+                                        std::to_string(maxl));
+    }
+    // tables
+    const int cnt = h->count;
+    h->tiles.assign(1 + 2 * MAXL, std::vector<int32_t>(cnt + 1, 0));
+    h->lists.assign(2 * MAXL, std::vector<int32_t>());
+    for (int i = 0; i < cnt; ++i) {
+        const HostInst& hi = h->hi[i];
+        const int L = hi.il.L;
+        h->tiles[tt_all0()][i + 1] = tiles_of(hi.il.n[0]);
+        for (int d = 0; d < MAXL; ++d) {
+            h->tiles[tt_cut(d)][i + 1] = (d < L && hi.cut > d) ? tiles_of(hi.il.n[d]) : 0;
+            h->tiles[tt_lvl(d)][i + 1] = (d < L - 1) ? tiles_of(hi.il.n[d]) : 0;
+            if (hi.cut == d && d < L) h->lists[lt_sub(d)].push_back(i);
+            if (L - 1 == d) h->lists[lt_coarse(d)].push_back(i);
+        }
+    }
+    for (auto& t : h->tiles)
+        for (int i = 0; i < cnt; ++i) t[i + 1] += t[i];
+    std::vector<int32_t> flat((size_t)(1 + 2 * MAXL) * (cnt + 1));
+    for (size_t t = 0; t < h->tiles.size(); ++t) std::copy(h->tiles[t].begin(), h->tiles[t].end(), flat.begin() + t * (cnt + 1));
+    std::vector<int32_t> lflat((size_t)2 * MAXL * cnt, 0);
+    for (size_t t = 0; t < h->lists.size(); ++t) std::copy(h->lists[t].begin(), h->lists[t].end(), lflat.begin() + t * cnt);
+    if (h->d_tiles) {
+        HIPCHK(hipMemcpyAsync(h->d_tiles, flat.data(), flat.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d_lists, lflat.data(), lflat.size() * 4, hipMemcpyHostToDevice, h->stream));
+        for (int i = 0; i < cnt; ++i) {
+            const HostInst& hi = h->hi[i];
+            HIPCHK(hipMemcpyAsync(h->ws + hi.il.ops, hi.ops.data(), hi.ops.size() * 4, hipMemcpyHostToDevice, h->stream));
+        }
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (h->sub_lds > 65536) {
+            HIPCHK(prepare_subtree(h->prec == KC_F32_CYCLE, h->sub_lds));
+        }
+    }
+    return KC_OK;
+}
+
+void fill_inst_static(kc_hier* h)
+{
+    const bool f64 = h->prec == KC_F64;
+    for (int i = 0; i < h->count; ++i) {
+        const HostInst& hi = h->hi[i];
+        InstDev& I = h->h_inst[i];
+        I.L = hi.il.L;
+        I.cut = hi.cut;
+        I.nc2 = hi.p.n_coarsest * hi.p.n_coarsest;
+        I.sub_lds = hi.lds_elems;
+        for (int d = 0; d < hi.il.L; ++d) {
+            for (int q = 0; q < 9; ++q) {
+                I.s64[d][q] = hi.s[d][q];
+                I.s32[d][q] = (float)hi.s[d][q];
+            }
+            LevelDev& Lv = I.lev[d];
+            Lv.n = hi.il.n[d];
+            Lv.lda = Lv.ldb = Lv.ldf = hi.il.ld[d];
+            const bool own = d > 0 || !f64;   // FP64 level 0 binds the caller's arrays per call
+            Lv.A = own ? (void*)(h->ws + hi.il.A[d]) : nullptr;
+            Lv.B = h->ws + hi.il.B[d];
+            Lv.F = own ? (void*)(h->ws + hi.il.F[d]) : nullptr;
+            Lv.fscale = 1.0;
+            I.lds_off[d] = hi.lds_off[d];
+        }
+        I.lds_tmp = hi.lds_tmp;
+        for (int k = 0; k < KMAX; ++k) {
+            I.ops_beg[k] = hi.ops_beg[k];
+            I.ops_len[k] = hi.ops_len[k];
+        }
+        I.ops = (const uint32_t*)(h->ws + hi.il.ops);
+        I.chol64 = (const double*)(h->ws + hi.il.chol64);
+        I.chol32 = (const float*)(h->ws + hi.il.chol32);
+        I.r = (double*)(h->ws + hi.il.r);
+        I.z = (double*)(h->ws + hi.il.z);
+        I.p = (double*)(h->ws + hi.il.p);
+        I.q = (double*)(h->ws + hi.il.q);
+        I.ldv = hi.il.ld[0];
+        I.n0 = hi.il.n[0];
+        const double hh = 1.0 / (double)(hi.il.n[0] + 1);
+        I.h2 = hh * hh;
+        I.h2inv = (double)(hi.il.n[0] + 1) * (double)(hi.il.n[0] + 1);
+        fine_stencil_derivs(hi.p.theta, hi.p.eps, I.ds_th, I.ds_ep);
+    }
+}
+
+void set_omega(kc_hier* h, double omega)
+{
+    for (int i = 0; i < h->count; ++i) {
+        InstDev& I = h->h_inst[i];
+        for (int d = 0; d < I.L; ++d) {
+            I.w64[d] = omega / I.s64[d][4];
+            I.w32[d] = (float)I.w64[d];
+        }
+    }
+}
+
+kc_status upload_inst(kc_hier* h)
+{
+    HIPCHK(hipMemcpyAsync(h->d_inst, h->h_inst, sizeof(InstDev) * h->count, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipEventRecord(h->ev_upload, h->stream));
+    h->upload_pending = true;
+    return KC_OK;
+}
+
+kc_status upload_state(kc_hier* h, double tol, int maxit)
+{
+    for (int i = 0; i < h->count; ++i) {
+        InstState& s = h->h_st[i];
+        std::memset(&s, 0, sizeof s);
+        s.tol = tol;
+        s.maxit = maxit;
+        s.scale = 1.0;
+        s.scale_used = 1.0;
+    }
+    HIPCHK(hipMemcpyAsync(h->d_st, h->h_st, sizeof(InstState) * h->count, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipEventRecord(h->ev_upload, h->stream));
+    h->upload_pending = true;
+    return KC_OK;
+}
+
+kc_status check_cycle(const kc_cycle_params* c)
+{
+    if (!c) return fail(KC_ERR_ARG, "null cycle parameters");
+    if (c->kappa < 1) return fail(KC_ERR_ARG, "kappa must be >= 1");
+    if (c->nu1 < 0 || c->nu2 < 0 || c->nu1 > 3 || c->nu2 > 3) return fail(KC_ERR_ARG, "nu1, nu2 must be in 0..3");
+    if (!(c->omega > 0.0) || !std::isfinite(c->omega)) return fail(KC_ERR_ARG, "omega must be positive");
+    return KC_OK;
+}
+
+enum Driver { DRV_CYCLE = 0, DRV_SOLVE64 = 1, DRV_IR = 2, DRV_PCG = 3 };
+
+// launches of one iteration of a driver
+void iteration(kc_hier* h, int drv, const kc_cycle_params& c, std::vector<Launch>& out)
+{
+    const bool f32 = h->prec == KC_F32_CYCLE;
+    const int kappa = clamp_kappa(h, c.kappa);
+    const bool paper = h->ex.mode == 1;
+    switch (drv) {
+    case DRV_CYCLE:
+        if (paper) cycle_paper(h, c, kappa, false, false, out);
+        else cycle_fused(h, c, kappa, false, FIN_NONE, false, out);
+        break;
+    case DRV_SOLVE64:
+        if (paper) {
+            Launch n = grid(h, GK_NORM, false, tt_all0(), 0);
+            n.sa.fin = FIN_STOP;
+            out.push_back(n);
+            cycle_paper(h, c, kappa, false, false, out);
+        } else {
+            cycle_fused(h, c, kappa, false, FIN_STOP, false, out);
+        }
+        break;
+    case DRV_IR: {
+        Launch r = grid(h, GK_IR_RESID, true, tt_all0(), 0);
+        r.sa.fin = FIN_STOP_IR;
+        out.push_back(r);
+        if (paper) cycle_paper(h, c, kappa, true, true, out);
+        else cycle_fused(h, c, kappa, true, FIN_NONE, true, out);
+        out.push_back(grid(h, GK_IR_UPDATE, true, tt_all0(), 0));
+        break;
+    }
+    case DRV_PCG: {
+        if (f32) out.push_back(grid(h, GK_PCG_PRECIN, true, tt_all0(), 0));
+        if (paper) cycle_paper(h, c, kappa, true, f32, out);
+        else cycle_fused(h, c, kappa, true, FIN_NONE, f32, out);
+        Launch rz = grid(h, GK_PCG_RZ, f32, tt_all0(), 0);
+        rz.sa.fin = FIN_RZ;
+        out.push_back(rz);
+        out.push_back(grid(h, GK_PCG_P, f32, tt_all0(), 0));
+        Launch ap = grid(h, GK_PCG_AP, f32, tt_all0(), 0);
+        ap.sa.fin = FIN_PQ;
+        out.push_back(ap);
+        Launch up = grid(h, GK_PCG_UPD, f32, tt_all0(), 0);
+        up.sa.fin = FIN_PCG_R;
+        out.push_back(up);
+        break;
+    }
+    }
+}
+
+kc_status launch_iteration(kc_hier* h, int drv, const kc_cycle_params& c, int times)
+{
+    std::vector<Launch> ls;
+    iteration(h, drv, c, ls);
+    if (!h->ex.use_graph) {
+        for (int t = 0; t < times; ++t) HIPCHK(run(h, ls));
+        return KC_OK;
+    }
+    auto key = std::make_tuple(drv, clamp_kappa(h, c.kappa), c.nu1, c.nu2, 0.0);
+    auto it = h->graphs.find(key);
+    if (it == h->graphs.end()) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = run(h, ls);
+        hipError_t e2 = hipStreamEndCapture(h->stream, &g);
+        if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); return fail(KC_ERR_HIP, std::string("capture: ") + hipGetErrorString(e)); }
+        HIPCHK(e2);
+        hipGraphExec_t ge = nullptr;
+        HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        it = h->graphs.emplace(key, ge).first;
+    }
+    for (int t = 0; t < times; ++t) HIPCHK(hipGraphLaunch(it->second, h->stream));
+    return KC_OK;
+}
+
+void drop_graphs(kc_hier* h)
+{
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+}
+
+kc_status enter(kc_hier* h)
+{
+    // the pinned mirrors are rewritten by this call: the previous upload must be done
+    if (h->upload_pending) {
+        HIPCHK(hipEventSynchronize(h->ev_upload));
+        h->upload_pending = false;
+    }
+    if (h->own_stream) {
+        HIPCHK(hipEventRecord(h->ev_in, h->user_stream));
+        HIPCHK(hipStreamWaitEvent(h->stream, h->ev_in, 0));
+    }
+    return KC_OK;
+}
+
+kc_status leave(kc_hier* h)
+{
+    if (h->own_stream) {
+        HIPCHK(hipEventRecord(h->ev_out, h->stream));
+        HIPCHK(hipStreamWaitEvent(h->user_stream, h->ev_out, 0));
+    }
+    return KC_OK;
+}
+
+// poll-driven loop: launch iterations until every instance reports done
+kc_status drive(kc_hier* h, int drv, const kc_cycle_params& c, int maxit, int32_t* iters, double* relres,
+                int32_t* status)
+{
+    HIPCHK(hipEventRecord(h->t0, h->stream));
+    int launched = 0;
+    int batch = h->ex.poll_every > 0 ? h->ex.poll_every : 2;
+    std::vector<double> prev_rel(h->count, -1.0);
+    std::vector<int> prev_it(h->count, 0);
+    const int limit = maxit + 2;
+    for (;;) {
+        const int n = std::min(batch, limit - launched);
+        if (n <= 0) break;
+        kc_status s = launch_iteration(h, drv, c, n);
+        if (s != KC_OK) return s;
+        launched += n;
+        HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, sizeof(InstState) * h->count, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        bool all = true;
+        double need = 1.0;
+        for (int i = 0; i < h->count; ++i) {
+            const InstState& s2 = h->h_st[i];
+            if (s2.done) continue;
+            all = false;
+            // remaining cycles predicted from the observed reduction rate
+            if (prev_rel[i] > 0.0 && s2.relres > 0.0 && s2.iters > prev_it[i]) {
+                const double rate = std::pow(s2.relres / prev_rel[i], 1.0 / (s2.iters - prev_it[i]));
+                if (rate > 0.0 && rate < 1.0) {
+                    const double rem = std::log(s2.tol / s2.relres) / std::log(rate);
+                    need = std::max(need, rem);
+                } else {
+                    need = std::max(need, 4.0);
+                }
+            } else {
+                need = std::max(need, 2.0);
+            }
+            prev_rel[i] = s2.relres;
+            prev_it[i] = s2.iters;
+        }
+        if (all) break;
+        if (h->ex.poll_every <= 0) batch = std::max(1, std::min(256, (int)std::ceil(need * 0.9)));
+    }
+    HIPCHK(hipEventRecord(h->t1, h->stream));
+    HIPCHK(hipEventSynchronize(h->t1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->t0, h->t1));
+    h->last_ms = ms;
+    h->last_launched = launched;
+    kc_status worst = KC_OK;
+    int64_t maxits = 0;
+    for (int i = 0; i < h->count; ++i) {
+        const InstState& s2 = h->h_st[i];
+        kc_status si = s2.done ? (kc_status)s2.status : KC_NOT_CONVERGED;
+        if (iters) iters[i] = s2.iters;
+        if (relres) relres[i] = s2.relres;
+        if (status) status[i] = si;
+        maxits = std::max<int64_t>(maxits, s2.iters);
+        if (si < 0) worst = (worst < 0) ? std::min(worst, si) : si;
+        else if (worst >= 0 && si > worst) worst = si;
+    }
+    h->last_cycles = maxits;
+    return worst;
+}
+
+kc_status prepare_call(kc_hier* h, const kc_cycle_params* c)
+{
+    kc_status s = check_cycle(c);
+    if (s != KC_OK) return s;
+    if (c->omega != h->omega_set) {
+        set_omega(h, c->omega);
+        h->omega_set = c->omega;
+    }
+    return KC_OK;
+}
+
+template <typename PtrT>
+kc_status check_ptrs(kc_hier* h, PtrT const* p, const int64_t* ld, const char* what)
+{
+    if (!p || !ld) return fail(KC_ERR_ARG, std::string("null ") + what);
+    for (int i = 0; i < h->count; ++i) {
+        if (!p[i]) return fail(KC_ERR_ARG, std::string("null device pointer in ") + what);
+        if (ld[i] < h->hi[i].il.n[0] || ld[i] > INT32_MAX) return fail(KC_ERR_ARG, std::string("bad leading dimension of ") + what);
+    }
+    return KC_OK;
+}
+
+void record_counts(kc_hier* h, int drv, const kc_cycle_params& c)
+{
+    std::vector<Launch> ls;
+    iteration(h, drv, c, ls);
+    count_launches(ls, h->last_grid, h->last_sub);
+    int64_t st = 0;
+    for (const Launch& L : ls)
+        if (L.type == L_SUB)
+            for (int idx : h->lists[lt_sub(L.ba.depth)]) {
+                const HostInst& hi = h->hi[idx];
+                const int kk = std::min(L.ba.kappa, KMAX);
+                st += hi.ops_len[kk - 1];
+                if (L.ba.pair && L.ba.kappa > 1) st += hi.ops_len[std::min(L.ba.kappa - 1, KMAX) - 1];
+                break;
+            }
+    h->last_sub_stages = st;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+void kc_exec_default(kc_exec* e)
+{
+    if (!e) return;
+    std::memset(e, 0, sizeof *e);
+    e->mode = 0;
+    e->use_graph = 1;
+    e->coarse_cutover = 63;
+    e->coarse_threads = 512;
+    e->poll_every = 0;
+}
+
+const char* kc_status_string(kc_status s)
+{
+    switch (s) {
+    case KC_OK: return "KC_OK";
+    case KC_NOT_CONVERGED: return "KC_NOT_CONVERGED";
+    case KC_DIVERGED: return "KC_DIVERGED";
+    case KC_BREAKDOWN: return "KC_BREAKDOWN";
+    case KC_ERR_ARG: return "KC_ERR_ARG";
+    case KC_ERR_HIP: return "KC_ERR_HIP";
+    case KC_ERR_WORKSPACE: return "KC_ERR_WORKSPACE";
+    case KC_ERR_NONFINITE: return "KC_ERR_NONFINITE";
+    case KC_ERR_STATE: return "KC_ERR_STATE";
+    }
+    return "KC_UNKNOWN";
+}
+
+const char* kc_last_error(void) { return g_err.c_str(); }
+
+kc_status kc_workspace_bytes(const kc_problem* probs, int32_t count, kc_precision prec, size_t* bytes)
+{
+    if (!bytes) return fail(KC_ERR_ARG, "null bytes");
+    Layout lay;
+    kc_status s = make_layout(probs, count, prec, lay);
+    if (s != KC_OK) return s;
+    *bytes = lay.total;
+    return KC_OK;
+}
+
+kc_status kc_level_stencils(const kc_problem* p, int32_t max_levels, int32_t* nlevels, double* stencils)
+{
+    if (!p || !nlevels) return fail(KC_ERR_ARG, "null argument");
+    int L;
+    kc_status s = check_problem(*p, L);
+    if (s != KC_OK) return s;
+    *nlevels = L;
+    double cur[9];
+    fine_stencil(p->theta, p->eps, cur);
+    for (int d = 0; d < L && d < max_levels; ++d) {
+        if (stencils) std::memcpy(stencils + 9 * d, cur, sizeof cur);
+        double nxt[9];
+        galerkin(cur, nxt);
+        std::memcpy(cur, nxt, sizeof cur);
+    }
+    return KC_OK;
+}
+
+static kc_status validate_exec(const kc_exec* e)
+{
+    if (e->mode != 0 && e->mode != 1) return fail(KC_ERR_ARG, "exec.mode must be 0 or 1");
+    if (e->coarse_cutover < 7 || e->coarse_cutover > 63) return fail(KC_ERR_ARG, "coarse_cutover must be in 7..63");
+    if (e->coarse_threads != 256 && e->coarse_threads != 512 && e->coarse_threads != 1024)
+        return fail(KC_ERR_ARG, "coarse_threads must be 256, 512 or 1024");
+    if (e->poll_every < 0) return fail(KC_ERR_ARG, "poll_every must be >= 0");
+    return KC_OK;
+}
+
+static void build_host(kc_hier* h, const kc_problem* probs)
+{
+    h->hi.assign(h->count, HostInst());
+    for (int i = 0; i < h->count; ++i) {
+        HostInst& hi = h->hi[i];
+        hi.p = probs[i];
+        hi.il = h->lay.il[i];
+        fine_stencil(hi.p.theta, hi.p.eps, hi.s[0]);
+        for (int d = 1; d < hi.il.L; ++d) galerkin(hi.s[d - 1], hi.s[d]);
+    }
+}
+
+kc_status kc_schedule_counts(const kc_problem* probs, int32_t count, const kc_exec* exec, const kc_cycle_params* c,
+                             int64_t* grid_launches, int64_t* subtree_launches, int64_t* subtree_stages)
+{
+    kc_status s = check_cycle(c);
+    if (s != KC_OK) return s;
+    kc_hier h;
+    h.count = count;
+    kc_exec_default(&h.ex);
+    if (exec) h.ex = *exec;
+    if ((s = validate_exec(&h.ex)) != KC_OK) return s;
+    if ((s = make_layout(probs, count, KC_F64, h.lay)) != KC_OK) return s;
+    build_host(&h, probs);
+    // host-only planning: no device tables are written and the LDS limit is not checked
+    h.d_tiles = nullptr;
+    s = plan_exec(&h);
+    if (s != KC_OK) return s;
+    std::vector<int32_t> zeros((size_t)(1 + 2 * MAXL) * (count + 1) + 2 * MAXL * count, 0);
+    h.d_tiles = zeros.data();
+    h.d_lists = zeros.data() + (size_t)(1 + 2 * MAXL) * (count + 1);
+    std::vector<Launch> ls;
+    iteration(&h, DRV_CYCLE, *c, ls);
+    int64_t g = 0, sb = 0;
+    count_launches(ls, g, sb);
+    int64_t st = 0;
+    for (const Launch& L : ls)
+        if (L.type == L_SUB)
+            for (int idx : h.lists[lt_sub(L.ba.depth)]) {
+                const HostInst& hi = h.hi[idx];
+                st += hi.ops_len[std::min(L.ba.kappa, KMAX) - 1];
+                if (L.ba.pair && L.ba.kappa > 1) st += hi.ops_len[std::min(L.ba.kappa - 1, KMAX) - 1];
+                break;
+            }
+    if (grid_launches) *grid_launches = g;
+    if (subtree_launches) *subtree_launches = sb;
+    if (subtree_stages) *subtree_stages = st;
+    h.d_tiles = nullptr;
+    h.d_lists = nullptr;
+    return KC_OK;
+}
+
+kc_status kc_create(const kc_problem* probs, int32_t count, kc_precision prec, const kc_exec* exec, void* d_workspace,
+                    size_t bytes, void* hip_stream, kc_hier** out)
+{
+    if (!out) return fail(KC_ERR_ARG, "null out");
+    *out = nullptr;
+    kc_hier* h = new kc_hier();
+    h->count = count;
+    h->prec = prec;
+    kc_exec_default(&h->ex);
+    if (exec) h->ex = *exec;
+    kc_status s = validate_exec(&h->ex);
+    if (s != KC_OK) { delete h; return s; }
+    s = make_layout(probs, count, prec, h->lay);
+    if (s != KC_OK) { delete h; return s; }
+    if (!d_workspace || bytes < h->lay.total) { delete h; return fail(KC_ERR_WORKSPACE, "workspace missing or smaller than kc_workspace_bytes"); }
+    if (((uintptr_t)d_workspace) % ALIGN != 0) { delete h; return fail(KC_ERR_WORKSPACE, "workspace must be 256-byte aligned"); }
+    h->ws = (char*)d_workspace;
+    h->ws_bytes = bytes;
+    h->user_stream = (hipStream_t)hip_stream;
+    auto cleanup = [&](kc_status st) { kc_destroy(h); return st; };
+    if (h->user_stream == nullptr) {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+            return cleanup(fail(KC_ERR_HIP, "hipStreamCreateWithFlags failed"));
+        h->own_stream = true;
+    } else {
+        h->stream = h->user_stream;
+    }
+    if (hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming) != hipSuccess || hipEventCreate(&h->t0) != hipSuccess ||
+        hipEventCreate(&h->t1) != hipSuccess || hipEventCreateWithFlags(&h->ev_upload, hipEventDisableTiming) != hipSuccess)
+        return cleanup(fail(KC_ERR_HIP, "hipEventCreate failed"));
+    if (hipHostMalloc((void**)&h->h_inst, sizeof(InstDev) * count, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_st, sizeof(InstState) * count, hipHostMallocDefault) != hipSuccess)
+        return cleanup(fail(KC_ERR_HIP, "hipHostMalloc failed"));
+    std::memset(h->h_inst, 0, sizeof(InstDev) * count);
+    std::memset(h->h_st, 0, sizeof(InstState) * count);
+    h->d_inst = (InstDev*)(h->ws + h->lay.inst);
+    h->d_st = (InstState*)(h->ws + h->lay.state);
+    h->d_tiles = (int32_t*)(h->ws + h->lay.tiles);
+    h->d_lists = (int32_t*)(h->ws + h->lay.lists);
+    h->d_partial = (double*)(h->ws + h->lay.partial);
+    h->d_hist = (double*)(h->ws + h->lay.hist);
+    if ((s = enter(h)) != KC_OK) return cleanup(s);
+    build_host(h, probs);
+    // coarsest Cholesky factors
+    for (int i = 0; i < count; ++i) {
+        HostInst& hi = h->hi[i];
+        std::vector<double> c64;
+        std::vector<float> c32;
+        if (!coarse_cholesky<double>(hi.p.n_coarsest, hi.s[hi.il.L - 1], c64) ||
+            !coarse_cholesky<float>(hi.p.n_coarsest, hi.s[hi.il.L - 1], c32))
+            return cleanup(fail(KC_ERR_ARG, "coarsest matrix is not positive definite"));
+        if (hipMemcpyAsync(h->ws + hi.il.chol64, c64.data(), c64.size() * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+            hipMemcpyAsync(h->ws + hi.il.chol32, c32.data(), c32.size() * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess)
+            return cleanup(fail(KC_ERR_HIP, "upload of the coarsest factor failed"));
+    }
+    if ((s = plan_exec(h)) != KC_OK) return cleanup(s);
+    fill_inst_static(h);
+    set_omega(h, 0.8);
+    h->omega_set = 0.8;
+    if ((s = upload_inst(h)) != KC_OK) return cleanup(s);
+    if ((s = upload_state(h, 0.0, 0)) != KC_OK) return cleanup(s);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return cleanup(fail(KC_ERR_HIP, "setup synchronisation failed"));
+    if ((s = leave(h)) != KC_OK) return cleanup(s);
+    *out = h;
+    return KC_OK;
+}
+
+kc_status kc_destroy(kc_hier* h)
+{
+    if (!h) return KC_OK;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    if (h->h_inst) (void)hipHostFree(h->h_inst);
+    if (h->h_st) (void)hipHostFree(h->h_st);
+    if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+    if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+    if (h->t0) (void)hipEventDestroy(h->t0);
+    if (h->t1) (void)hipEventDestroy(h->t1);
+    if (h->ev_upload) (void)hipEventDestroy(h->ev_upload);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return KC_OK;
+}
+
+kc_status kc_set_exec(kc_hier* h, const kc_exec* exec)
+{
+    if (!h || !exec) return fail(KC_ERR_ARG, "null argument");
+    kc_status s = validate_exec(exec);
+    if (s != KC_OK) return s;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    kc_exec old = h->ex;
+    h->ex = *exec;
+    if ((s = plan_exec(h)) != KC_OK) {
+        h->ex = old;
+        (void)plan_exec(h);
+        return s;
+    }
+    fill_inst_static(h);
+    set_omega(h, h->omega_set);
+    if ((s = upload_inst(h)) != KC_OK) return s;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return KC_OK;
+}
+
+// level-0 binding of the cycle arrays for each driver
+static void bind_level0_user(kc_hier* h, double* const* v, const int64_t* ldv, const double* const* f, const int64_t* ldf)
+{
+    for (int i = 0; i < h->count; ++i) {
+        InstDev& I = h->h_inst[i];
+        const HostInst& hi = h->hi[i];
+        LevelDev& L0 = I.lev[0];
+        L0.A = v[i];
+        L0.lda = (int32_t)ldv[i];
+        L0.B = h->ws + hi.il.B[0];
+        L0.ldb = hi.il.ld[0];
+        L0.F = (void*)f[i];
+        L0.ldf = (int32_t)ldf[i];
+        L0.fscale = I.h2;
+        I.u = v[i];
+        I.ldu = (int32_t)ldv[i];
+        I.f = f[i];
+        I.ldf = (int32_t)ldf[i];
+    }
+}
+
+static void bind_level0_internal(kc_hier* h, bool pcg64)
+{
+    for (int i = 0; i < h->count; ++i) {
+        InstDev& I = h->h_inst[i];
+        const HostInst& hi = h->hi[i];
+        LevelDev& L0 = I.lev[0];
+        if (pcg64) {   // FP64 preconditioner: cycle on z with right-hand side r
+            L0.A = I.z;
+            L0.lda = I.ldv;
+            L0.B = h->ws + hi.il.B[0];
+            L0.ldb = hi.il.ld[0];
+            L0.F = I.r;
+            L0.ldf = I.ldv;
+        } else {       // FP32 cycle arrays
+            L0.A = h->ws + hi.il.A[0];
+            L0.B = h->ws + hi.il.B[0];
+            L0.F = h->ws + hi.il.F[0];
+            L0.lda = L0.ldb = L0.ldf = hi.il.ld[0];
+        }
+        L0.fscale = 1.0;
+    }
+}
+
+static void bind_user_vectors(kc_hier* h, double* const* u, const int64_t* ldu, const double* const* f, const int64_t* ldf)
+{
+    for (int i = 0; i < h->count; ++i) {
+        InstDev& I = h->h_inst[i];
+        I.u = u[i];
+        I.ldu = (int32_t)ldu[i];
+        I.f = f[i];
+        I.ldf = (int32_t)ldf[i];
+    }
+}
+
+kc_status kc_cycle(kc_hier* h, double* const* d_v, const int64_t* ldv, const double* const* d_f, const int64_t* ldf,
+                   const kc_cycle_params* c)
+{
+    if (!h) return fail(KC_ERR_ARG, "null hierarchy");
+    if (h->prec != KC_F64) return fail(KC_ERR_STATE, "kc_cycle needs an FP64 hierarchy");
+    kc_status s;
+    if ((s = check_ptrs(h, d_v, ldv, "v")) != KC_OK || (s = check_ptrs(h, d_f, ldf, "f")) != KC_OK) return s;
+    if ((s = prepare_call(h, c)) != KC_OK) return s;
+    if ((s = enter(h)) != KC_OK) return s;
+    bind_level0_user(h, d_v, ldv, d_f, ldf);
+    if ((s = upload_inst(h)) != KC_OK) return s;
+    if ((s = upload_state(h, 0.0, 0)) != KC_OK) return s;
+    if ((s = launch_iteration(h, DRV_CYCLE, *c, 1)) != KC_OK) return s;
+    record_counts(h, DRV_CYCLE, *c);
+    return leave(h);
+}
+
+kc_status kc_solve(kc_hier* h, double* const* d_u, const int64_t* ldu, const double* const* d_f, const int64_t* ldf,
+                   const kc_cycle_params* c, double tol, int32_t maxit, int32_t* iters, double* relres, int32_t* status)
+{
+    if (!h) return fail(KC_ERR_ARG, "null hierarchy");
+    kc_status s;
+    if ((s = check_ptrs(h, d_u, ldu, "u")) != KC_OK || (s = check_ptrs(h, d_f, ldf, "f")) != KC_OK) return s;
+    if (maxit < 0 || !(tol >= 0.0)) return fail(KC_ERR_ARG, "maxit must be >= 0 and tol >= 0");
+    if (maxit >= HIST_CAP) return fail(KC_ERR_ARG, "maxit must be below the history capacity (8192)");
+    if ((s = prepare_call(h, c)) != KC_OK) return s;
+    if ((s = enter(h)) != KC_OK) return s;
+    const bool f32 = h->prec == KC_F32_CYCLE;
+    if (f32) {
+        bind_user_vectors(h, d_u, ldu, d_f, ldf);
+        bind_level0_internal(h, false);
+    } else {
+        bind_level0_user(h, d_u, ldu, d_f, ldf);
+    }
+    if ((s = upload_inst(h)) != KC_OK) return s;
+    if ((s = upload_state(h, tol, maxit)) != KC_OK) return s;
+    {
+        Launch L = grid(h, GK_SSF, f32, tt_all0(), 0);
+        L.sa.fin = FIN_SSF;
+        HIPCHK(launch_grid(L.gk, L.f32, L.sa, L.nblocks, h->stream));
+    }
+    const int drv = f32 ? DRV_IR : DRV_SOLVE64;
+    s = drive(h, drv, *c, maxit, iters, relres, status);
+    record_counts(h, drv, *c);
+    h->last_driver = f32 ? "solve_ir_f32" : "solve_f64";
+    kc_status s2 = leave(h);
+    return s2 != KC_OK ? s2 : s;
+}
+
+kc_status kc_pcg(kc_hier* h, double* const* d_u, const int64_t* ldu, const double* const* d_f, const int64_t* ldf,
+                 const kc_cycle_params* c, double tol, int32_t maxit, int32_t* iters, double* relres, int32_t* status)
+{
+    if (!h) return fail(KC_ERR_ARG, "null hierarchy");
+    kc_status s;
+    if ((s = check_ptrs(h, d_u, ldu, "u")) != KC_OK || (s = check_ptrs(h, d_f, ldf, "f")) != KC_OK) return s;
+    if (maxit < 0 || !(tol >= 0.0)) return fail(KC_ERR_ARG, "maxit must be >= 0 and tol >= 0");
+    if (maxit >= HIST_CAP) return fail(KC_ERR_ARG, "maxit must be below the history capacity (8192)");
+    if ((s = prepare_call(h, c)) != KC_OK) return s;
+    if ((s = enter(h)) != KC_OK) return s;
+    const bool f32 = h->prec == KC_F32_CYCLE;
+    bind_user_vectors(h, d_u, ldu, d_f, ldf);
+    bind_level0_internal(h, !f32);
+    if ((s = upload_inst(h)) != KC_OK) return s;
+    if ((s = upload_state(h, tol, maxit)) != KC_OK) return s;
+    {
+        Launch L = grid(h, GK_PCG_INIT, f32, tt_all0(), 0);
+        L.sa.fin = FIN_PCG_INIT;
+        HIPCHK(launch_grid(L.gk, L.f32, L.sa, L.nblocks, h->stream));
+    }
+    s = drive(h, DRV_PCG, *c, maxit, iters, relres, status);
+    record_counts(h, DRV_PCG, *c);
+    h->last_driver = f32 ? "pcg_f32_precond" : "pcg_f64";
+    kc_status s2 = leave(h);
+    return s2 != KC_OK ? s2 : s;
+}
+
+kc_status kc_apply_A(kc_hier* h, double* const* d_y, const int64_t* ldy, const double* const* d_x, const int64_t* ldx)
+{
+    if (!h) return fail(KC_ERR_ARG, "null hierarchy");
+    kc_status s;
+    if ((s = check_ptrs(h, d_y, ldy, "y")) != KC_OK || (s = check_ptrs(h, d_x, ldx, "x")) != KC_OK) return s;
+    if ((s = enter(h)) != KC_OK) return s;
+    for (int i = 0; i < h->count; ++i) {
+        InstDev& I = h->h_inst[i];
+        I.x = d_x[i];
+        I.ldx = (int32_t)ldx[i];
+        I.y = d_y[i];
+        I.ldy = (int32_t)ldy[i];
+    }
+    if ((s = upload_inst(h)) != KC_OK) return s;
+    if ((s = upload_state(h, 0.0, 0)) != KC_OK) return s;
+    Launch L = grid(h, GK_APPLY, false, tt_all0(), 0);
+    HIPCHK(launch_grid(L.gk, L.f32, L.sa, L.nblocks, h->stream));
+    return leave(h);
+}
+
+kc_status kc_grad_params(kc_hier* h, const double* const* d_lam, const int64_t* ldl, const double* const* d_u,
+                         const int64_t* ldu, double* dtheta, double* deps)
+{
+    if (!h) return fail(KC_ERR_ARG, "null hierarchy");
+    if (!dtheta || !deps) return fail(KC_ERR_ARG, "null outputs");
+    kc_status s;
+    if ((s = check_ptrs(h, d_lam, ldl, "lam")) != KC_OK || (s = check_ptrs(h, d_u, ldu, "u")) != KC_OK) return s;
+    if ((s = enter(h)) != KC_OK) return s;
+    for (int i = 0; i < h->count; ++i) {
+        InstDev& I = h->h_inst[i];
+        I.x = d_lam[i];
+        I.ldx = (int32_t)ldl[i];
+        I.y = (double*)d_u[i];
+        I.ldy = (int32_t)ldu[i];
+    }
+    if ((s = upload_inst(h)) != KC_OK) return s;
+    if ((s = upload_state(h, 0.0, 0)) != KC_OK) return s;
+    Launch L = grid(h, GK_GRAD, false, tt_all0(), 0);
+    L.sa.fin = FIN_GRAD;
+    HIPCHK(launch_grid(L.gk, L.f32, L.sa, L.nblocks, h->stream));
+    HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, sizeof(InstState) * h->count, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < h->count; ++i) {
+        dtheta[i] = h->h_st[i].dth;
+        deps[i] = h->h_st[i].deps;
+    }
+    return leave(h);
+}
+
+kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
+{
+    if (!h || !out || cap == 0) return fail(KC_ERR_ARG, "null argument");
+    std::string js = "{";
+    js += "\"count\": " + std::to_string(h->count);
+    js += ", \"precision\": \"" + std::string(h->prec == KC_F64 ? "f64" : "f32_cycle") + "\"";
+    js += ", \"mode\": \"" + std::string(h->ex.mode == 1 ? "paper" : "fused") + "\"";
+    js += ", \"graph\": " + std::to_string(h->ex.use_graph);
+    js += ", \"coarse_cutover\": " + std::to_string(h->ex.coarse_cutover);
+    js += ", \"coarse_threads\": " + std::to_string(h->ex.coarse_threads);
+    js += ", \"subtree_lds_bytes\": " + std::to_string(h->sub_lds);
+    js += ", \"workspace_bytes\": " + std::to_string(h->lay.total);
+    js += ", \"driver\": \"" + h->last_driver + "\"";
+    js += ", \"grid_launches_per_iteration\": " + std::to_string(h->last_grid);
+    js += ", \"subtree_launches_per_iteration\": " + std::to_string(h->last_sub);
+    js += ", \"subtree_stages_per_iteration\": " + std::to_string(h->last_sub_stages);
+    js += ", \"iterations_launched\": " + std::to_string(h->last_launched);
+    js += ", \"max_iterations\": " + std::to_string(h->last_cycles);
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%.6f", h->last_ms);
+    js += ", \"last_ms\": " + std::string(buf);
+    js += ", \"levels\": [";
+    for (int i = 0; i < h->count; ++i) {
+        if (i) js += ", ";
+        js += "{\"L\": " + std::to_string(h->hi[i].il.L) + ", \"cut\": " + std::to_string(h->hi[i].cut) +
+              ", \"n\": " + std::to_string(h->hi[i].il.n[0]) + "}";
+    }
+    js += "]}";
+    if (js.size() + 1 > cap) return fail(KC_ERR_ARG, "stats buffer too small");
+    std::memcpy(out, js.c_str(), js.size() + 1);
+    return KC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+"""GPU parity: the HIP library against the oracle, element by element, on
+seeded inputs (through the C-ABI via the ctypes binding).
+
+FP64 paths use the same arithmetic order as the oracle (per-point stencil
+sums, Jacobi update, full weighting, bilinear gather, Galerkin stencils,
+Cholesky coarsest solve), so single cycles and stand-alone iterates are
+compared bitwise; the bar stated by the workload is 1e-11 relative, which is
+asserted everywhere.  Norms are summed in a different order, so a relative
+residual may differ in the last bits: iteration counts must be identical and
+the tests check that no stop decision lies within 1e-12 of the tolerance.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2010_00626_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def K():
+    from paper_2010_00626_amd import kcycle
+    return kcycle
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def banner(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+
+
+@pytest.mark.parametrize("n", [7, 63, 127, 255, 1023])
+def test_apply_A_bitwise(n):
+    banner(f"apply_A n={n}")
+    rng = np.random.default_rng(n)
+    th, ep = 0.7, 3e-3
+    x = rng.uniform(-1, 1, (n, n))
+    H = K().Hierarchy([(n, th, ep)])
+    y = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    H.apply_A(y, dev(x))
+    ref = O.Hierarchy(n, th, ep).apply(x)
+    assert np.array_equal(host(y), ref)
+
+
+CYCLE_CASES = [
+    # n, n_coarsest, kappa, nu1, nu2, mode, graph
+    (63, 3, 1, 2, 2, "fused", True),
+    (63, 1, 3, 2, 2, "fused", False),
+    (127, 1, 2, 2, 2, "fused", True),
+    (255, 1, 3, 1, 1, "fused", True),
+    (255, 1, 4, 2, 1, "fused", True),
+    (511, 1, 2 ** 31 - 1, 2, 2, "fused", True),
+    (1023, 1, 3, 2, 2, "fused", True),
+    (127, 3, 2, 2, 2, "paper", True),
+    (255, 1, 3, 1, 1, "paper", False),
+    (63, 7, 1, 2, 2, "paper", True),
+]
+
+
+@pytest.mark.parametrize("n,nc,kappa,nu1,nu2,mode,graph", CYCLE_CASES)
+def test_one_cycle_bitwise(n, nc, kappa, nu1, nu2, mode, graph):
+    banner(f"one cycle n={n} nc={nc} kappa={kappa} nu={nu1}+{nu2} mode={mode} graph={graph}")
+    rng = np.random.default_rng(n + kappa)
+    th, ep = 0.9, 2e-3
+    v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
+    H = K().Hierarchy([(n, th, ep, nc)], exec=dict(mode=mode, use_graph=graph))
+    v = dev(v0)
+    H.cycle(v, dev(f), kappa=kappa, nu1=nu1, nu2=nu2)
+    Ho = O.Hierarchy(n, th, ep, n_coarsest=nc)
+    ref = Ho.cycle(v0, f, kappa=min(kappa, 64), nu1=nu1, nu2=nu2)[0]
+    got = host(v)
+    assert relmax(got, ref) <= 1e-11
+    assert np.array_equal(got, ref)
+    # a second cycle on the same handle reuses the captured schedule
+    H.cycle(v, dev(f), kappa=kappa, nu1=nu1, nu2=nu2)
+    ref2 = Ho.cycle(ref, f, kappa=min(kappa, 64), nu1=nu1, nu2=nu2)[0]
+    assert np.array_equal(host(v), ref2)
+
+
+def check_stop_margin(hist, tol):
+    """No relative residual of the run lies within 1e-12 (relative) of tol."""
+    h = np.asarray(hist)
+    assert np.all(np.abs(h - tol) > 1e-12 * tol)
+
+
+@pytest.mark.parametrize("kappa", [1, 2, 3, 4, 5])
+def test_config1_solve(kappa):
+    w = inputs.config1()
+    inst = w.instances[0]
+    banner(f"config1 solve kappa={kappa}")
+    Ho = O.Hierarchy(inst.n, inst.theta, inst.eps, n_coarsest=w.n_coarsest, omega=w.omega)
+    u_ref, rc, it_ref, hist = Ho.solve(inst.f, kappa=kappa, nu1=w.nu1, nu2=w.nu2, tol=w.tol, maxit=1000)
+    assert rc == O.OK
+    check_stop_margin(hist, w.tol)
+    H = K().Hierarchy([(inst.n, inst.theta, inst.eps, w.n_coarsest)])
+    u = torch.zeros((inst.n, inst.n), dtype=torch.float64, device="cuda")
+    iters, relres, status = H.solve(u, dev(inst.f), kappa=kappa, nu1=w.nu1, nu2=w.nu2, omega=w.omega, tol=w.tol,
+                                    maxit=1000)
+    assert status == [0]
+    assert iters[0] == it_ref
+    assert abs(relres[0] - hist[-1]) <= 1e-12 * hist[-1]
+    got = host(u)
+    assert relmax(got, u_ref) <= 1e-11
+    assert np.array_equal(got, u_ref)
+
+
+@pytest.mark.parametrize("n,kappa,mode", [(255, 1, "fused"), (255, 3, "fused"), (255, 2 ** 31 - 1, "fused"),
+                                          (511, 2, "fused"), (255, 3, "paper")])
+def test_standalone_solve_reduced_config2(n, kappa, mode):
+    banner(f"stand-alone n={n} kappa={kappa} mode={mode}")
+    rng = np.random.default_rng(1)
+    f = inputs.uniform_rhs(rng, n)
+    th, ep = math.pi / 6, 1e-4
+    Ho = O.Hierarchy(n, th, ep)
+    u_ref, rc, it_ref, hist = Ho.solve(f, kappa=min(kappa, 64), tol=1e-8, maxit=5000)
+    assert rc == O.OK
+    check_stop_margin(hist, 1e-8)
+    H = K().Hierarchy([(n, th, ep)], exec=dict(mode=mode))
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    iters, relres, status = H.solve(u, dev(f), kappa=kappa, tol=1e-8, maxit=5000)
+    assert status == [0] and iters[0] == it_ref
+    got = host(u)
+    assert relmax(got, u_ref) <= 1e-11
+    assert np.array_equal(got, u_ref)
+
+
+def test_batched_equals_per_instance():
+    banner("batched ragged stand-alone")
+    specs = [(255, 0.3, 1e-3), (63, 1.2, 1e-2), (511, 2.0, 1e-4), (127, 0.8, 0.05), (31, 2.7, 1e-5)]
+    rng = np.random.default_rng(2)
+    fs = [inputs.uniform_rhs(rng, s[0]) for s in specs]
+    Hb = K().Hierarchy(specs)
+    us = [torch.zeros((s[0], s[0]), dtype=torch.float64, device="cuda") for s in specs]
+    iters, relres, status = Hb.solve(us, [dev(f) for f in fs], kappa=3, tol=1e-8, maxit=3000)
+    assert status == [0] * len(specs)
+    for k, (s, f) in enumerate(zip(specs, fs)):
+        Ho = O.Hierarchy(*s)
+        u_ref, rc, it_ref, hist = Ho.solve(f, kappa=3, tol=1e-8, maxit=3000)
+        assert iters[k] == it_ref, k
+        assert np.array_equal(host(us[k]), u_ref), k
+        Hs = K().Hierarchy([s])
+        u1 = torch.zeros_like(us[k])
+        it1, _, st1 = Hs.solve(u1, dev(f), kappa=3, tol=1e-8, maxit=3000)
+        assert it1[0] == iters[k] and torch.equal(u1, us[k])
+
+
+@pytest.mark.parametrize("n,kappa", [(255, 1), (255, 3), (511, 4)])
+def test_ir_fp32(n, kappa):
+    banner(f"FP32 cycles + FP64 refinement n={n} kappa={kappa}")
+    rng = np.random.default_rng(1)
+    f = inputs.uniform_rhs(rng, n)
+    th, ep = math.pi / 6, 1e-4
+    Ho = O.Hierarchy(n, th, ep)
+    u_ir, rc, it_ir, hist = Ho.ir_solve(f, kappa=kappa, tol=1e-8, maxit=5000)
+    u64, rc64, it64, _ = Ho.solve(f, kappa=kappa, tol=1e-8, maxit=5000)
+    assert rc == O.OK
+    H = K().Hierarchy([(n, th, ep)], precision="f32")
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    iters, relres, status = H.solve(u, dev(f), kappa=kappa, tol=1e-8, maxit=5000)
+    assert status == [0]
+    got = host(u)
+    true_rel = np.linalg.norm(f - Ho.apply(got)) / np.linalg.norm(f)
+    assert true_rel < 1e-8
+    assert abs(iters[0] - it_ir) <= 1
+    assert iters[0] <= it64 + 2
+    assert relmax(got, u_ir) <= 1e-6
+    assert relmax(got, u64) <= 1e-6
+
+
+@pytest.mark.parametrize("n,kappa,f32", [(127, 1, False), (255, 2, False), (255, 3, False), (255, 3, True),
+                                         (511, 4, True)])
+def test_pcg(n, kappa, f32):
+    banner(f"PCG n={n} kappa={kappa} f32={f32}")
+    f = inputs.gaussian_sum_rhs(5, n)
+    th, ep = 3 * math.pi / 8, 1e-5
+    Ho = O.Hierarchy(n, th, ep)
+    u_ref, rc, it_ref, hist = Ho.pcg(f, kappa=kappa, nu1=1, nu2=1, tol=1e-8, maxit=500, precond_f32=f32)
+    assert rc == O.OK
+    H = K().Hierarchy([(n, th, ep)], precision="f32" if f32 else "f64")
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    iters, relres, status = H.pcg(u, dev(f), kappa=kappa, nu1=1, nu2=1, tol=1e-8, maxit=500)
+    assert status == [0]
+    assert abs(iters[0] - it_ref) <= (0 if not f32 else 1)
+    got = host(u)
+    assert relmax(got, u_ref) <= (1e-9 if not f32 else 1e-6)
+    true_rel = np.linalg.norm(f - Ho.apply(got)) / np.linalg.norm(f)
+    assert true_rel < 2e-8
+
+
+def test_grad_params_match_oracle():
+    banner("gradient inner products")
+    n = 255
+    rng = np.random.default_rng(3)
+    specs = [(n, 0.4, 1e-3), (n, 2.2, 0.05)]
+    lams = [rng.uniform(-1, 1, (n, n)) for _ in specs]
+    us = [rng.uniform(-1, 1, (n, n)) for _ in specs]
+    H = K().Hierarchy(specs)
+    dth, de = H.grad_params([dev(x) for x in lams], [dev(x) for x in us])
+    for k, s in enumerate(specs):
+        rt, re = O.Hierarchy(*s).grad_params(lams[k], us[k])
+        assert abs(dth[k] - rt) <= 1e-12 * abs(rt)
+        assert abs(de[k] - re) <= 1e-12 * abs(re)
+
+
+def test_failure_statuses():
+    banner("failure statuses")
+    n = 63
+    f = inputs.uniform_rhs(np.random.default_rng(0), n)
+    KK = K()
+    H = KK.Hierarchy([(n, 0.4, 1e-3, 3)])
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    it, rr, st = H.solve(u, dev(f), kappa=2, tol=1e-10, maxit=1)
+    assert st == [KK.KC_NOT_CONVERGED] and it == [1]
+    u.zero_()
+    it, rr, st = H.solve(u, dev(f), kappa=1, omega=2.5, tol=1e-10, maxit=500)
+    assert st == [KK.KC_DIVERGED]
+    bad = f.copy()
+    bad[3, 4] = np.nan
+    u.zero_()
+    it, rr, st = H.solve(u, dev(bad), kappa=1, tol=1e-10, maxit=5)
+    assert st == [KK.KC_ERR_NONFINITE]
+    with pytest.raises(KK.KCycleError):
+        H.cycle(u, dev(f), kappa=0)
+
+
+def test_deterministic_rerun():
+    banner("run-twice determinism")
+    n = 511
+    f = inputs.uniform_rhs(np.random.default_rng(7), n)
+    H = K().Hierarchy([(n, 1.0, 1e-3)])
+    outs = []
+    for _ in range(2):
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        it, rr, st = H.solve(u, dev(f), kappa=3, tol=1e-9, maxit=2000)
+        outs.append((it[0], rr[0], host(u)))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2])
