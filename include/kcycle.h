@@ -91,10 +91,11 @@ typedef struct {
     int32_t mode;           /* 0 = fused kernels + persistent coarse subtree (default);
                                1 = one kernel per operation of Algorithm 4 ("paper-structured") */
     int32_t use_graph;      /* 1 = capture one cycle as a hipGraph and replay it (default) */
-    int32_t coarse_cutover; /* levels with n <= cutover run in the persistent kernel (31 or 63; default 63) */
-    int32_t coarse_threads; /* threads of the persistent kernel (256, 512 or 1024; default 512) */
+    int32_t coarse_cutover; /* levels with n <= cutover run in the persistent kernel (7..63; default 31) */
+    int32_t coarse_threads; /* threads of the persistent kernel (256 or 512; default 512) */
     int32_t poll_every;     /* cycles launched between host polls of the stop flags (default 0 = adaptive) */
-    int32_t reserved[3];
+    int32_t coarse_wave_n;  /* persistent-kernel levels with n <= this run on one wave (0..15; default 15) */
+    int32_t reserved[2];
 } kc_exec;
 
 typedef struct kc_hier kc_hier;
@@ -160,6 +161,25 @@ kc_status kc_level_stencils(const kc_problem* p, int32_t max_levels, int32_t* nl
 kc_status kc_schedule_counts(const kc_problem* probs, int32_t count, const kc_exec* exec,
                              const kc_cycle_params* c, int64_t* grid_launches, int64_t* subtree_launches,
                              int64_t* subtree_stages);
+
+/* instrumentation: average duration of one launch of a single schedule
+ * stage, timed with hip events around `reps` back-to-back launches on the
+ * hierarchy's stream, on the arrays bound by the previous driver call (run a
+ * kc_solve / kc_pcg / kc_cycle first).  which:
+ *   0 = fused pre-smoothing kernel of the fine level (nu1 sweeps + residual +
+ *       full weighting; the stand-alone FP64 variant also sums the residual),
+ *   1 = fused post-smoothing kernel of the fine level (prolong-add + nu2),
+ *   2 = one persistent coarse launch (both calls below the first parent),
+ *   3 = the FP64 residual pass of refinement (FP32 hierarchies),
+ *   100 + d / 200 + d = the pre / post kernel of depth d (0 = finest),
+ *   300 + d = the persistent launch of depth d (a pair of calls; for d = 0
+ *   a single call of the whole cycle).
+ * bytes receives the algorithmic bytes one launch must move (every input read
+ * once, every output written once).  The instances are left finished (the
+ * stop flags are set), so run a driver call again before relying on them.
+ * Synchronises.  KC_ERR_STATE if the stage does not exist in this schedule. */
+kc_status kc_time_stage(kc_hier* h, int32_t which, const kc_cycle_params* c, int32_t reps, double* avg_ms,
+                        double* bytes);
 
 /* JSON summary: sizes, launches per cycle, last solve's timings */
 kc_status kc_stats(const kc_hier* h, char* out, size_t cap);

@@ -37,8 +37,7 @@ struct InstDev {
     LevelDev lev[MAXL];  // cycle levels (level 0 may alias user arrays)
     const double* chol64;  // lower Cholesky factor of the coarsest matrix, nc2 x nc2 row-major (scaled system)
     const float* chol32;
-    int32_t lds_off[MAXL]; // persistent kernel: element offset of level d's v in LDS (F follows)
-    int32_t lds_tmp;       // persistent kernel: element offset of the shared sweep buffer
+    int32_t lds_off[MAXL]; // persistent kernel: element offset of level d's three (n+2)^2 arrays
     int32_t ops_beg[MAXL + 1]; // persistent kernel op list of a call with counter k = 1..MAXL+1
     int32_t ops_len[MAXL + 1];
     const uint32_t* ops;       // op list storage
@@ -133,6 +132,7 @@ struct SubArgs {
     int32_t nu1, nu2;
     int32_t zg;               // single call: estimate is zero on entry
     int32_t fin;              // single call: FIN_STOP computes the stop test first
+    int32_t wave_n;           // levels with n <= wave_n are run by one wave
     double* hist;
 };
 

@@ -49,7 +49,7 @@ template <typename T> struct Sten {
         for (int k = 0; k < 9; ++k) c[k] = s[k];
     }
     // sum over the 3x3 neighbourhood of x at (row pointer p, stride st), fixed order
-    __device__ T apply(const T* x, int st) const
+    __device__ __forceinline__ T apply(const T* x, int st) const
     {
         T acc = T(0);
         acc += c[0] * x[-st - 1];
@@ -92,7 +92,7 @@ __device__ inline T gapply(const Sten<T>& s, const T* x, int ld, int n, int j, i
 
 // full weighting sum around the fine point at r (stride st)
 template <typename T>
-__device__ inline T fw_sum(const T* r, int st)
+__device__ __forceinline__ T fw_sum(const T* r, int st)
 {
     const T q = T(0.25), h = T(0.5);
     T acc = T(0);
@@ -110,7 +110,7 @@ __device__ inline T fw_sum(const T* r, int st)
 
 // bilinear prolongation at fine (j, i) from coarse values V(J, I)
 template <typename T, typename Get>
-__device__ inline T prolong_at(int j, int i, Get V)
+__device__ __forceinline__ T prolong_at(int j, int i, Get V)
 {
     const int Js = (j - 1) >> 1, Is = (i - 1) >> 1;
     const bool jo = j & 1, io = i & 1;
@@ -264,36 +264,35 @@ __device__ void apply_fin(const StageArgs& a, int inst, double S0, double S1)
     }
 }
 
-// every block of a reducing launch calls this once with its thread values
-__device__ void reduce_finalize(const StageArgs& a, const Tile& t, double v0, double v1)
+// every block of a reducing launch stores its two block sums; the finalize
+// kernel (one workgroup per instance, launched next on the stream) adds them
+// in block order and applies the solver's decision
+__device__ void reduce_partial(const StageArgs& a, const Tile& t, double v0, double v1)
 {
     __shared__ double red[2][GRID_THREADS / 64];
-    __shared__ int am_last;
     const double s0 = block_sum<GRID_THREADS>(v0, red[0]);
     const double s1 = block_sum<GRID_THREADS>(v1, red[1]);
-    const int gb = a.tile_off[t.inst] + t.blk;
     if (threadIdx.x == 0) {
+        const int gb = a.tile_off[t.inst] + t.blk;
         a.partial[2 * gb] = s0;
         a.partial[2 * gb + 1] = s1;
-        __threadfence();
-        const int prev = atomicAdd(&a.st[t.inst].counter, 1);
-        am_last = (prev == t.nblk - 1);
     }
-    __syncthreads();
-    if (!am_last) return;
-    __threadfence();
-    const int b0 = a.tile_off[t.inst];
+}
+
+__global__ void __launch_bounds__(GRID_THREADS) k_finalize(StageArgs a)
+{
+    __shared__ double red[2][GRID_THREADS / 64];
+    const int inst = blockIdx.x;
+    const int b0 = a.tile_off[inst], nb = a.tile_off[inst + 1] - b0;
+    if (nb == 0 || a.st[inst].done) return;
     double t0 = 0.0, t1 = 0.0;
-    for (int k = threadIdx.x; k < t.nblk; k += GRID_THREADS) {
-        t0 += __builtin_nontemporal_load(&a.partial[2 * (b0 + k)]);
-        t1 += __builtin_nontemporal_load(&a.partial[2 * (b0 + k) + 1]);
+    for (int k = threadIdx.x; k < nb; k += GRID_THREADS) {
+        t0 += a.partial[2 * (b0 + k)];
+        t1 += a.partial[2 * (b0 + k) + 1];
     }
     const double S0 = block_sum<GRID_THREADS>(t0, red[0]);
     const double S1 = block_sum<GRID_THREADS>(t1, red[1]);
-    if (threadIdx.x == 0) {
-        a.st[t.inst].counter = 0;
-        apply_fin(a, t.inst, S0, S1);
-    }
+    if (threadIdx.x == 0) apply_fin(a, inst, S0, S1);
 }
 
 template <typename T> __device__ inline T* buf(const LevelDev& L, int sel) { return (T*)(sel ? L.B : L.A); }
@@ -301,8 +300,8 @@ template <typename T> __device__ inline T* buf(const LevelDev& L, int sel) { ret
 // ---------------------------------------------------------------------------
 // unfused kernels: one kernel per operation of Algorithm 4
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a, int kind)
+template <typename T, int kind>
+__global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a)
 {
     Tile t;
     if (!get_tile(a, a.depth, false, t)) return;
@@ -350,6 +349,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a, int kind)
         return;
     }
 
+#pragma unroll
     for (int k = ty; k < TY; k += GRID_THREADS / 64) {
         const int j = t.y0 + k, i = t.x0 + tx;
         const bool in = (j < n) && (i < n);
@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a, int kind)
             break;
         }
     }
-    if (kind == GK_NORM) reduce_finalize(a, t, nrm, 0.0);
+    if (kind == GK_NORM) reduce_partial(a, t, nrm, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -433,12 +433,26 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
     const T w = P<T>::w(I, d);
     const bool zg = a.zg != 0;
 
-    for (int p = threadIdx.x; p < RH * RW; p += GRID_THREADS) {
-        const int rj = p / RW, ri = p - rj * RW;
-        const int j = ry0 + rj, i = rx0 + ri;
-        const bool in = inside(j, i, n);
-        sf[p] = in ? fs * F[(size_t)j * Lv.ldf + i] : T(0);
-        sv[0][p] = (in && !zg) ? A[(size_t)j * Lv.lda + i] : T(0);
+    {   // every load of the region in flight before the LDS stores
+        constexpr int NR = RH * RW, NPT = (NR + GRID_THREADS - 1) / GRID_THREADS;
+        T fa[NPT], va[NPT];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int p = threadIdx.x + k * GRID_THREADS;
+            const int rj = p / RW, ri = p - rj * RW;
+            const int j = ry0 + rj, i = rx0 + ri;
+            const bool in = p < NR && inside(j, i, n);
+            fa[k] = in ? fs * F[(size_t)j * Lv.ldf + i] : T(0);
+            va[k] = (in && !zg) ? A[(size_t)j * Lv.lda + i] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int p = threadIdx.x + k * GRID_THREADS;
+            if (p < NR) {
+                sf[p] = fa[k];
+                sv[0][p] = va[k];
+            }
+        }
     }
     __syncthreads();
 
@@ -453,51 +467,51 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
         }
     }
 
-    int cur = 0;
 #pragma unroll
     for (int k = 1; k <= NU; ++k) {
         const int ww = RW - 2 * k, hh = RH - 2 * k;
+        T* src = sv[(k - 1) & 1];
+        T* dst = sv[k & 1];
         for (int p = threadIdx.x; p < ww * hh; p += GRID_THREADS) {
             const int rj = k + p / ww, ri = k + (p % ww);
             const int q = rj * RW + ri;
             T val = T(0);
             if (inside(ry0 + rj, rx0 + ri, n)) {
                 if (k == 1 && zg) val = w * sf[q];
-                else val = sv[cur][q] + w * (sf[q] - s.apply(&sv[cur][q], RW));
+                else val = src[q] + w * (sf[q] - s.apply(&src[q], RW));
             }
-            sv[cur ^ 1][q] = val;
+            dst[q] = val;
         }
         __syncthreads();
-        cur ^= 1;
     }
+    const T* vs = sv[NU & 1];
+    T* rs = sv[(NU + 1) & 1];
 
     // smoothed estimate on the tile
     for (int p = threadIdx.x; p < TX * TY; p += GRID_THREADS) {
         const int y = p / TX, x = p % TX;
         const int j = t.y0 + y, i = t.x0 + x;
-        if (j < n && i < n) B[(size_t)j * Lv.ldb + i] = sv[cur][(H + y) * RW + (H + x)];
+        if (j < n && i < n) B[(size_t)j * Lv.ldb + i] = vs[(H + y) * RW + (H + x)];
     }
     // residual on [x0, x0+TX] x [y0, y0+TY]
     for (int p = threadIdx.x; p < (TX + 1) * (TY + 1); p += GRID_THREADS) {
         const int y = p / (TX + 1), x = p % (TX + 1);
         const int q = (H + y) * RW + (H + x);
-        const int j = t.y0 + y, i = t.x0 + x;
-        sv[cur ^ 1][q] = inside(j, i, n) ? sf[q] - s.apply(&sv[cur][q], RW) : T(0);
+        rs[q] = inside(t.y0 + y, t.x0 + x, n) ? sf[q] - s.apply(&vs[q], RW) : T(0);
     }
     __syncthreads();
     {
         const LevelDev& Lc = I.lev[d + 1];
         const int nc = Lc.n, ldc = Lc.ldf;
         T* Fc = (T*)Lc.F;
-        const T* r = sv[cur ^ 1];
         for (int p = threadIdx.x; p < (TX / 2) * (TY / 2); p += GRID_THREADS) {
             const int Ic = (t.x0 >> 1) + (p % (TX / 2)), Jc = (t.y0 >> 1) + (p / (TX / 2));
             if (Ic >= nc || Jc >= nc) continue;
             const int q = (2 * Jc + 1 - ry0) * RW + (2 * Ic + 1 - rx0);
-            Fc[(size_t)Jc * ldc + Ic] = fw_sum(&r[q], RW);
+            Fc[(size_t)Jc * ldc + Ic] = fw_sum(&rs[q], RW);
         }
     }
-    if (a.fin == FIN_STOP) reduce_finalize(a, t, nrm, 0.0);
+    if (a.fin == FIN_STOP) reduce_partial(a, t, nrm, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -530,16 +544,38 @@ __global__ void __launch_bounds__(GRID_THREADS) k_post(StageArgs a)
     s.load(P<T>::s(I, d));
     const T w = P<T>::w(I, d);
 
-    for (int p = threadIdx.x; p < RH * RW; p += GRID_THREADS) {
-        const int rj = p / RW, ri = p - rj * RW;
-        const int j = ry0 + rj, i = rx0 + ri;
-        const bool in = inside(j, i, n);
-        sf[p] = in ? fs * F[(size_t)j * Lv.ldf + i] : T(0);
-        sv[0][p] = in ? B[(size_t)j * Lv.ldb + i] : T(0);
-    }
-    for (int p = threadIdx.x; p < CH * CW; p += GRID_THREADS) {
-        const int cj = p / CW, ci = p - cj * CW;
-        sc[p] = gload(Vc, ldc, nc, cy0 + cj, cx0 + ci);
+    {   // every load of the region in flight before the LDS stores
+        constexpr int NR = RH * RW, NPT = (NR + GRID_THREADS - 1) / GRID_THREADS;
+        constexpr int NC = CH * CW, NPC = (NC + GRID_THREADS - 1) / GRID_THREADS;
+        T fa[NPT], va[NPT], ca[NPC];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int p = threadIdx.x + k * GRID_THREADS;
+            const int rj = p / RW, ri = p - rj * RW;
+            const int j = ry0 + rj, i = rx0 + ri;
+            const bool in = p < NR && inside(j, i, n);
+            fa[k] = in ? fs * F[(size_t)j * Lv.ldf + i] : T(0);
+            va[k] = in ? B[(size_t)j * Lv.ldb + i] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NPC; ++k) {
+            const int p = threadIdx.x + k * GRID_THREADS;
+            const int cj = p / CW, ci = p - cj * CW;
+            ca[k] = (p < NC) ? gload(Vc, ldc, nc, cy0 + cj, cx0 + ci) : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int p = threadIdx.x + k * GRID_THREADS;
+            if (p < NR) {
+                sf[p] = fa[k];
+                sv[0][p] = va[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NPC; ++k) {
+            const int p = threadIdx.x + k * GRID_THREADS;
+            if (p < NC) sc[p] = ca[k];
+        }
     }
     __syncthreads();
     for (int p = threadIdx.x; p < RH * RW; p += GRID_THREADS) {
@@ -550,24 +586,25 @@ __global__ void __launch_bounds__(GRID_THREADS) k_post(StageArgs a)
         sv[0][p] = sv[0][p] + e;
     }
     __syncthreads();
-    int cur = 0;
 #pragma unroll
     for (int k = 1; k <= NU; ++k) {
         const int ww = RW - 2 * k, hh = RH - 2 * k;
+        T* src = sv[(k - 1) & 1];
+        T* dst = sv[k & 1];
         for (int p = threadIdx.x; p < ww * hh; p += GRID_THREADS) {
             const int rj = k + p / ww, ri = k + (p % ww);
             const int q = rj * RW + ri;
             T val = T(0);
-            if (inside(ry0 + rj, rx0 + ri, n)) val = sv[cur][q] + w * (sf[q] - s.apply(&sv[cur][q], RW));
-            sv[cur ^ 1][q] = val;
+            if (inside(ry0 + rj, rx0 + ri, n)) val = src[q] + w * (sf[q] - s.apply(&src[q], RW));
+            dst[q] = val;
         }
         __syncthreads();
-        cur ^= 1;
     }
+    const T* vs = sv[NU & 1];
     for (int p = threadIdx.x; p < TX * TY; p += GRID_THREADS) {
         const int y = p / TX, x = p % TX;
         const int j = t.y0 + y, i = t.x0 + x;
-        if (j < n && i < n) A[(size_t)j * Lv.lda + i] = sv[cur][(H + y) * RW + (H + x)];
+        if (j < n && i < n) A[(size_t)j * Lv.lda + i] = vs[(H + y) * RW + (H + x)];
     }
 }
 
@@ -589,175 +626,374 @@ __device__ inline void chol_solve(int m, const T* Lc, const T* F, int sf, T* v, 
     }
 }
 
+// the same substitution on an n x n grid stored with a zero ring (stride P)
+template <typename T>
+__device__ inline void chol_solve_padded(int n, const T* Lc, const T* F, T* v, int P)
+{
+    const int m = n * n;
+    auto at = [&](int p) { return (p / n + 1) * P + (p % n + 1); };
+    for (int p = 0; p < m; ++p) {
+        T acc = F[at(p)];
+        for (int q = 0; q < p; ++q) acc -= Lc[p * m + q] * v[at(q)];
+        v[at(p)] = acc / Lc[p * m + p];
+    }
+    for (int p = m - 1; p >= 0; --p) {
+        T acc = v[at(p)];
+        for (int q = p + 1; q < m; ++q) acc -= Lc[q * m + p] * v[at(q)];
+        v[at(p)] = acc / Lc[p * m + p];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // persistent coarse kernel: one workgroup runs whole calls of the cycle on the
-// coarse levels of one instance, all levels resident in LDS.  Rows are spread
-// over waves (row j on wave j mod waves, column i on lane i), n <= 63.
+// coarse levels of one instance, every level resident in LDS.  Each level d has
+// three (n+2) x (n+2) arrays with a zero ring (two sweep buffers and F), so no
+// stencil needs a bounds check.  Bit d of `cur` says which sweep buffer holds
+// the current estimate of level d (sweeps ping-pong, nothing is copied).
+// Levels with n > wave_n spread rows over all waves and end each phase with a
+// workgroup barrier; levels with n <= wave_n are run by wave 0 alone, whose
+// phases need only wave-level ordering, while the other waves wait at the next
+// workgroup barrier.
 // ---------------------------------------------------------------------------
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// per-launch copy of everything the persistent kernel reads between phases:
+// LDS keeps it out of global memory, whose latency would otherwise be paid
+// once per phase (the phase fences forbid caching it in scalar registers)
+template <typename T>
+struct SubParams {
+    static constexpr int OPS = 512, CH = 81;
+    T s[MAXL][9];
+    T w[MAXL];
+    int n[MAXL];
+    int off[MAXL];
+    uint32_t ops[OPS];
+    int nops[2];
+    T chol[CH];
+};
+
+// One phase of the persistent kernel touches every interior point of one
+// level once.  Each phase is a small out-of-line function (the kernel runs
+// hundreds of phases per launch; inlining them all would not fit the
+// instruction cache).  Point mapping: a "single" level is spread over the 64
+// lanes of wave 0 (point p on lane p mod 64); otherwise row j goes to wave
+// j mod waves and column i to lane i.  Arrays have a zero ring, stride n + 2.
+// LDS pointers: the phase functions are not inlined, so their arguments carry
+// the LDS address space explicitly (generic pointers would compile to FLAT
+// accesses, which are slower than ds_read / ds_write)
+template <typename T> using lds = __attribute__((address_space(3))) T*;
+template <typename T> using clds = const __attribute__((address_space(3))) T*;
+template <typename T> __device__ __forceinline__ lds<T> to_lds(T* p) { return (lds<T>)(p); }
+template <typename T> __device__ __forceinline__ clds<T> to_lds(const T* p) { return (clds<T>)(p); }
+
+// Visit every interior point (j, i) of an n x n level: value(j, i) computes a
+// point's new value, store(j, i, v) writes it.  A lane works on U points at a
+// time and computes all of them (with clamped, always-valid indices) before it
+// stores any, so their loads and FP chains overlap.  value() must not read
+// what store() writes for another point.
+template <int U, typename T, typename VF, typename SF>
+__device__ __forceinline__ void for_points(int n, bool single, VF value, SF store)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    T val[U];
+    if (single) {
+        if (wv != 0) return;
+        const int m = n * n;
+        const uint32_t inv = (65536u + n - 1) / n;   // exact p / n for p < n^2, n <= 15
+        for (int p0 = lane; p0 < m; p0 += 64 * U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = min(p0 + 64 * u, m - 1);
+                const int j = (int)(((uint32_t)p * inv) >> 16);
+                val[u] = value(j, p - j * n);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = p0 + 64 * u;
+                if (p < m) {
+                    const int j = (int)(((uint32_t)p * inv) >> 16);
+                    store(j, p - j * n, val[u]);
+                }
+            }
+        }
+    } else {
+        if (lane >= n) return;
+        const int nw = blockDim.x >> 6;
+        for (int j0 = wv; j0 < n; j0 += nw * U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) val[u] = value(min(j0 + nw * u, n - 1), lane);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (j0 + nw * u < n) store(j0 + nw * u, lane, val[u]);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T sten_lds(const Sten<T>& s, clds<T> x, int st)
+{
+    T acc = T(0);
+    acc += s.c[0] * x[-st - 1];
+    acc += s.c[1] * x[-st];
+    acc += s.c[2] * x[-st + 1];
+    acc += s.c[3] * x[-1];
+    acc += s.c[4] * x[0];
+    acc += s.c[5] * x[1];
+    acc += s.c[6] * x[st - 1];
+    acc += s.c[7] * x[st];
+    acc += s.c[8] * x[st + 1];
+    return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ T fw_lds(clds<T> r, int st)
+{
+    const T q = T(0.25), h = T(0.5);
+    T acc = T(0);
+    acc += q * r[-st - 1];
+    acc += h * r[-st];
+    acc += q * r[-st + 1];
+    acc += h * r[-1];
+    acc += T(1) * r[0];
+    acc += h * r[1];
+    acc += q * r[st - 1];
+    acc += h * r[st];
+    acc += q * r[st + 1];
+    return acc;
+}
+
+template <typename T>
+__device__ __noinline__ void ph_sweep(clds<T> __restrict__ x, lds<T> __restrict__ y, clds<T> __restrict__ F,
+                                     clds<T> __restrict__ sc, T w, int n, bool single, bool zg)
+{
+    const int P = n + 2;
+    Sten<T> s;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) s.c[k] = sc[k];
+    auto st = [&](int j, int i, T v) { y[(j + 1) * P + (i + 1)] = v; };
+    if (zg) {
+        for_points<4, T>(n, single, [&](int j, int i) { return w * F[(j + 1) * P + (i + 1)]; }, st);
+    } else {
+        for_points<4, T>(n, single, [&](int j, int i) {
+            const int q = (j + 1) * P + (i + 1);
+            return x[q] + w * (F[q] - sten_lds(s, x + q, P));
+        }, st);
+    }
+}
+
+template <typename T>
+__device__ __noinline__ void ph_resid(clds<T> __restrict__ x, lds<T> __restrict__ r, clds<T> __restrict__ F,
+                                     clds<T> __restrict__ sc, int n, bool single)
+{
+    const int P = n + 2;
+    Sten<T> s;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) s.c[k] = sc[k];
+    for_points<4, T>(n, single, [&](int j, int i) {
+        const int q = (j + 1) * P + (i + 1);
+        return F[q] - sten_lds(s, x + q, P);
+    }, [&](int j, int i, T v) { r[(j + 1) * P + (i + 1)] = v; });
+}
+
+// F_c = P^T r on the coarse level (nc = (n - 1) / 2 points per side)
+template <typename T>
+__device__ __noinline__ void ph_restrict(clds<T> __restrict__ r, lds<T> __restrict__ Fc, int n, bool single_c)
+{
+    const int nc = (n - 1) / 2;
+    const int P = n + 2, Pc = nc + 2;
+    for_points<4, T>(nc, single_c, [&](int J, int I) { return fw_lds<T>(r + (2 * J + 2) * P + (2 * I + 2), P); },
+                     [&](int J, int I, T v) { Fc[(J + 1) * Pc + (I + 1)] = v; });
+}
+
+// x += P vc (each point reads only its own x)
+template <typename T>
+__device__ __noinline__ void ph_prolong(lds<T> __restrict__ x, clds<T> __restrict__ vc, int n, bool single)
+{
+    const int P = n + 2, Pc = (n - 1) / 2 + 2;
+    for_points<4, T>(n, single, [&](int j, int i) {
+        const T e = prolong_at<T>(j, i, [&](int J, int I) { return vc[(J + 1) * Pc + (I + 1)]; });
+        return x[(j + 1) * P + (i + 1)] + e;
+    }, [&](int j, int i, T v) { x[(j + 1) * P + (i + 1)] = v; });
+}
+
+template <typename T>
+__device__ __noinline__ void ph_zero(lds<T> __restrict__ x, int n, bool single)
+{
+    const int P = n + 2;
+    for_points<1, T>(n, single, [&](int, int) { return T(0); }, [&](int j, int i, T v) { x[(j + 1) * P + (i + 1)] = v; });
+}
+
 template <typename T>
 struct Sub {
     T* sm;
+    const SubParams<T>* pp;
     const InstDev* I;
-    int nu1, nu2;
+    int nu1, nu2, wave_n;
+    uint32_t cur;           // bit d: current estimate of level d is in the second buffer
+    bool pending = false;   // wave 0 has written LDS since the last workgroup barrier
 
-    __device__ T* v(int d) const { return sm + I->lds_off[d]; }
-    __device__ T* f(int d) const { return sm + I->lds_off[d] + I->lev[d].n * I->lev[d].n; }
-    __device__ T* tmp() const { return sm + I->lds_tmp; }
-
-    template <typename Fn>
-    __device__ void each(int n, Fn fn) const
+    __device__ __forceinline__ int n_(int d) const { return pp->n[d]; }
+    __device__ __forceinline__ T* buf(int d, int which) const
     {
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-        if (lane < n)
-            for (int j = wv; j < n; j += nw) fn(j, lane);
+        const int P = pp->n[d] + 2;
+        return sm + pp->off[d] + which * P * P;
+    }
+    __device__ __forceinline__ T* v(int d) const { return buf(d, (cur >> d) & 1); }
+    __device__ __forceinline__ T* o(int d) const { return buf(d, ((cur >> d) & 1) ^ 1); }
+    __device__ __forceinline__ T* f(int d) const { return buf(d, 2); }
+    __device__ __forceinline__ bool single(int d) const { return pp->n[d] <= wave_n; }
+    __device__ __forceinline__ void sten(int d, Sten<T>& s) const { s.load(pp->s[d]); }
+
+    __device__ __forceinline__ void sync(int d) const
+    {
+        if (single(d)) wave_sync();
+        else __syncthreads();
     }
 
-    __device__ T at(const T* x, int n, int j, int i) const { return inside(j, i, n) ? x[j * n + i] : T(0); }
-
-    __device__ T lapply(const Sten<T>& s, const T* x, int n, int j, int i) const
+    __device__ __forceinline__ void sweeps(int d, int nu, bool zg)
     {
-        T acc = T(0);
-        acc += s.c[0] * at(x, n, j - 1, i - 1);
-        acc += s.c[1] * at(x, n, j - 1, i);
-        acc += s.c[2] * at(x, n, j - 1, i + 1);
-        acc += s.c[3] * at(x, n, j, i - 1);
-        acc += s.c[4] * at(x, n, j, i);
-        acc += s.c[5] * at(x, n, j, i + 1);
-        acc += s.c[6] * at(x, n, j + 1, i - 1);
-        acc += s.c[7] * at(x, n, j + 1, i);
-        acc += s.c[8] * at(x, n, j + 1, i + 1);
-        return acc;
-    }
-
-    // nu sweeps on level d; v(d) holds the result
-    __device__ void sweeps(int d, int nu, bool zg) const
-    {
-        const int n = I->lev[d].n;
-        Sten<T> s;
-        s.load(P<T>::s(*I, d));
-        const T w = P<T>::w(*I, d);
-        T* cur = v(d);
-        T* oth = tmp();
-        const T* F = f(d);
+        const int n = n_(d);
+        const bool sg = single(d);
         for (int k = 0; k < nu; ++k) {
-            const bool z = zg && k == 0;
-            each(n, [&](int j, int i) {
-                const int q = j * n + i;
-                oth[q] = z ? w * F[q] : cur[q] + w * (F[q] - lapply(s, cur, n, j, i));
-            });
-            __syncthreads();
-            T* tt = cur; cur = oth; oth = tt;
-        }
-        if (cur != v(d)) {
-            T* vd = v(d);
-            each(n, [&](int j, int i) { vd[j * n + i] = cur[j * n + i]; });
-            __syncthreads();
+            ph_sweep<T>(to_lds<T>(v(d)), to_lds<T>(o(d)), to_lds<T>(f(d)), to_lds<T>(&pp->s[d][0]), pp->w[d], n, sg, zg && k == 0);
+            sync(d);
+            cur ^= 1u << d;
         }
         if (zg && nu == 0) {
-            T* vd = v(d);
-            each(n, [&](int j, int i) { vd[j * n + i] = T(0); });
-            __syncthreads();
+            ph_zero<T>(to_lds<T>(v(d)), n, sg);
+            sync(d);
         }
     }
 
-    __device__ void pre(int d, bool zg) const
+    __device__ __forceinline__ void pre(int d, bool zg)
     {
         sweeps(d, nu1, zg);
-        const int n = I->lev[d].n, nc = I->lev[d + 1].n;
-        Sten<T> s;
-        s.load(P<T>::s(*I, d));
-        const T* vd = v(d);
-        const T* F = f(d);
-        T* r = tmp();
-        each(n, [&](int j, int i) { r[j * n + i] = F[j * n + i] - lapply(s, vd, n, j, i); });
-        __syncthreads();
-        T* Fc = f(d + 1);
-        each(nc, [&](int J, int II) {
-            const int j = 2 * J + 1, i = 2 * II + 1;
-            const T q = T(0.25), h = T(0.5);
-            T acc = T(0);
-            acc += q * at(r, n, j - 1, i - 1);
-            acc += h * at(r, n, j - 1, i);
-            acc += q * at(r, n, j - 1, i + 1);
-            acc += h * at(r, n, j, i - 1);
-            acc += T(1) * at(r, n, j, i);
-            acc += h * at(r, n, j, i + 1);
-            acc += q * at(r, n, j + 1, i - 1);
-            acc += h * at(r, n, j + 1, i);
-            acc += q * at(r, n, j + 1, i + 1);
-            Fc[J * nc + II] = acc;
-        });
-        __syncthreads();
+        ph_resid<T>(to_lds<T>(v(d)), to_lds<T>(o(d)), to_lds<T>(f(d)), to_lds<T>(&pp->s[d][0]), n_(d), single(d));
+        sync(d);
+        ph_restrict<T>(to_lds<T>((const T*)o(d)), to_lds<T>(f(d + 1)), n_(d), single(d + 1));
+        sync(d + 1);
     }
 
-    __device__ void post(int d) const
+    __device__ __forceinline__ void post(int d)
     {
-        const int n = I->lev[d].n, nc = I->lev[d + 1].n;
-        T* vd = v(d);
-        const T* vc = v(d + 1);
-        each(n, [&](int j, int i) {
-            const T e = prolong_at<T>(j, i, [&](int J, int II) { return at(vc, nc, J, II); });
-            vd[j * n + i] = vd[j * n + i] + e;
-        });
-        __syncthreads();
+        ph_prolong<T>(to_lds<T>(v(d)), to_lds<T>((const T*)v(d + 1)), n_(d), single(d));
+        sync(d);
         sweeps(d, nu2, false);
     }
 
-    __device__ void solve(int d) const
+    __device__ __forceinline__ void solve(int d)
     {
-        if (threadIdx.x == 0) chol_solve<T>(I->nc2, P<T>::chol(*I), f(d), 1, v(d), 1);
-        __syncthreads();
+        const int n = n_(d);
+        const T* Lc = (n * n * n * n <= SubParams<T>::CH) ? pp->chol : P<T>::chol(*I);
+        if (threadIdx.x == 0) chol_solve_padded<T>(n, Lc, f(d), v(d), n + 2);
+        sync(d);
     }
 
-    __device__ void call(int k) const
+    // waves that skip a wave-0 operation still follow its buffer swaps
+    __device__ __forceinline__ void skip(int kind, int d, bool zg)
     {
-        const int kk = min(k, MAXL + 1);
-        const uint32_t* ops = I->ops + I->ops_beg[kk - 1];
-        const int nops = I->ops_len[kk - 1];
+        int k = 0;
+        if (kind == SOP_PRE) k = (zg && nu1 == 0) ? 0 : nu1;
+        else if (kind == SOP_POST) k = nu2;
+        if (k & 1) cur ^= 1u << d;
+    }
+
+    // the operations of one call (list `which` of the staged op lists)
+    __device__ void call(int which)
+    {
+        const int base = which ? pp->nops[0] : 0;
+        const int nops = pp->nops[which];
+        const bool w0 = (threadIdx.x >> 6) == 0;
         for (int o = 0; o < nops; ++o) {
-            const uint32_t op = ops[o];
+            const uint32_t op = pp->ops[base + o];
             const int kind = op & 15, d = (op >> 4) & 255;
             const bool zg = (op >> 12) & 1;
+            const bool sg = single(d);
+            if (sg && !w0) {
+                skip(kind, d, zg);
+                pending = true;
+                continue;
+            }
+            if (!sg && pending) {
+                __syncthreads();
+                pending = false;
+            }
             if (kind == SOP_PRE) pre(d, zg);
             else if (kind == SOP_POST) post(d);
             else solve(d);
+            if (sg || (kind == SOP_PRE && single(d + 1))) pending = true;
         }
     }
 };
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_subtree(SubArgs a)
+__global__ void __launch_bounds__(512) k_subtree(SubArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ SubParams<T> pp;
     const int inst = a.list[blockIdx.x];
     if (a.st[inst].done) return;
     const InstDev& I = a.inst[inst];
-    Sub<T> S{reinterpret_cast<T*>(smem_raw), &I, a.nu1, a.nu2};
-    const int d0 = a.depth;
+    T* sm = reinterpret_cast<T*>(smem_raw);
+    const int d0 = a.depth, L = I.L;
+
+    // stage parameters, op lists and a small coarsest factor in LDS
+    const int k1 = min(a.kappa, MAXL + 1), k2 = min(max(a.kappa - 1, 1), MAXL + 1);
+    const int n1 = I.ops_len[k1 - 1], n2 = (a.pair && a.kappa > 1) ? I.ops_len[k2 - 1] : 0;
+    for (int t = threadIdx.x; t < n1 + n2; t += blockDim.x)
+        pp.ops[t] = (t < n1) ? I.ops[I.ops_beg[k1 - 1] + t] : I.ops[I.ops_beg[k2 - 1] + (t - n1)];
+    for (int t = threadIdx.x; t < MAXL * 9; t += blockDim.x) {
+        const int d = t / 9;
+        pp.s[d][t % 9] = (d < L) ? P<T>::s(I, d)[t % 9] : T(0);
+    }
+    if (threadIdx.x < MAXL) {
+        const int d = threadIdx.x;
+        pp.w[d] = (d < L) ? P<T>::w(I, d) : T(0);
+        pp.n[d] = (d < L) ? I.lev[d].n : 0;
+        pp.off[d] = I.lds_off[d];
+    }
+    if (threadIdx.x == 0) {
+        pp.nops[0] = n1;
+        pp.nops[1] = n2;
+    }
+    if (I.nc2 * I.nc2 <= SubParams<T>::CH)
+        for (int t = threadIdx.x; t < I.nc2 * I.nc2; t += blockDim.x) pp.chol[t] = P<T>::chol(I)[t];
+    for (int p = threadIdx.x; p < I.sub_lds; p += blockDim.x) sm[p] = T(0);
+    __syncthreads();
+
+    Sub<T> S{sm, &pp, &I, a.nu1, a.nu2, a.wave_n, 0u};
     const LevelDev& Lv = I.lev[d0];
-    const int n = Lv.n;
+    const int n = pp.n[d0], Pst = n + 2;
     const T fs = (T)Lv.fscale;
     const T* Fg = (const T*)Lv.F;
     T* Ag = (T*)Lv.A;
     T* v0 = S.v(d0);
     T* f0 = S.f(d0);
     const bool zero = a.pair || a.zg;
-    S.each(n, [&](int j, int i) {
-        f0[j * n + i] = fs * Fg[(size_t)j * Lv.ldf + i];
-        v0[j * n + i] = zero ? T(0) : Ag[(size_t)j * Lv.lda + i];
-    });
+    for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
+        const int j = p / n, i = p - j * n;
+        f0[(j + 1) * Pst + (i + 1)] = fs * Fg[(size_t)j * Lv.ldf + i];
+        if (!zero) v0[(j + 1) * Pst + (i + 1)] = Ag[(size_t)j * Lv.lda + i];
+    }
     __syncthreads();
 
     if (a.fin == FIN_STOP) {
         __shared__ double red[16];
         __shared__ int stop;
         Sten<T> s;
-        s.load(P<T>::s(I, d0));
+        S.sten(d0, s);
         double nrm = 0.0;
-        S.each(n, [&](int j, int i) {
-            const double r = (double)(f0[j * n + i] - S.lapply(s, v0, n, j, i));
+        for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
+            const int j = p / n, i = p - j * n;
+            const int q = (j + 1) * Pst + (i + 1);
+            const double r = (double)(f0[q] - s.apply(&v0[q], Pst));
             nrm += r * r;
-        });
+        }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
@@ -772,10 +1008,14 @@ __global__ void __launch_bounds__(1024) k_subtree(SubArgs a)
         if (stop) return;
     }
 
-    S.call(a.kappa);
-    if (a.pair && a.kappa > 1) S.call(a.kappa - 1);
-
-    S.each(n, [&](int j, int i) { Ag[(size_t)j * Lv.lda + i] = v0[j * n + i]; });
+    S.call(0);
+    if (n2 > 0) S.call(1);
+    __syncthreads();
+    const T* vr = S.v(d0);
+    for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
+        const int j = p / n, i = p - j * n;
+        Ag[(size_t)j * Lv.lda + i] = vr[(j + 1) * Pst + (i + 1)];
+    }
 }
 
 // coarsest direct solve on global memory (paper-structured mode); the coarsest
@@ -802,8 +1042,8 @@ __global__ void __launch_bounds__(64) k_coarsest(SubArgs a)
 // ---------------------------------------------------------------------------
 // driver kernels on the fine level (FP64 vectors)
 // ---------------------------------------------------------------------------
-template <bool F32>
-__global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a, int kind)
+template <bool F32, int kind>
+__global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
 {
     Tile t;
     if (!get_tile(a, 0, true, t)) return;
@@ -819,6 +1059,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a, int kind)
     const double scale = st.scale, scale_used = st.scale_used;
     const double alpha = st.alpha, beta = st.beta;
     const bool first = st.iters == 0;
+#pragma unroll
     for (int k = ty; k < TY; k += GRID_THREADS / 64) {
         const int j = t.y0 + k, i = t.x0 + tx;
         if (j >= n || i >= n) continue;
@@ -899,7 +1140,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a, int kind)
             break;
         }
     }
-    if (a.fin != FIN_NONE) reduce_finalize(a, t, acc0, acc1);
+    if (a.fin != FIN_NONE) reduce_partial(a, t, acc0, acc1);
 }
 
 // ---------------------------------------------------------------------------
@@ -931,22 +1172,64 @@ static hipError_t launch_post(const StageArgs& a, int nb, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T>
+static hipError_t launch_unfused(GridKernel k, const StageArgs& a, int nb, hipStream_t s)
+{
+    const dim3 g(nb), b(GRID_THREADS);
+    switch (k) {
+    case GK_SWEEP: k_unfused<T, GK_SWEEP><<<g, b, 0, s>>>(a); break;
+    case GK_RESID: k_unfused<T, GK_RESID><<<g, b, 0, s>>>(a); break;
+    case GK_RESTRICT: k_unfused<T, GK_RESTRICT><<<g, b, 0, s>>>(a); break;
+    case GK_ZERO: k_unfused<T, GK_ZERO><<<g, b, 0, s>>>(a); break;
+    case GK_PROLONG: k_unfused<T, GK_PROLONG><<<g, b, 0, s>>>(a); break;
+    case GK_ADD: k_unfused<T, GK_ADD><<<g, b, 0, s>>>(a); break;
+    case GK_COPY: k_unfused<T, GK_COPY><<<g, b, 0, s>>>(a); break;
+    case GK_NORM: k_unfused<T, GK_NORM><<<g, b, 0, s>>>(a); break;
+    case GK_ZERO_SELF: k_unfused<T, GK_ZERO_SELF><<<g, b, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <bool F32>
+static hipError_t launch_driver(GridKernel k, const StageArgs& a, int nb, hipStream_t s)
+{
+    const dim3 g(nb), b(GRID_THREADS);
+    switch (k) {
+    case GK_SSF: k_driver<F32, GK_SSF><<<g, b, 0, s>>>(a); break;
+    case GK_IR_RESID: k_driver<F32, GK_IR_RESID><<<g, b, 0, s>>>(a); break;
+    case GK_IR_UPDATE: k_driver<F32, GK_IR_UPDATE><<<g, b, 0, s>>>(a); break;
+    case GK_PCG_INIT: k_driver<F32, GK_PCG_INIT><<<g, b, 0, s>>>(a); break;
+    case GK_PCG_PRECIN: k_driver<F32, GK_PCG_PRECIN><<<g, b, 0, s>>>(a); break;
+    case GK_PCG_RZ: k_driver<F32, GK_PCG_RZ><<<g, b, 0, s>>>(a); break;
+    case GK_PCG_P: k_driver<F32, GK_PCG_P><<<g, b, 0, s>>>(a); break;
+    case GK_PCG_AP: k_driver<F32, GK_PCG_AP><<<g, b, 0, s>>>(a); break;
+    case GK_PCG_UPD: k_driver<F32, GK_PCG_UPD><<<g, b, 0, s>>>(a); break;
+    case GK_APPLY: k_driver<F32, GK_APPLY><<<g, b, 0, s>>>(a); break;
+    case GK_GRAD: k_driver<F32, GK_GRAD><<<g, b, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nb, hipStream_t s)
 {
     if (nb <= 0) return hipSuccess;
+    hipError_t e;
     switch (k) {
-    case GK_PRE: return f32 ? launch_pre<float>(a, nb, s) : launch_pre<double>(a, nb, s);
-    case GK_POST: return f32 ? launch_post<float>(a, nb, s) : launch_post<double>(a, nb, s);
+    case GK_PRE: e = f32 ? launch_pre<float>(a, nb, s) : launch_pre<double>(a, nb, s); break;
+    case GK_POST: e = f32 ? launch_post<float>(a, nb, s) : launch_post<double>(a, nb, s); break;
     case GK_SWEEP: case GK_RESID: case GK_RESTRICT: case GK_ZERO: case GK_PROLONG: case GK_ADD: case GK_COPY:
     case GK_NORM: case GK_ZERO_SELF:
-        if (f32) k_unfused<float><<<nb, GRID_THREADS, 0, s>>>(a, (int)k);
-        else k_unfused<double><<<nb, GRID_THREADS, 0, s>>>(a, (int)k);
-        return hipGetLastError();
+        e = f32 ? launch_unfused<float>(k, a, nb, s) : launch_unfused<double>(k, a, nb, s);
+        break;
     default:
-        if (f32) k_driver<true><<<nb, GRID_THREADS, 0, s>>>(a, (int)k);
-        else k_driver<false><<<nb, GRID_THREADS, 0, s>>>(a, (int)k);
-        return hipGetLastError();
+        e = f32 ? launch_driver<true>(k, a, nb, s) : launch_driver<false>(k, a, nb, s);
+        break;
     }
+    if (e != hipSuccess || a.fin == FIN_NONE) return e;
+    k_finalize<<<a.count, GRID_THREADS, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t launch_subtree(bool f32, const SubArgs& a, int32_t threads, int32_t lds_bytes, hipStream_t s)

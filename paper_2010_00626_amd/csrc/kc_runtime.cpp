@@ -260,7 +260,7 @@ struct HostInst {
     double s[MAXL][9];
     std::vector<uint32_t> ops;
     int ops_beg[KMAX] = {}, ops_len[KMAX] = {};
-    int lds_off[MAXL] = {}, lds_tmp = 0, lds_elems = 0;
+    int lds_off[MAXL] = {}, lds_elems = 0;
 };
 
 // op list of one call at depth d with counter k (Algorithm 3), levels in LDS
@@ -366,6 +366,7 @@ Launch sub(kc_hier* h, bool f32, int depth, int kappa, bool pair, int nu1, int n
     L.ba.nu2 = nu2;
     L.ba.zg = zg ? 1 : 0;
     L.ba.fin = fin;
+    L.ba.wave_n = h->ex.coarse_wave_n;
     L.ba.hist = h->d_hist;
     L.threads = h->ex.coarse_threads;
     L.lds = h->sub_lds;
@@ -512,18 +513,16 @@ kc_status plan_exec(kc_hier* h)
         int off = 0;
         for (int d = 0; d < MAXL; ++d) hi.lds_off[d] = 0;
         if (cut < L) {
-            for (int d = cut; d < L; ++d) {
+            for (int d = cut; d < L; ++d) {   // two sweep buffers and F, each (n+2)^2 with a zero ring
                 hi.lds_off[d] = off;
-                off += 2 * hi.il.n[d] * hi.il.n[d];
+                off += 3 * (hi.il.n[d] + 2) * (hi.il.n[d] + 2);
             }
-            hi.lds_tmp = off;
-            off += hi.il.n[cut] * hi.il.n[cut];
         }
         hi.lds_elems = off;
         h->sub_lds = std::max(h->sub_lds, (int)(off * T));
     }
     if (h->sub_lds > 0 && h->d_tiles) {
-        const int maxl = max_lds_bytes();
+        const int maxl = max_lds_bytes() - 8192;   // the kernel's static parameter block stays below 8 KB
         if (h->sub_lds > maxl)
             return fail(KC_ERR_ARG, "coarse cutover needs " + std::to_string(h->sub_lds) + " B of LDS, device allows " +
                                         std::to_string(maxl));
@@ -589,7 +588,6 @@ void fill_inst_static(kc_hier* h)
             Lv.fscale = 1.0;
             I.lds_off[d] = hi.lds_off[d];
         }
-        I.lds_tmp = hi.lds_tmp;
         for (int k = 0; k < KMAX; ++k) {
             I.ops_beg[k] = hi.ops_beg[k];
             I.ops_len[k] = hi.ops_len[k];
@@ -877,9 +875,10 @@ void kc_exec_default(kc_exec* e)
     std::memset(e, 0, sizeof *e);
     e->mode = 0;
     e->use_graph = 1;
-    e->coarse_cutover = 63;
+    e->coarse_cutover = 31;
     e->coarse_threads = 512;
     e->poll_every = 0;
+    e->coarse_wave_n = 15;
 }
 
 const char* kc_status_string(kc_status s)
@@ -932,9 +931,11 @@ static kc_status validate_exec(const kc_exec* e)
 {
     if (e->mode != 0 && e->mode != 1) return fail(KC_ERR_ARG, "exec.mode must be 0 or 1");
     if (e->coarse_cutover < 7 || e->coarse_cutover > 63) return fail(KC_ERR_ARG, "coarse_cutover must be in 7..63");
-    if (e->coarse_threads != 256 && e->coarse_threads != 512 && e->coarse_threads != 1024)
-        return fail(KC_ERR_ARG, "coarse_threads must be 256, 512 or 1024");
+    if (e->coarse_threads != 256 && e->coarse_threads != 512)
+        return fail(KC_ERR_ARG, "coarse_threads must be 256 or 512");
     if (e->poll_every < 0) return fail(KC_ERR_ARG, "poll_every must be >= 0");
+    if (e->coarse_wave_n < 0 || e->coarse_wave_n > 15) return fail(KC_ERR_ARG, "coarse_wave_n must be in 0..15");
+    if (e->coarse_threads * 8 < 64 * e->coarse_cutover) return fail(KC_ERR_ARG, "coarse_threads too small for the cutover");
     return KC_OK;
 }
 
@@ -1277,6 +1278,65 @@ kc_status kc_grad_params(kc_hier* h, const double* const* d_lam, const int64_t* 
     return leave(h);
 }
 
+kc_status kc_time_stage(kc_hier* h, int32_t which, const kc_cycle_params* c, int32_t reps, double* avg_ms, double* bytes)
+{
+    if (!h || !avg_ms || !bytes || reps < 1) return fail(KC_ERR_ARG, "bad argument");
+    kc_status s = prepare_call(h, c);
+    if (s != KC_OK) return s;
+    if ((s = enter(h)) != KC_OK) return s;
+    if ((s = upload_inst(h)) != KC_OK) return s;
+    if ((s = upload_state(h, 0.0, 0)) != KC_OK) return s;   // every instance active, no reduction decisions
+    const bool f32 = h->prec == KC_F32_CYCLE;
+    const double T = f32 ? 4.0 : 8.0;
+    Launch L{};
+    double b = 0.0;
+    const bool is_pre = which == 0 || (which >= 100 && which < 100 + MAXL);
+    const bool is_post = which == 1 || (which >= 200 && which < 200 + MAXL);
+    if (is_pre || is_post) {
+        const int d = which <= 1 ? 0 : which % 100;
+        if (d >= h->max_cut) return fail(KC_ERR_STATE, "no grid-wide stage at that depth (persistent kernel there)");
+        L = grid(h, is_pre ? GK_PRE : GK_POST, f32, tt_cut(d), d);
+        L.sa.nu = is_pre ? c->nu1 : c->nu2;
+        for (int i = 0; i < h->count; ++i) {
+            if (h->hi[i].cut <= d) continue;
+            const double nf = h->hi[i].il.n[d], ncs = h->hi[i].il.n[d + 1];
+            // pre: read v and f, write v and f_c; post: read v, f and v_c, write v
+            b += (3.0 * nf * nf + ncs * ncs) * T;
+        }
+    } else if (which == 2 || (which >= 300 && which < 300 + MAXL)) {
+        int d = -1;
+        if (which >= 300) d = which - 300;
+        for (int k = 1; k < MAXL && d < 0; ++k)
+            if (nlist(h, lt_sub(k)) > 0) d = k;
+        if (d < 0 || nlist(h, lt_sub(d)) == 0) return fail(KC_ERR_STATE, "no persistent launch at that depth");
+        L = sub(h, f32, d, clamp_kappa(h, c->kappa), true, c->nu1, c->nu2, false, FIN_NONE);
+        for (int idx : h->lists[lt_sub(d)]) {
+            const double n = h->hi[idx].il.n[d];
+            b += 2.0 * n * n * T;   // reads f, writes v of the top level; coarser levels stay in LDS
+        }
+    } else if (which == 3) {
+        if (!f32) return fail(KC_ERR_STATE, "the refinement residual pass exists on FP32 hierarchies");
+        L = grid(h, GK_IR_RESID, true, tt_all0(), 0);
+        for (int i = 0; i < h->count; ++i) {
+            const double n0 = h->hi[i].il.n[0];
+            b += n0 * n0 * (8.0 + 8.0 + 4.0);   // read u, f; write the FP32 right-hand side
+        }
+    } else {
+        return fail(KC_ERR_ARG, "unknown stage");
+    }
+    std::vector<Launch> one(1, L);
+    HIPCHK(run(h, one));   // warm
+    HIPCHK(hipEventRecord(h->t0, h->stream));
+    for (int r = 0; r < reps; ++r) HIPCHK(run(h, one));
+    HIPCHK(hipEventRecord(h->t1, h->stream));
+    HIPCHK(hipEventSynchronize(h->t1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->t0, h->t1));
+    *avg_ms = (double)ms / reps;
+    *bytes = b;
+    return leave(h);
+}
+
 kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
 {
     if (!h || !out || cap == 0) return fail(KC_ERR_ARG, "null argument");
@@ -1287,6 +1347,7 @@ kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
     js += ", \"graph\": " + std::to_string(h->ex.use_graph);
     js += ", \"coarse_cutover\": " + std::to_string(h->ex.coarse_cutover);
     js += ", \"coarse_threads\": " + std::to_string(h->ex.coarse_threads);
+    js += ", \"coarse_wave_n\": " + std::to_string(h->ex.coarse_wave_n);
     js += ", \"subtree_lds_bytes\": " + std::to_string(h->sub_lds);
     js += ", \"workspace_bytes\": " + std::to_string(h->lay.total);
     js += ", \"driver\": \"" + h->last_driver + "\"";

@@ -45,7 +45,8 @@ class CycleParams(C.Structure):
 
 class Exec(C.Structure):
     _fields_ = [("mode", C.c_int32), ("use_graph", C.c_int32), ("coarse_cutover", C.c_int32),
-                ("coarse_threads", C.c_int32), ("poll_every", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("coarse_threads", C.c_int32), ("poll_every", C.c_int32), ("coarse_wave_n", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 _lib = None
@@ -76,13 +77,14 @@ def lib():
         L.kc_level_stencils.argtypes = [P(Problem), i32, P(i32), P(dbl)]
         L.kc_schedule_counts.argtypes = [P(Problem), i32, P(Exec), P(CycleParams), P(i64), P(i64), P(i64)]
         L.kc_stats.argtypes = [vp, C.c_char_p, sz]
+        L.kc_time_stage.argtypes = [vp, i32, P(CycleParams), i32, P(dbl), P(dbl)]
         L.kc_status_string.argtypes = [i32]
         L.kc_status_string.restype = C.c_char_p
         L.kc_last_error.argtypes = []
         L.kc_last_error.restype = C.c_char_p
         for name in ("kc_workspace_bytes", "kc_create", "kc_destroy", "kc_set_exec", "kc_cycle", "kc_solve",
                      "kc_pcg", "kc_apply_A", "kc_grad_params", "kc_level_stencils", "kc_schedule_counts",
-                     "kc_stats"):
+                     "kc_stats", "kc_time_stage"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -94,8 +96,8 @@ def _check(status: int, allow_positive: bool = False) -> int:
     return status
 
 
-def exec_options(mode: int | str = 0, use_graph: bool = True, coarse_cutover: int = 63,
-                 coarse_threads: int = 512, poll_every: int = 0) -> Exec:
+def exec_options(mode: int | str = 0, use_graph: bool = True, coarse_cutover: int = 31,
+                 coarse_threads: int = 512, poll_every: int = 0, coarse_wave_n: int = 15) -> Exec:
     e = Exec()
     lib().kc_exec_default(C.byref(e))
     e.mode = {"fused": 0, "paper": 1}.get(mode, mode) if isinstance(mode, str) else int(mode)
@@ -103,6 +105,7 @@ def exec_options(mode: int | str = 0, use_graph: bool = True, coarse_cutover: in
     e.coarse_cutover = int(coarse_cutover)
     e.coarse_threads = int(coarse_threads)
     e.poll_every = int(poll_every)
+    e.coarse_wave_n = int(coarse_wave_n)
     return e
 
 
@@ -252,6 +255,13 @@ class Hierarchy:
         e = exec_options(**kw)
         _check(lib().kc_set_exec(self._h, C.byref(e)))
         self._e = e
+
+    def time_stage(self, which: int, kappa=3, nu1=2, nu2=2, omega=0.8, reps=50):
+        """Average ms of one launch of a schedule stage and its algorithmic bytes."""
+        c = self._params(kappa, nu1, nu2, omega)
+        ms, b = C.c_double(), C.c_double()
+        _check(lib().kc_time_stage(self._h, int(which), C.byref(c), int(reps), C.byref(ms), C.byref(b)))
+        return ms.value, b.value
 
     def stats(self) -> dict:
         buf = C.create_string_buffer(1 << 16)
