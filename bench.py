@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--cpu-cycles", type=int, default=40, help="oracle cycles timed for the CPU baseline")
     ap.add_argument("--kappa", type=int, default=0, help="force the headline kappa (0 = fastest of the sweep)")
     ap.add_argument("--precision", default="", help="force the headline precision (f64 or f32)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the execution-option autotuner")
+    ap.add_argument("--extras", default="c4,c3,c5,hbm",
+                    help="extra measurements: c4 (batched uneven), c3 (PCG 4095^2), c5 (adjoint), hbm (8191^2 kernel)")
     return ap.parse_args()
 
 
@@ -49,7 +52,7 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (no multi-GPU path is built)"}))
         sys.exit(2)
     import torch
-    from paper_2010_00626_amd import inputs, kcycle, model
+    from paper_2010_00626_amd import autotune, inputs, kcycle, model
 
     dev = torch.device("cuda:0")
     w = inputs.config2()
@@ -67,11 +70,21 @@ def main():
         u.zero_()
         return H[prec].solve(u, f, kappa=kappa, **kw)
 
+    tuned = {}
+
+    def tune(prec, kappa):
+        if args.no_tune:
+            return None
+        r = autotune.tune(H[prec], u, f, kappa, w.nu1, w.nu2, w.omega, driver="solve", iters=10)
+        tuned[(prec, kappa)] = r["exec"]
+        return r["exec"]
+
     kappas = [1, 2, 3, 4, 6, kcycle.KAPPA_W]
     per = {}
     if not args.no_sweep:
         for prec in ("f64", "f32"):
             for k in kappas:
+                cfg = tune(prec, k)
                 solve(prec, k)                       # warm-up (graph capture)
                 times, its = [], None
                 for _ in range(args.sweep_reps):
@@ -91,6 +104,7 @@ def main():
                     "grid_launches_per_cycle": stats["grid_launches_per_iteration"],
                     "persistent_launches_per_cycle": stats["subtree_launches_per_iteration"],
                     "persistent_stages_per_cycle": stats["subtree_stages_per_iteration"],
+                    "exec": cfg,
                 }
                 print(f"[bench] {prec} kappa={key}: {its[0]} cycles, {med * 1e3:.2f} ms", file=sys.stderr, flush=True)
 
@@ -108,6 +122,8 @@ def main():
     else:
         best_k, best_p = 3, (args.precision or "f32")
 
+    if (best_p, best_k) in tuned:
+        H[best_p].set_exec(**tuned[(best_p, best_k)])
     for _ in range(args.warmup):
         solve(best_p, best_k)
     torch.cuda.synchronize()
@@ -152,6 +168,19 @@ def main():
                       "measured_best_kappa": "W" if best_k == kcycle.KAPPA_W else str(best_k),
                       "rel_errors": {k: round(v, 4) for k, v in fitted.rel_errors.items()}}
 
+    extras = {}
+    ex = set(x for x in args.extras.split(",") if x)
+    del H
+    torch.cuda.empty_cache()
+    if "hbm" in ex:
+        extras["fine_kernel_8191"] = hbm_kernel(kcycle, torch)
+    if "c4" in ex:
+        extras["c4_batched"] = c4_batched(inputs, kcycle, autotune, torch)
+    if "c3" in ex:
+        extras["c3_pcg"] = c3_pcg(inputs, kcycle, torch)
+    if "c5" in ex:
+        extras["c5_adjoint"] = c5_adjoint(inputs, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inst, w, best_k, per, args.cpu_cycles)
@@ -166,9 +195,136 @@ def main():
                    "kappa": "W" if best_k == kcycle.KAPPA_W else best_k, "precision": best_p,
                    "cycles": its[0], "unknowns": N},
         "roofline": roofline, "kernels": kernels, "per_kappa": per, "model": model_info,
-        "cpu_baseline": cpu,
+        "extras": extras, "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def hbm_kernel(kcycle, torch):
+    """Fine-level fused kernels on an 8191^2 FP64 grid (537 MB per array, far
+    beyond the 256 MB Infinity Cache): achieved HBM bandwidth of one launch."""
+    n = 8191
+    Hh = kcycle.Hierarchy([(n, math.pi / 4, 1e-4)], "f64")
+    fh = torch.zeros((n, n), dtype=torch.float64, device="cuda").uniform_(-1, 1)
+    uh = torch.zeros_like(fh)
+    Hh.solve(uh, fh, kappa=1, tol=0.0, maxit=1)      # binds the arrays
+    res = {}
+    for name, which in (("pre", 0), ("post", 1)):
+        ms, b = Hh.time_stage(which, kappa=1, reps=20)
+        res[name] = {"ms": round(ms, 4), "bytes": b, "GB_s": round(b / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_8TBs": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    Hh.close()
+    del Hh, fh, uh
+    torch.cuda.empty_cache()
+    return res
+
+
+def c4_batched(inputs, kcycle, autotune, torch):
+    """64 uneven instances (255^2..2047^2), kappa=3 stand-alone to 1e-8:
+    one batched FP32-cycle/FP64-refinement solve against a loop of plain
+    per-instance FP64 solves."""
+    wl = inputs.config4()
+    probs = [(i.n, i.theta, i.eps) for i in wl.instances]
+    fs = [torch.from_numpy(i.f).to("cuda") for i in wl.instances]
+    us = [torch.zeros_like(x) for x in fs]
+    N = wl.unknowns
+    kw = dict(kappa=3, nu1=wl.nu1, nu2=wl.nu2, omega=wl.omega, tol=wl.tol, maxit=4000)
+    Hb = kcycle.Hierarchy(probs, "f32")
+    cfg = autotune.tune(Hb, us, fs, 3, wl.nu1, wl.nu2, wl.omega, driver="solve", iters=6)["exec"]
+    for x in us:
+        x.zero_()
+    Hb.solve(us, fs, **kw)
+    times = []
+    for _ in range(3):
+        for x in us:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, rr, st = Hb.solve(us, fs, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    assert all(x == 0 for x in st), st
+    tb = statistics.median(times)
+    grid_b = Hb.stats()["grid_launches_per_iteration"]
+    Hb.close()
+    del Hb
+    # plain per-instance FP64 loop
+    Hs = [kcycle.Hierarchy([p], "f64") for p in probs]
+    for h_, x, fx in zip(Hs, us, fs):
+        x.zero_()
+        h_.solve(x, fx, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its64 = []
+    for h_, x, fx in zip(Hs, us, fs):
+        x.zero_()
+        i64, _, s64 = h_.solve(x, fx, **kw)
+        its64.append(i64[0])
+        assert s64 == [0]
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    for h_ in Hs:
+        h_.close()
+    sizes = sorted(set(p[0] for p in probs))
+    return {"instances": len(probs), "sizes": {str(s): sum(1 for p in probs if p[0] == s) for s in sizes},
+            "unknowns": N, "kappa": 3, "batched_f32_ms": round(tb * 1e3, 2),
+            "batched_unknowns_per_s": N / tb, "batched_max_cycles": max(it), "batched_exec": cfg,
+            "batched_grid_launches_per_cycle": grid_b,
+            "per_instance_f64_loop_ms": round(tl * 1e3, 2), "per_instance_unknowns_per_s": N / tl,
+            "per_instance_max_cycles": max(its64), "speedup_batched_f32_vs_loop_f64": round(tl / tb, 3)}
+
+
+def c3_pcg(inputs, kcycle, torch):
+    """4095^2, theta=3pi/8, eps=1e-5: CG preconditioned by one kappa-cycle
+    (nu=1+1), FP32 cycles with FP64 CG vectors, to 1e-8, per kappa."""
+    wl = inputs.config3()
+    inst = wl.instances[0]
+    n = inst.n
+    f = torch.from_numpy(inst.f).to("cuda")
+    u = torch.zeros_like(f)
+    Hc = kcycle.Hierarchy([(n, inst.theta, inst.eps)], "f32")
+    out = {}
+    for k in wl.kappas:
+        u.zero_()
+        Hc.pcg(u, f, kappa=k, nu1=1, nu2=1, omega=wl.omega, tol=wl.tol, maxit=1000)
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, rr, st = Hc.pcg(u, f, kappa=k, nu1=1, nu2=1, omega=wl.omega, tol=wl.tol, maxit=1000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[str(k)] = {"iterations": it[0], "relres": rr[0], "status": st[0], "ms": round(dt * 1e3, 2),
+                       "ms_per_iteration": round(dt * 1e3 / max(it[0], 1), 4), "unknowns_per_s": n * n / dt}
+    Hc.close()
+    return out
+
+
+def c5_adjoint(inputs, torch):
+    """16 x 1023^2 instances, kappa=3 PCG forward and adjoint to 1e-8:
+    loss 1/2 ||u - u*||^2, u* for (theta + 0.1, 2 eps); forward + backward."""
+    from paper_2010_00626_amd import autograd as ag
+    wl = inputs.config5()
+    th = torch.tensor([i.theta for i in wl.instances], dtype=torch.float64)
+    ep = torch.tensor([i.eps for i in wl.instances], dtype=torch.float64)
+    f = torch.from_numpy(np.stack([i.f for i in wl.instances])).to("cuda")
+    cfg = ag.SolveConfig(kappa=3, nu1=1, nu2=1, tol=wl.tol, tol_adjoint=wl.tol)
+    with torch.no_grad():
+        target = ag.solve(f, th + 0.1, 2 * ep, cfg)
+    times = []
+    for _ in range(2):
+        tht = th.clone().requires_grad_(True)
+        ept = ep.clone().requires_grad_(True)
+        fr = f.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = 0.5 * ((ag.solve(fr, tht, ept, cfg) - target) ** 2).sum()
+        L.backward()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    dt = min(times)
+    N = wl.unknowns
+    return {"instances": len(wl.instances), "unknowns": N, "forward_backward_ms": round(dt * 1e3, 2),
+            "unknowns_per_s": N / dt, "solves": 3, "loss": float(L.detach())}
 
 
 def cpu_baseline(inst, w, kappa, per, cycles):

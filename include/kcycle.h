@@ -181,6 +181,13 @@ kc_status kc_schedule_counts(const kc_problem* probs, int32_t count, const kc_ex
 kc_status kc_time_stage(kc_hier* h, int32_t which, const kc_cycle_params* c, int32_t reps, double* avg_ms,
                         double* bytes);
 
+/* instrumentation for the run-time model (Section 3.2): one warm-up cycle,
+ * then `reps` kappa-cycles on (v, f) back to back (graph replays, no stop
+ * test), timed with hip events on the hierarchy's stream; v is overwritten.
+ * FP64 hierarchies.  Synchronises. */
+kc_status kc_time_cycles(kc_hier* h, double* const* d_v, const int64_t* ldv, const double* const* d_f,
+                         const int64_t* ldf, const kc_cycle_params* c, int32_t reps, double* ms_per_cycle);
+
 /* JSON summary: sizes, launches per cycle, last solve's timings */
 kc_status kc_stats(const kc_hier* h, char* out, size_t cap);
 

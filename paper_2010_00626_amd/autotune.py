@@ -1,0 +1,100 @@
+"""Execution-option autotuner for the kappa-cycle library.
+
+The library's results do not depend on its execution options (every kernel
+variant rounds each operation the same way), so the options can be chosen by
+measurement alone: for a hierarchy, a cycle (kappa, nu1, nu2) and a driver,
+each candidate (coarse cutover, persistent-kernel threads, single-wave level
+size) runs a fixed number of iterations and the fastest is kept.  Results are
+cached per (device, instance sizes, precision, driver, kappa, nu1, nu2) in
+memory and, when KC_AUTOTUNE_CACHE names a file, in that JSON file.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import kcycle
+
+DEFAULT_CANDIDATES = tuple(
+    dict(coarse_cutover=c, coarse_threads=t, coarse_wave_n=w)
+    for c in (15, 31, 63) for t in (256, 512) for w in (7, 15)
+    if not (c == 63 and t == 256)       # 63 rows need at least 8 waves
+)
+
+_memory: dict = {}
+
+
+def _device_name() -> str:
+    import torch
+    return torch.cuda.get_device_name(torch.cuda.current_device())
+
+
+def _key(H, driver, kappa, nu1, nu2) -> str:
+    return json.dumps([_device_name(), H.sizes, H.precision, driver, int(kappa), int(nu1), int(nu2)])
+
+
+def _load_file() -> dict:
+    path = os.environ.get("KC_AUTOTUNE_CACHE")
+    if not path or not os.path.exists(path):
+        return {}
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_file(key: str, value: dict) -> None:
+    path = os.environ.get("KC_AUTOTUNE_CACHE")
+    if not path:
+        return
+    data = _load_file()
+    data[key] = value
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1)
+    os.replace(tmp, path)
+
+
+def tune(H: "kcycle.Hierarchy", u, f, kappa: int, nu1: int = 2, nu2: int = 2, omega: float = 0.8,
+         driver: str = "solve", iters: int = 12, candidates=DEFAULT_CANDIDATES, force: bool = False) -> dict:
+    """Pick the fastest execution options for `driver` ("solve" or "pcg") on
+    hierarchy H, apply them to H and return {"exec": ..., "ms_per_iter": ...,
+    "trials": [...]}; u is used as scratch (zeroed before every trial)."""
+    key = _key(H, driver, kappa, nu1, nu2)
+    if not force:
+        hit = _memory.get(key) or _load_file().get(key)
+        if hit:
+            H.set_exec(**hit["exec"])
+            _memory[key] = hit
+            return hit
+    run = H.solve if driver == "solve" else H.pcg
+    us = u if isinstance(u, (list, tuple)) else [u]
+    trials = []
+    for cand in candidates:
+        opts = dict(cand, poll_every=iters + 2)
+        try:
+            H.set_exec(**opts)
+        except kcycle.KCycleError:
+            continue                      # e.g. the levels do not fit the LDS
+        for x in us:
+            x.zero_()
+        run(u, f, kappa=kappa, nu1=nu1, nu2=nu2, omega=omega, tol=0.0, maxit=2)   # capture
+        for x in us:
+            x.zero_()
+        t0 = time.perf_counter()
+        run(u, f, kappa=kappa, nu1=nu1, nu2=nu2, omega=omega, tol=0.0, maxit=iters)
+        wall = time.perf_counter() - t0
+        dev_ms = H.stats()["last_ms"]
+        trials.append({"exec": cand, "ms_per_iter": dev_ms / (iters + 1), "wall_ms": wall * 1e3})
+    if not trials:
+        raise RuntimeError("no execution candidate is valid for this hierarchy")
+    best = min(trials, key=lambda r: r["ms_per_iter"])
+    H.set_exec(**best["exec"])
+    for x in us:
+        x.zero_()
+    result = {"exec": best["exec"], "ms_per_iter": best["ms_per_iter"], "trials": trials}
+    _memory[key] = result
+    _store_file(key, result)
+    return result

@@ -783,7 +783,9 @@ kc_status drive(kc_hier* h, int drv, const kc_cycle_params& c, int maxit, int32_
             if (s2.done) continue;
             all = false;
             // remaining cycles predicted from the observed reduction rate
-            if (prev_rel[i] > 0.0 && s2.relres > 0.0 && s2.iters > prev_it[i]) {
+            if (!(s2.tol > 0.0)) {
+                need = std::max(need, (double)(s2.maxit - s2.iters + 1));
+            } else if (prev_rel[i] > 0.0 && s2.relres > 0.0 && s2.iters > prev_it[i]) {
                 const double rate = std::pow(s2.relres / prev_rel[i], 1.0 / (s2.iters - prev_it[i]));
                 if (rate > 0.0 && rate < 1.0) {
                     const double rem = std::log(s2.tol / s2.relres) / std::log(rate);
@@ -1334,6 +1336,30 @@ kc_status kc_time_stage(kc_hier* h, int32_t which, const kc_cycle_params* c, int
     HIPCHK(hipEventElapsedTime(&ms, h->t0, h->t1));
     *avg_ms = (double)ms / reps;
     *bytes = b;
+    return leave(h);
+}
+
+kc_status kc_time_cycles(kc_hier* h, double* const* d_v, const int64_t* ldv, const double* const* d_f,
+                         const int64_t* ldf, const kc_cycle_params* c, int32_t reps, double* ms_per_cycle)
+{
+    if (!h || !ms_per_cycle || reps < 1) return fail(KC_ERR_ARG, "bad argument");
+    if (h->prec != KC_F64) return fail(KC_ERR_STATE, "kc_time_cycles needs an FP64 hierarchy");
+    kc_status s;
+    if ((s = check_ptrs(h, d_v, ldv, "v")) != KC_OK || (s = check_ptrs(h, d_f, ldf, "f")) != KC_OK) return s;
+    if ((s = prepare_call(h, c)) != KC_OK) return s;
+    if ((s = enter(h)) != KC_OK) return s;
+    bind_level0_user(h, d_v, ldv, d_f, ldf);
+    if ((s = upload_inst(h)) != KC_OK) return s;
+    if ((s = upload_state(h, 0.0, 0)) != KC_OK) return s;
+    if ((s = launch_iteration(h, DRV_CYCLE, *c, 1)) != KC_OK) return s;   // capture + warm
+    HIPCHK(hipEventRecord(h->t0, h->stream));
+    if ((s = launch_iteration(h, DRV_CYCLE, *c, reps)) != KC_OK) return s;
+    HIPCHK(hipEventRecord(h->t1, h->stream));
+    HIPCHK(hipEventSynchronize(h->t1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->t0, h->t1));
+    *ms_per_cycle = (double)ms / reps;
+    record_counts(h, DRV_CYCLE, *c);
     return leave(h);
 }
 

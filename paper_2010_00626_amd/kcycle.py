@@ -78,13 +78,14 @@ def lib():
         L.kc_schedule_counts.argtypes = [P(Problem), i32, P(Exec), P(CycleParams), P(i64), P(i64), P(i64)]
         L.kc_stats.argtypes = [vp, C.c_char_p, sz]
         L.kc_time_stage.argtypes = [vp, i32, P(CycleParams), i32, P(dbl), P(dbl)]
+        L.kc_time_cycles.argtypes = arr + [P(CycleParams), i32, P(dbl)]
         L.kc_status_string.argtypes = [i32]
         L.kc_status_string.restype = C.c_char_p
         L.kc_last_error.argtypes = []
         L.kc_last_error.restype = C.c_char_p
         for name in ("kc_workspace_bytes", "kc_create", "kc_destroy", "kc_set_exec", "kc_cycle", "kc_solve",
                      "kc_pcg", "kc_apply_A", "kc_grad_params", "kc_level_stencils", "kc_schedule_counts",
-                     "kc_stats", "kc_time_stage"):
+                     "kc_stats", "kc_time_stage", "kc_time_cycles"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -262,6 +263,15 @@ class Hierarchy:
         ms, b = C.c_double(), C.c_double()
         _check(lib().kc_time_stage(self._h, int(which), C.byref(c), int(reps), C.byref(ms), C.byref(b)))
         return ms.value, b.value
+
+    def time_cycles(self, v, f, kappa=1, nu1=2, nu2=2, omega=0.8, reps=10):
+        """Milliseconds per kappa-cycle over `reps` back-to-back cycles (FP64)."""
+        pv, lv = self._arrays(v, "v")
+        pf, lf = self._arrays(f, "f")
+        c = self._params(kappa, nu1, nu2, omega)
+        ms = C.c_double()
+        _check(lib().kc_time_cycles(self._h, pv, lv, pf, lf, C.byref(c), int(reps), C.byref(ms)))
+        return ms.value
 
     def stats(self) -> dict:
         buf = C.create_string_buffer(1 << 16)
