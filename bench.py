@@ -228,14 +228,16 @@ def c4_batched(inputs, kcycle, autotune, torch):
     fs = [torch.from_numpy(i.f).to("cuda") for i in wl.instances]
     us = [torch.zeros_like(x) for x in fs]
     N = wl.unknowns
-    kw = dict(kappa=3, nu1=wl.nu1, nu2=wl.nu2, omega=wl.omega, tol=wl.tol, maxit=4000)
+    # two instances have grid-aligned anisotropy (theta within 0.03 rad of an axis, eps ~ 1e-4): the
+    # pointwise smoother leaves a contraction factor near 0.997 there, so they need ~5000 cycles
+    kw = dict(kappa=3, nu1=wl.nu1, nu2=wl.nu2, omega=wl.omega, tol=wl.tol, maxit=12000)
     Hb = kcycle.Hierarchy(probs, "f32")
     cfg = autotune.tune(Hb, us, fs, 3, wl.nu1, wl.nu2, wl.omega, driver="solve", iters=6)["exec"]
     for x in us:
         x.zero_()
-    Hb.solve(us, fs, **kw)
+    Hb.solve(us, fs, **dict(kw, maxit=3))
     times = []
-    for _ in range(3):
+    for _ in range(2):
         for x in us:
             x.zero_()
         torch.cuda.synchronize()
@@ -252,7 +254,7 @@ def c4_batched(inputs, kcycle, autotune, torch):
     Hs = [kcycle.Hierarchy([p], "f64") for p in probs]
     for h_, x, fx in zip(Hs, us, fs):
         x.zero_()
-        h_.solve(x, fx, **kw)
+        h_.solve(x, fx, **dict(kw, maxit=3))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     its64 = []
@@ -268,10 +270,12 @@ def c4_batched(inputs, kcycle, autotune, torch):
     sizes = sorted(set(p[0] for p in probs))
     return {"instances": len(probs), "sizes": {str(s): sum(1 for p in probs if p[0] == s) for s in sizes},
             "unknowns": N, "kappa": 3, "batched_f32_ms": round(tb * 1e3, 2),
-            "batched_unknowns_per_s": N / tb, "batched_max_cycles": max(it), "batched_exec": cfg,
+            "batched_unknowns_per_s": N / tb, "batched_max_cycles": max(it),
+            "batched_median_cycles": statistics.median(it), "batched_max_relres": max(rr), "batched_exec": cfg,
             "batched_grid_launches_per_cycle": grid_b,
             "per_instance_f64_loop_ms": round(tl * 1e3, 2), "per_instance_unknowns_per_s": N / tl,
-            "per_instance_max_cycles": max(its64), "speedup_batched_f32_vs_loop_f64": round(tl / tb, 3)}
+            "per_instance_max_cycles": max(its64), "per_instance_median_cycles": statistics.median(its64),
+            "speedup_batched_f32_vs_loop_f64": round(tl / tb, 3)}
 
 
 def c3_pcg(inputs, kcycle, torch):

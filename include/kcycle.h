@@ -95,7 +95,9 @@ typedef struct {
     int32_t coarse_threads; /* threads of the persistent kernel (256 or 512; default 512) */
     int32_t poll_every;     /* cycles launched between host polls of the stop flags (default 0 = adaptive) */
     int32_t coarse_wave_n;  /* persistent-kernel levels with n <= this run on one wave (0..15; default 15) */
-    int32_t reserved[2];
+    int32_t small_tile_n;   /* fused grid kernels on levels whose largest n <= this use 16 x 16 tiles instead of
+                               64 x 32 (0 = never; 0..4095; default 0); results do not depend on it */
+    int32_t reserved;
 } kc_exec;
 
 typedef struct kc_hier kc_hier;
@@ -140,6 +142,15 @@ kc_status kc_solve(kc_hier* h, double* const* d_u, const int64_t* ldu, const dou
 kc_status kc_pcg(kc_hier* h, double* const* d_u, const int64_t* ldu, const double* const* d_f,
                  const int64_t* ldf, const kc_cycle_params* c, double tol, int32_t maxit,
                  int32_t* iters, double* relres, int32_t* status);
+
+/* relative-residual history of instance `instance` in the last kc_solve or
+ * kc_pcg on h: out[k] = ||r_k|| / ||f|| after k cycles (stand-alone; out[0]
+ * is the initial guess) or k CG iterations (recurrence residual, out[0] = 1).
+ * *count receives the number of entries recorded, min(iters + 1, 8192): the
+ * first 8192 are kept, longer runs are not limited by this.  Copies
+ * min(cap, *count) entries to the host buffer out (may be NULL when cap is
+ * 0).  KC_ERR_STATE before any solve.  Synchronises. */
+kc_status kc_residual_history(kc_hier* h, int32_t instance, double* out, int32_t cap, int32_t* count);
 
 /* y = A x on every instance's fine level (FP64), asynchronous */
 kc_status kc_apply_A(kc_hier* h, double* const* d_y, const int64_t* ldy, const double* const* d_x,

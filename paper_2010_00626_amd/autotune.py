@@ -3,8 +3,10 @@
 The library's results do not depend on its execution options (every kernel
 variant rounds each operation the same way), so the options can be chosen by
 measurement alone: for a hierarchy, a cycle (kappa, nu1, nu2) and a driver,
-each candidate (coarse cutover, persistent-kernel threads, single-wave level
-size) runs a fixed number of iterations and the fastest is kept.  Results are
+each candidate runs a fixed number of iterations and the fastest is kept.  The
+search is staged: first the persistent-kernel options (coarse cutover,
+threads, single-wave level size), then, with the best of those fixed, the
+largest level size that the fused grid kernels run in 16 x 16 tiles.  Results are
 cached per (device, instance sizes, precision, driver, kappa, nu1, nu2) in
 memory and, when KC_AUTOTUNE_CACHE names a file, in that JSON file.
 """
@@ -16,11 +18,13 @@ import time
 
 from . import kcycle
 
-DEFAULT_CANDIDATES = tuple(
-    dict(coarse_cutover=c, coarse_threads=t, coarse_wave_n=w)
+COARSE_CANDIDATES = tuple(
+    dict(coarse_cutover=c, coarse_threads=t, coarse_wave_n=w, small_tile_n=0)
     for c in (15, 31, 63) for t in (256, 512) for w in (7, 15)
     if not (c == 63 and t == 256)       # 63 rows need at least 8 waves
 )
+TILE_CANDIDATES = tuple(dict(small_tile_n=s) for s in (127, 255, 511, 1023))
+DEFAULT_STAGES = (COARSE_CANDIDATES, TILE_CANDIDATES)
 
 _memory: dict = {}
 
@@ -58,7 +62,7 @@ def _store_file(key: str, value: dict) -> None:
 
 
 def tune(H: "kcycle.Hierarchy", u, f, kappa: int, nu1: int = 2, nu2: int = 2, omega: float = 0.8,
-         driver: str = "solve", iters: int = 12, candidates=DEFAULT_CANDIDATES, force: bool = False) -> dict:
+         driver: str = "solve", iters: int = 12, stages=DEFAULT_STAGES, force: bool = False) -> dict:
     """Pick the fastest execution options for `driver` ("solve" or "pcg") on
     hierarchy H, apply them to H and return {"exec": ..., "ms_per_iter": ...,
     "trials": [...]}; u is used as scratch (zeroed before every trial)."""
@@ -72,25 +76,30 @@ def tune(H: "kcycle.Hierarchy", u, f, kappa: int, nu1: int = 2, nu2: int = 2, om
     run = H.solve if driver == "solve" else H.pcg
     us = u if isinstance(u, (list, tuple)) else [u]
     trials = []
-    for cand in candidates:
-        opts = dict(cand, poll_every=iters + 2)
-        try:
-            H.set_exec(**opts)
-        except kcycle.KCycleError:
-            continue                      # e.g. the levels do not fit the LDS
-        for x in us:
-            x.zero_()
-        run(u, f, kappa=kappa, nu1=nu1, nu2=nu2, omega=omega, tol=0.0, maxit=2)   # capture
-        for x in us:
-            x.zero_()
-        t0 = time.perf_counter()
-        run(u, f, kappa=kappa, nu1=nu1, nu2=nu2, omega=omega, tol=0.0, maxit=iters)
-        wall = time.perf_counter() - t0
-        dev_ms = H.stats()["last_ms"]
-        trials.append({"exec": cand, "ms_per_iter": dev_ms / (iters + 1), "wall_ms": wall * 1e3})
-    if not trials:
-        raise RuntimeError("no execution candidate is valid for this hierarchy")
-    best = min(trials, key=lambda r: r["ms_per_iter"])
+    best = None
+    for stage in stages:
+        base = dict(best["exec"]) if best else {}
+        for part in stage:
+            cand = dict(base, **part)
+            if best and cand == best["exec"]:
+                continue
+            try:
+                H.set_exec(**dict(cand, poll_every=iters + 2))
+            except kcycle.KCycleError:
+                continue                      # e.g. the levels do not fit the LDS
+            for x in us:
+                x.zero_()
+            run(u, f, kappa=kappa, nu1=nu1, nu2=nu2, omega=omega, tol=0.0, maxit=2)   # capture
+            for x in us:
+                x.zero_()
+            t0 = time.perf_counter()
+            run(u, f, kappa=kappa, nu1=nu1, nu2=nu2, omega=omega, tol=0.0, maxit=iters)
+            wall = time.perf_counter() - t0
+            dev_ms = H.stats()["last_ms"]
+            trials.append({"exec": cand, "ms_per_iter": dev_ms / (iters + 1), "wall_ms": wall * 1e3})
+        if not trials:
+            raise RuntimeError("no execution candidate is valid for this hierarchy")
+        best = min(trials, key=lambda r: r["ms_per_iter"])
     H.set_exec(**best["exec"])
     for x in us:
         x.zero_()

@@ -10,6 +10,7 @@ namespace kc {
 constexpr int MAXL = 16;          // levels per instance
 constexpr int TX = 64;            // grid-kernel tile width  (one wave64 row)
 constexpr int TY = 32;            // grid-kernel tile height
+constexpr int TS = 16;            // small-level tile side of the fused kernels
 constexpr int GRID_THREADS = 256; // threads of the grid-wide kernels
 constexpr int HIST_CAP = 8192;    // relres history entries kept per instance
 
@@ -117,7 +118,7 @@ struct StageArgs {
     int32_t fin;              // Finalize kind of this launch's reduction
     int32_t nu;               // sweeps for fused pre/post kernels
     int32_t src, dst;         // buffer selectors for unfused kernels (0 = A, 1 = B)
-    int32_t flags;
+    int32_t flags;            // bit 0: fused kernels use 16 x 16 tiles (table built for that shape)
 };
 
 // arguments of a persistent coarse-kernel launch

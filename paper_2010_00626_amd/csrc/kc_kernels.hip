@@ -138,6 +138,7 @@ __device__ inline int find_inst(const int32_t* off, int count, int b)
 }
 
 // returns false when the instance is finished (the whole block leaves together)
+template <int BX = TX, int BY = TY>
 __device__ inline bool get_tile(const StageArgs& a, int depth_for_size, bool fine_user, Tile& t)
 {
     const int b = blockIdx.x;
@@ -147,9 +148,9 @@ __device__ inline bool get_tile(const StageArgs& a, int depth_for_size, bool fin
     t.nblk = a.tile_off[i + 1] - a.tile_off[i];
     const InstDev& I = a.inst[i];
     const int n = fine_user ? I.n0 : I.lev[depth_for_size].n;
-    const int tx = (n + TX - 1) / TX;
-    t.x0 = (t.blk % tx) * TX;
-    t.y0 = (t.blk / tx) * TY;
+    const int tx = (n + BX - 1) / BX;
+    t.x0 = (t.blk % tx) * BX;
+    t.y0 = (t.blk / tx) * BY;
     return a.st[i].done == 0;
 }
 
@@ -410,7 +411,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a)
 // fused pre-smoothing: nu sweeps + residual + full weighting in one pass
 // (input region = tile + halo nu+1, swept in LDS); optional input norm
 // ---------------------------------------------------------------------------
-template <typename T, int NU>
+template <typename T, int NU, int TX, int TY>
 __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
 {
     constexpr int H = NU + 1;
@@ -418,7 +419,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
     __shared__ T sv[2][RH * RW];
     __shared__ T sf[RH * RW];
     Tile t;
-    if (!get_tile(a, a.depth, false, t)) return;
+    if (!get_tile<TX, TY>(a, a.depth, false, t)) return;
     const InstDev& I = a.inst[t.inst];
     const int d = a.depth;
     const LevelDev& Lv = I.lev[d];
@@ -517,7 +518,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
 // ---------------------------------------------------------------------------
 // fused post-smoothing: prolong-add + nu sweeps (input region = tile + halo nu)
 // ---------------------------------------------------------------------------
-template <typename T, int NU>
+template <typename T, int NU, int TX, int TY>
 __global__ void __launch_bounds__(GRID_THREADS) k_post(StageArgs a)
 {
     constexpr int H = NU;
@@ -527,7 +528,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_post(StageArgs a)
     __shared__ T sf[RH * RW];
     __shared__ T sc[CH * CW];
     Tile t;
-    if (!get_tile(a, a.depth, false, t)) return;
+    if (!get_tile<TX, TY>(a, a.depth, false, t)) return;
     const InstDev& I = a.inst[t.inst];
     const int d = a.depth;
     const LevelDev& Lv = I.lev[d];
@@ -1146,14 +1147,29 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// tile shape of a grid launch: flags bit 0 set = 16 x 16 tiles (small levels), else 64 x 32
+template <typename T, int NU>
+static void pre_shape(const StageArgs& a, int nb, hipStream_t s)
+{
+    if (a.flags & 1) k_pre<T, NU, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a);
+    else k_pre<T, NU, TX, TY><<<nb, GRID_THREADS, 0, s>>>(a);
+}
+
+template <typename T, int NU>
+static void post_shape(const StageArgs& a, int nb, hipStream_t s)
+{
+    if (a.flags & 1) k_post<T, NU, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a);
+    else k_post<T, NU, TX, TY><<<nb, GRID_THREADS, 0, s>>>(a);
+}
+
 template <typename T>
 static hipError_t launch_pre(const StageArgs& a, int nb, hipStream_t s)
 {
     switch (a.nu) {
-    case 0: k_pre<T, 0><<<nb, GRID_THREADS, 0, s>>>(a); break;
-    case 1: k_pre<T, 1><<<nb, GRID_THREADS, 0, s>>>(a); break;
-    case 2: k_pre<T, 2><<<nb, GRID_THREADS, 0, s>>>(a); break;
-    case 3: k_pre<T, 3><<<nb, GRID_THREADS, 0, s>>>(a); break;
+    case 0: pre_shape<T, 0>(a, nb, s); break;
+    case 1: pre_shape<T, 1>(a, nb, s); break;
+    case 2: pre_shape<T, 2>(a, nb, s); break;
+    case 3: pre_shape<T, 3>(a, nb, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1163,10 +1179,10 @@ template <typename T>
 static hipError_t launch_post(const StageArgs& a, int nb, hipStream_t s)
 {
     switch (a.nu) {
-    case 0: k_post<T, 0><<<nb, GRID_THREADS, 0, s>>>(a); break;
-    case 1: k_post<T, 1><<<nb, GRID_THREADS, 0, s>>>(a); break;
-    case 2: k_post<T, 2><<<nb, GRID_THREADS, 0, s>>>(a); break;
-    case 3: k_post<T, 3><<<nb, GRID_THREADS, 0, s>>>(a); break;
+    case 0: post_shape<T, 0>(a, nb, s); break;
+    case 1: post_shape<T, 1>(a, nb, s); break;
+    case 2: post_shape<T, 2>(a, nb, s); break;
+    case 3: post_shape<T, 3>(a, nb, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -182,6 +182,7 @@ struct Layout {
 };
 
 int tiles_of(int n) { return ((n + TX - 1) / TX) * ((n + TY - 1) / TY); }
+int tiles_small(int n) { return ((n + TS - 1) / TS) * ((n + TS - 1) / TS); }
 
 kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Layout& lay)
 {
@@ -205,7 +206,7 @@ kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Lay
         int L;
         kc_status st = check_problem(probs[i], L);
         if (st != KC_OK) return st;
-        tiles0 += tiles_of(probs[i].n);
+        tiles0 += std::max(tiles_of(probs[i].n), tiles_small(probs[i].n));   // either tile shape at depth 0
     }
     lay.total_tiles0 = tiles0;
     lay.partial = take(sizeof(double) * 2 * (size_t)tiles0);
@@ -303,6 +304,7 @@ struct kc_hier {
     std::vector<std::vector<int32_t>> tiles;   // host copies of the tile tables
     std::vector<std::vector<int32_t>> lists;   // host copies of the instance lists
     int max_cut = 0, max_L = 0;
+    int small[MAXL] = {};                      // fused grid kernels at depth d use 16 x 16 tiles
     int sub_lds = 0;
     std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> graphs;
     double omega_set = -1.0;
@@ -310,6 +312,7 @@ struct kc_hier {
     int64_t last_grid = 0, last_sub = 0, last_sub_stages = 0, last_cycles = 0, last_launched = 0;
     double last_ms = 0.0;
     std::string last_driver;
+    std::vector<int32_t> last_iters;           // per instance, last kc_solve / kc_pcg
 };
 
 namespace {
@@ -350,6 +353,14 @@ Launch grid(kc_hier* h, GridKernel gk, bool f32, int table, int depth)
     return L;
 }
 
+// fused PRE/POST launch at depth d, in the tile shape chosen for that depth
+Launch fused_grid(kc_hier* h, GridKernel gk, bool f32, int d)
+{
+    Launch L = grid(h, gk, f32, tt_cut(d), d);
+    L.sa.flags = h->small[d];
+    return L;
+}
+
 Launch sub(kc_hier* h, bool f32, int depth, int kappa, bool pair, int nu1, int nu2, bool zg, int fin)
 {
     Launch L{};
@@ -378,7 +389,7 @@ Launch sub(kc_hier* h, bool f32, int depth, int kappa, bool pair, int nu1, int n
 void gen_fused(kc_hier* h, int d, int k, bool zg, int fin, const kc_cycle_params& c, bool f32,
                std::vector<Launch>& out)
 {
-    Launch pre = grid(h, GK_PRE, f32, tt_cut(d), d);
+    Launch pre = fused_grid(h, GK_PRE, f32, d);
     pre.sa.zg = zg ? 1 : 0;
     pre.sa.fin = fin;
     pre.sa.nu = c.nu1;
@@ -388,7 +399,7 @@ void gen_fused(kc_hier* h, int d, int k, bool zg, int fin, const kc_cycle_params
         gen_fused(h, d + 1, k, true, FIN_NONE, c, f32, out);
         if (k > 1) gen_fused(h, d + 1, k - 1, false, FIN_NONE, c, f32, out);
     }
-    Launch post = grid(h, GK_POST, f32, tt_cut(d), d);
+    Launch post = fused_grid(h, GK_POST, f32, d);
     post.sa.nu = c.nu2;
     out.push_back(post);
 }
@@ -531,12 +542,19 @@ kc_status plan_exec(kc_hier* h)
     const int cnt = h->count;
     h->tiles.assign(1 + 2 * MAXL, std::vector<int32_t>(cnt + 1, 0));
     h->lists.assign(2 * MAXL, std::vector<int32_t>());
+    for (int d = 0; d < MAXL; ++d) {
+        int maxn = 0;
+        for (int i = 0; i < cnt; ++i)
+            if (d < h->hi[i].il.L && h->hi[i].cut > d) maxn = std::max(maxn, h->hi[i].il.n[d]);
+        h->small[d] = (maxn > 0 && maxn <= h->ex.small_tile_n) ? 1 : 0;
+    }
     for (int i = 0; i < cnt; ++i) {
         const HostInst& hi = h->hi[i];
         const int L = hi.il.L;
         h->tiles[tt_all0()][i + 1] = tiles_of(hi.il.n[0]);
         for (int d = 0; d < MAXL; ++d) {
-            h->tiles[tt_cut(d)][i + 1] = (d < L && hi.cut > d) ? tiles_of(hi.il.n[d]) : 0;
+            const int tc = h->small[d] ? tiles_small(hi.il.n[d]) : tiles_of(hi.il.n[d]);
+            h->tiles[tt_cut(d)][i + 1] = (d < L && hi.cut > d) ? tc : 0;
             h->tiles[tt_lvl(d)][i + 1] = (d < L - 1) ? tiles_of(hi.il.n[d]) : 0;
             if (hi.cut == d && d < L) h->lists[lt_sub(d)].push_back(i);
             if (L - 1 == d) h->lists[lt_coarse(d)].push_back(i);
@@ -937,6 +955,7 @@ static kc_status validate_exec(const kc_exec* e)
         return fail(KC_ERR_ARG, "coarse_threads must be 256 or 512");
     if (e->poll_every < 0) return fail(KC_ERR_ARG, "poll_every must be >= 0");
     if (e->coarse_wave_n < 0 || e->coarse_wave_n > 15) return fail(KC_ERR_ARG, "coarse_wave_n must be in 0..15");
+    if (e->small_tile_n < 0 || e->small_tile_n > 4095) return fail(KC_ERR_ARG, "small_tile_n must be in 0..4095");
     if (e->coarse_threads * 8 < 64 * e->coarse_cutover) return fail(KC_ERR_ARG, "coarse_threads too small for the cutover");
     return KC_OK;
 }
@@ -1179,7 +1198,6 @@ kc_status kc_solve(kc_hier* h, double* const* d_u, const int64_t* ldu, const dou
     kc_status s;
     if ((s = check_ptrs(h, d_u, ldu, "u")) != KC_OK || (s = check_ptrs(h, d_f, ldf, "f")) != KC_OK) return s;
     if (maxit < 0 || !(tol >= 0.0)) return fail(KC_ERR_ARG, "maxit must be >= 0 and tol >= 0");
-    if (maxit >= HIST_CAP) return fail(KC_ERR_ARG, "maxit must be below the history capacity (8192)");
     if ((s = prepare_call(h, c)) != KC_OK) return s;
     if ((s = enter(h)) != KC_OK) return s;
     const bool f32 = h->prec == KC_F32_CYCLE;
@@ -1200,6 +1218,8 @@ kc_status kc_solve(kc_hier* h, double* const* d_u, const int64_t* ldu, const dou
     s = drive(h, drv, *c, maxit, iters, relres, status);
     record_counts(h, drv, *c);
     h->last_driver = f32 ? "solve_ir_f32" : "solve_f64";
+    if (s >= 0) h->last_iters.assign(iters, iters + h->count);
+    else h->last_iters.clear();
     kc_status s2 = leave(h);
     return s2 != KC_OK ? s2 : s;
 }
@@ -1211,7 +1231,6 @@ kc_status kc_pcg(kc_hier* h, double* const* d_u, const int64_t* ldu, const doubl
     kc_status s;
     if ((s = check_ptrs(h, d_u, ldu, "u")) != KC_OK || (s = check_ptrs(h, d_f, ldf, "f")) != KC_OK) return s;
     if (maxit < 0 || !(tol >= 0.0)) return fail(KC_ERR_ARG, "maxit must be >= 0 and tol >= 0");
-    if (maxit >= HIST_CAP) return fail(KC_ERR_ARG, "maxit must be below the history capacity (8192)");
     if ((s = prepare_call(h, c)) != KC_OK) return s;
     if ((s = enter(h)) != KC_OK) return s;
     const bool f32 = h->prec == KC_F32_CYCLE;
@@ -1227,8 +1246,27 @@ kc_status kc_pcg(kc_hier* h, double* const* d_u, const int64_t* ldu, const doubl
     s = drive(h, DRV_PCG, *c, maxit, iters, relres, status);
     record_counts(h, DRV_PCG, *c);
     h->last_driver = f32 ? "pcg_f32_precond" : "pcg_f64";
+    if (s >= 0) h->last_iters.assign(iters, iters + h->count);
+    else h->last_iters.clear();
     kc_status s2 = leave(h);
     return s2 != KC_OK ? s2 : s;
+}
+
+kc_status kc_residual_history(kc_hier* h, int32_t instance, double* out, int32_t cap, int32_t* count)
+{
+    if (!h || !count) return fail(KC_ERR_ARG, "null argument");
+    if (instance < 0 || instance >= h->count) return fail(KC_ERR_ARG, "instance out of range");
+    if (cap < 0 || (cap > 0 && !out)) return fail(KC_ERR_ARG, "out must hold cap entries");
+    if ((int)h->last_iters.size() != h->count) return fail(KC_ERR_STATE, "no kc_solve or kc_pcg has run on this hierarchy");
+    const int n = std::min(h->last_iters[instance] + 1, HIST_CAP);
+    *count = n;
+    const int m = std::min(cap, n);
+    if (m > 0) {
+        HIPCHK(hipMemcpyAsync(out, h->d_hist + (size_t)instance * HIST_CAP, sizeof(double) * m, hipMemcpyDeviceToHost,
+                              h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    return KC_OK;
 }
 
 kc_status kc_apply_A(kc_hier* h, double* const* d_y, const int64_t* ldy, const double* const* d_x, const int64_t* ldx)
@@ -1297,7 +1335,7 @@ kc_status kc_time_stage(kc_hier* h, int32_t which, const kc_cycle_params* c, int
     if (is_pre || is_post) {
         const int d = which <= 1 ? 0 : which % 100;
         if (d >= h->max_cut) return fail(KC_ERR_STATE, "no grid-wide stage at that depth (persistent kernel there)");
-        L = grid(h, is_pre ? GK_PRE : GK_POST, f32, tt_cut(d), d);
+        L = fused_grid(h, is_pre ? GK_PRE : GK_POST, f32, d);
         L.sa.nu = is_pre ? c->nu1 : c->nu2;
         for (int i = 0; i < h->count; ++i) {
             if (h->hi[i].cut <= d) continue;
@@ -1374,6 +1412,7 @@ kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
     js += ", \"coarse_cutover\": " + std::to_string(h->ex.coarse_cutover);
     js += ", \"coarse_threads\": " + std::to_string(h->ex.coarse_threads);
     js += ", \"coarse_wave_n\": " + std::to_string(h->ex.coarse_wave_n);
+    js += ", \"small_tile_n\": " + std::to_string(h->ex.small_tile_n);
     js += ", \"subtree_lds_bytes\": " + std::to_string(h->sub_lds);
     js += ", \"workspace_bytes\": " + std::to_string(h->lay.total);
     js += ", \"driver\": \"" + h->last_driver + "\"";

@@ -46,7 +46,7 @@ class CycleParams(C.Structure):
 class Exec(C.Structure):
     _fields_ = [("mode", C.c_int32), ("use_graph", C.c_int32), ("coarse_cutover", C.c_int32),
                 ("coarse_threads", C.c_int32), ("poll_every", C.c_int32), ("coarse_wave_n", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("small_tile_n", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -73,6 +73,7 @@ def lib():
         L.kc_solve.argtypes = arr + [P(CycleParams), dbl, i32, P(i32), P(dbl), P(i32)]
         L.kc_pcg.argtypes = arr + [P(CycleParams), dbl, i32, P(i32), P(dbl), P(i32)]
         L.kc_apply_A.argtypes = arr
+        L.kc_residual_history.argtypes = [vp, i32, P(dbl), i32, P(i32)]
         L.kc_grad_params.argtypes = arr + [P(dbl), P(dbl)]
         L.kc_level_stencils.argtypes = [P(Problem), i32, P(i32), P(dbl)]
         L.kc_schedule_counts.argtypes = [P(Problem), i32, P(Exec), P(CycleParams), P(i64), P(i64), P(i64)]
@@ -84,7 +85,7 @@ def lib():
         L.kc_last_error.argtypes = []
         L.kc_last_error.restype = C.c_char_p
         for name in ("kc_workspace_bytes", "kc_create", "kc_destroy", "kc_set_exec", "kc_cycle", "kc_solve",
-                     "kc_pcg", "kc_apply_A", "kc_grad_params", "kc_level_stencils", "kc_schedule_counts",
+                     "kc_pcg", "kc_apply_A", "kc_residual_history", "kc_grad_params", "kc_level_stencils", "kc_schedule_counts",
                      "kc_stats", "kc_time_stage", "kc_time_cycles"):
             getattr(L, name).restype = i32
         _lib = L
@@ -98,7 +99,8 @@ def _check(status: int, allow_positive: bool = False) -> int:
 
 
 def exec_options(mode: int | str = 0, use_graph: bool = True, coarse_cutover: int = 31,
-                 coarse_threads: int = 512, poll_every: int = 0, coarse_wave_n: int = 15) -> Exec:
+                 coarse_threads: int = 512, poll_every: int = 0, coarse_wave_n: int = 15,
+                 small_tile_n: int = 0) -> Exec:
     e = Exec()
     lib().kc_exec_default(C.byref(e))
     e.mode = {"fused": 0, "paper": 1}.get(mode, mode) if isinstance(mode, str) else int(mode)
@@ -107,6 +109,7 @@ def exec_options(mode: int | str = 0, use_graph: bool = True, coarse_cutover: in
     e.coarse_threads = int(coarse_threads)
     e.poll_every = int(poll_every)
     e.coarse_wave_n = int(coarse_wave_n)
+    e.small_tile_n = int(small_tile_n)
     return e
 
 
@@ -238,6 +241,15 @@ class Hierarchy:
     def pcg(self, u, f, kappa=1, nu1=1, nu2=1, omega=0.8, tol=1e-8, maxit=500):
         """CG preconditioned by one kappa-cycle per iteration; returns (iters, relres, status)."""
         return self._solver(lib().kc_pcg, u, f, kappa, nu1, nu2, omega, tol, maxit)
+
+    def residual_history(self, instance: int = 0) -> list:
+        """Relative residuals of the last solve / pcg of one instance, entry k
+        after k cycles or CG iterations (the first 8192 are kept)."""
+        n = C.c_int32()
+        _check(lib().kc_residual_history(self._h, int(instance), None, 0, C.byref(n)))
+        buf = (C.c_double * max(n.value, 1))()
+        _check(lib().kc_residual_history(self._h, int(instance), buf, n.value, C.byref(n)))
+        return list(buf[: n.value])
 
     def apply_A(self, y, x):
         py, ly = self._arrays(y, "y")

@@ -98,6 +98,27 @@ def test_one_cycle_bitwise(n, nc, kappa, nu1, nu2, mode, graph):
     assert np.array_equal(host(v), ref2)
 
 
+@pytest.mark.parametrize("n,kappa,small", [(255, 3, 4095), (1023, 2, 255), (1023, 2 ** 31 - 1, 511)])
+def test_small_tile_option(n, kappa, small):
+    """16 x 16 tiles on the small levels give the same bits as the oracle,
+    for one cycle and for a solve whose stopping norm runs in those tiles."""
+    banner(f"small tiles n={n} kappa={kappa} small_tile_n={small}")
+    rng = np.random.default_rng(n + 7)
+    th, ep = 2.1, 3e-4
+    v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
+    H = K().Hierarchy([(n, th, ep)], exec=dict(small_tile_n=small))
+    v = dev(v0)
+    H.cycle(v, dev(f), kappa=kappa, nu1=2, nu2=2)
+    Ho = O.Hierarchy(n, th, ep)
+    assert np.array_equal(host(v), Ho.cycle(v0, f, kappa=min(kappa, 64), nu1=2, nu2=2)[0])
+    u_ref, rc, it_ref, hist = Ho.solve(f, kappa=min(kappa, 64), tol=1e-6, maxit=500)
+    check_stop_margin(hist, 1e-6)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    iters, relres, status = H.solve(u, dev(f), kappa=kappa, tol=1e-6, maxit=500)
+    assert status == [0] and iters[0] == it_ref
+    assert np.array_equal(host(u), u_ref)
+
+
 def check_stop_margin(hist, tol):
     """No relative residual of the run lies within 1e-12 (relative) of tol."""
     h = np.asarray(hist)
@@ -120,6 +141,9 @@ def test_config1_solve(kappa):
     assert status == [0]
     assert iters[0] == it_ref
     assert abs(relres[0] - hist[-1]) <= 1e-12 * hist[-1]
+    gh = H.residual_history(0)
+    assert len(gh) == len(hist) == it_ref + 1
+    assert np.allclose(gh, hist, rtol=1e-12, atol=0.0)
     got = host(u)
     assert relmax(got, u_ref) <= 1e-11
     assert np.array_equal(got, u_ref)
@@ -202,6 +226,11 @@ def test_pcg(n, kappa, f32):
     iters, relres, status = H.pcg(u, dev(f), kappa=kappa, nu1=1, nu2=1, tol=1e-8, maxit=500)
     assert status == [0]
     assert abs(iters[0] - it_ref) <= (0 if not f32 else 1)
+    gh = H.residual_history(0)
+    assert len(gh) == iters[0] + 1 and gh[0] == 1.0 and gh[-1] == relres[0]
+    if not f32:
+        m = min(len(gh), len(hist))
+        assert np.allclose(gh[:m], hist[:m], rtol=1e-8, atol=0.0)
     got = host(u)
     assert relmax(got, u_ref) <= (1e-9 if not f32 else 1e-6)
     true_rel = np.linalg.norm(f - Ho.apply(got)) / np.linalg.norm(f)
