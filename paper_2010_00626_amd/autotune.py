@@ -4,9 +4,11 @@ The library's results do not depend on its execution options (every kernel
 variant rounds each operation the same way), so the options can be chosen by
 measurement alone: for a hierarchy, a cycle (kappa, nu1, nu2) and a driver,
 each candidate runs a fixed number of iterations and the fastest is kept.  The
-search is staged: first the persistent-kernel options (coarse cutover,
-threads, single-wave level size), then, with the best of those fixed, the
-largest level size that the fused grid kernels run in 16 x 16 tiles.  Results are
+search is coordinate descent over two groups of options, each searched with
+the best of the other fixed: the largest level size that the fused grid
+kernels run in 16 x 16 tiles, then the persistent-kernel options (coarse
+cutover, threads, single-wave level size), then the tile size again (the
+best cutover depends on how cheap the grid launches below it are).  Results are
 cached per (device, instance sizes, precision, driver, kappa, nu1, nu2) in
 memory and, when KC_AUTOTUNE_CACHE names a file, in that JSON file.
 """
@@ -19,12 +21,13 @@ import time
 from . import kcycle
 
 COARSE_CANDIDATES = tuple(
-    dict(coarse_cutover=c, coarse_threads=t, coarse_wave_n=w, small_tile_n=0)
+    dict(coarse_cutover=c, coarse_threads=t, coarse_wave_n=w)
     for c in (15, 31, 63) for t in (256, 512) for w in (7, 15)
     if not (c == 63 and t == 256)       # 63 rows need at least 8 waves
 )
-TILE_CANDIDATES = tuple(dict(small_tile_n=s) for s in (127, 255, 511, 1023))
-DEFAULT_STAGES = (COARSE_CANDIDATES, TILE_CANDIDATES)
+TILE_CANDIDATES = tuple(dict(small_tile_n=s) for s in (0, 127, 255, 511, 1023, 4095))
+DEFAULT_STAGES = (tuple(dict(coarse_cutover=31, coarse_threads=512, coarse_wave_n=15, **t) for t in TILE_CANDIDATES),
+                  COARSE_CANDIDATES, TILE_CANDIDATES)
 
 _memory: dict = {}
 
@@ -81,7 +84,7 @@ def tune(H: "kcycle.Hierarchy", u, f, kappa: int, nu1: int = 2, nu2: int = 2, om
         base = dict(best["exec"]) if best else {}
         for part in stage:
             cand = dict(base, **part)
-            if best and cand == best["exec"]:
+            if any(t["exec"] == cand for t in trials):
                 continue
             try:
                 H.set_exec(**dict(cand, poll_every=iters + 2))

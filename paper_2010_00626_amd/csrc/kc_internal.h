@@ -100,10 +100,17 @@ enum SubOp : uint32_t {
     SOP_POST = 2,     // prolong-add from depth+1 + nu2 sweeps
     SOP_SOLVE = 3,    // coarsest direct solve
 };
-__host__ __device__ inline uint32_t sop_make(uint32_t op, uint32_t depth, uint32_t zg)
+// op word: kind (bits 0-1) | depth (2-5) | zero-guess flag (6) | lg = log2(n + 1)
+// of the level (7-9) | LDS element offset of the level's three arrays (10-31)
+__host__ __device__ inline uint32_t sop_make(uint32_t op, uint32_t depth, uint32_t zg, uint32_t lg, uint32_t off)
 {
-    return op | (depth << 4) | (zg << 12);
+    return op | (depth << 2) | (zg << 6) | (lg << 7) | (off << 10);
 }
+__host__ __device__ inline int sop_kind(uint32_t w) { return (int)(w & 3u); }
+__host__ __device__ inline int sop_depth(uint32_t w) { return (int)((w >> 2) & 15u); }
+__host__ __device__ inline bool sop_zg(uint32_t w) { return ((w >> 6) & 1u) != 0; }
+__host__ __device__ inline int sop_lg(uint32_t w) { return (int)((w >> 7) & 7u); }
+__host__ __device__ inline int sop_off(uint32_t w) { return (int)(w >> 10); }
 
 // arguments of a grid-wide stage launch
 struct StageArgs {

@@ -678,12 +678,6 @@ struct SubParams {
     T chol[CH];
 };
 
-// One phase of the persistent kernel touches every interior point of one
-// level once.  Each phase is a small out-of-line function (the kernel runs
-// hundreds of phases per launch; inlining them all would not fit the
-// instruction cache).  Point mapping: a "single" level is spread over the 64
-// lanes of wave 0 (point p on lane p mod 64); otherwise row j goes to wave
-// j mod waves and column i to lane i.  Arrays have a zero ring, stride n + 2.
 // LDS pointers: the phase functions are not inlined, so their arguments carry
 // the LDS address space explicitly (generic pointers would compile to FLAT
 // accesses, which are slower than ds_read / ds_write)
@@ -692,144 +686,229 @@ template <typename T> using clds = const __attribute__((address_space(3))) T*;
 template <typename T> __device__ __forceinline__ lds<T> to_lds(T* p) { return (lds<T>)(p); }
 template <typename T> __device__ __forceinline__ clds<T> to_lds(const T* p) { return (clds<T>)(p); }
 
-// Visit every interior point (j, i) of an n x n level: value(j, i) computes a
-// point's new value, store(j, i, v) writes it.  A lane works on U points at a
-// time and computes all of them (with clamped, always-valid indices) before it
-// stores any, so their loads and FP chains overlap.  value() must not read
-// what store() writes for another point.
-template <int U, typename T, typename VF, typename SF>
-__device__ __forceinline__ void for_points(int n, bool single, VF value, SF store)
+// One phase of the persistent kernel touches every interior point of one
+// N x N level (N = 2^k - 1, known at compile time) once.  Arrays have a zero
+// ring, row stride N + 2.  Point mapping: thread t belongs to band t / (N + 1)
+// and column t mod (N + 1); band b owns the U = ceil(N / NB) consecutive rows
+// from b U (NB bands in all: 64 / (N + 1) when wave 0 runs the level alone,
+// threads / (N + 1) otherwise).  A lane loads the three columns around its
+// own for rows b U - 1 .. b U + U once and forms all U stencils from those
+// registers, computing every value before it stores any.  Column N (the ring)
+// and rows past N are computed on clamped indices and never stored.  Each
+// phase is a small out-of-line function: the kernel runs hundreds of phases
+// per launch and inlining them all would not fit the instruction cache.
+template <int N, int NB>
+struct Band {
+    static constexpr int B = N + 1, P = N + 2, U = (N + NB - 1) / NB;
+};
+
+// rows r0-1 .. r0+U of columns c-1, c, c+1 of x (padded indices clamped to the ring)
+template <typename T, int N, int U>
+__device__ __forceinline__ void load_rows(clds<T> x, int r0, int c, T (&w)[U + 2][3])
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    T val[U];
-    if (single) {
-        if (wv != 0) return;
-        const int m = n * n;
-        const uint32_t inv = (65536u + n - 1) / n;   // exact p / n for p < n^2, n <= 15
-        for (int p0 = lane; p0 < m; p0 += 64 * U) {
+    constexpr int P = N + 2;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int p = min(p0 + 64 * u, m - 1);
-                const int j = (int)(((uint32_t)p * inv) >> 16);
-                val[u] = value(j, p - j * n);
-            }
+    for (int k = 0; k < U + 2; ++k) {
+        const int pr = min(r0 + k, N + 1);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int p = p0 + 64 * u;
-                if (p < m) {
-                    const int j = (int)(((uint32_t)p * inv) >> 16);
-                    store(j, p - j * n, val[u]);
-                }
-            }
-        }
-    } else {
-        if (lane >= n) return;
-        const int nw = blockDim.x >> 6;
-        for (int j0 = wv; j0 < n; j0 += nw * U) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) val[u] = value(min(j0 + nw * u, n - 1), lane);
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (j0 + nw * u < n) store(j0 + nw * u, lane, val[u]);
-        }
+        for (int e = 0; e < 3; ++e) w[k][e] = x[pr * P + c + e];
     }
 }
 
-template <typename T>
-__device__ __forceinline__ T sten_lds(const Sten<T>& s, clds<T> x, int st)
+// fixed-order nine-point sum centred on window row k + 1 (south row first, west to east)
+template <typename T, int U>
+__device__ __forceinline__ T sten_win(const T (&s)[9], const T (&w)[U + 2][3], int k)
 {
     T acc = T(0);
-    acc += s.c[0] * x[-st - 1];
-    acc += s.c[1] * x[-st];
-    acc += s.c[2] * x[-st + 1];
-    acc += s.c[3] * x[-1];
-    acc += s.c[4] * x[0];
-    acc += s.c[5] * x[1];
-    acc += s.c[6] * x[st - 1];
-    acc += s.c[7] * x[st];
-    acc += s.c[8] * x[st + 1];
+    acc += s[0] * w[k][0];
+    acc += s[1] * w[k][1];
+    acc += s[2] * w[k][2];
+    acc += s[3] * w[k + 1][0];
+    acc += s[4] * w[k + 1][1];
+    acc += s[5] * w[k + 1][2];
+    acc += s[6] * w[k + 2][0];
+    acc += s[7] * w[k + 2][1];
+    acc += s[8] * w[k + 2][2];
     return acc;
 }
 
-template <typename T>
-__device__ __forceinline__ T fw_lds(clds<T> r, int st)
-{
-    const T q = T(0.25), h = T(0.5);
-    T acc = T(0);
-    acc += q * r[-st - 1];
-    acc += h * r[-st];
-    acc += q * r[-st + 1];
-    acc += h * r[-1];
-    acc += T(1) * r[0];
-    acc += h * r[1];
-    acc += q * r[st - 1];
-    acc += h * r[st];
-    acc += q * r[st + 1];
-    return acc;
-}
-
-template <typename T>
+// y = x + w (F - S x) (Jacobi), or y = w F on a zero guess
+template <typename T, int N, int NB>
 __device__ __noinline__ void ph_sweep(clds<T> __restrict__ x, lds<T> __restrict__ y, clds<T> __restrict__ F,
-                                     clds<T> __restrict__ sc, T w, int n, bool single, bool zg)
+                                     clds<T> __restrict__ sc, T om, int t, bool zg)
 {
-    const int P = n + 2;
-    Sten<T> s;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) s.c[k] = sc[k];
-    auto st = [&](int j, int i, T v) { y[(j + 1) * P + (i + 1)] = v; };
+    using G = Band<N, NB>;
+    constexpr int U = G::U, P = G::P;
+    const int b = t / G::B, c = t % G::B;
+    const int j0 = b * U;
+    if (b >= NB || j0 >= N) return;
+    const int cc = min(c, N - 1);
+    T val[U];
     if (zg) {
-        for_points<4, T>(n, single, [&](int j, int i) { return w * F[(j + 1) * P + (i + 1)]; }, st);
+#pragma unroll
+        for (int u = 0; u < U; ++u) val[u] = om * F[(min(j0 + u, N - 1) + 1) * P + cc + 1];
     } else {
-        for_points<4, T>(n, single, [&](int j, int i) {
-            const int q = (j + 1) * P + (i + 1);
-            return x[q] + w * (F[q] - sten_lds(s, x + q, P));
-        }, st);
+        T s[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) s[k] = sc[k];
+        T w[U + 2][3];
+        load_rows<T, N, U>(x, j0, cc, w);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T f = F[(min(j0 + u, N - 1) + 1) * P + cc + 1];
+            val[u] = w[u + 1][1] + om * (f - sten_win<T, U>(s, w, u));
+        }
+    }
+    if (c < N) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + u < N) y[(j0 + u + 1) * P + c + 1] = val[u];
     }
 }
 
-template <typename T>
+// r = F - S x
+template <typename T, int N, int NB>
 __device__ __noinline__ void ph_resid(clds<T> __restrict__ x, lds<T> __restrict__ r, clds<T> __restrict__ F,
-                                     clds<T> __restrict__ sc, int n, bool single)
+                                     clds<T> __restrict__ sc, int t)
 {
-    const int P = n + 2;
-    Sten<T> s;
+    using G = Band<N, NB>;
+    constexpr int U = G::U, P = G::P;
+    const int b = t / G::B, c = t % G::B;
+    const int j0 = b * U;
+    if (b >= NB || j0 >= N) return;
+    const int cc = min(c, N - 1);
+    T s[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) s.c[k] = sc[k];
-    for_points<4, T>(n, single, [&](int j, int i) {
-        const int q = (j + 1) * P + (i + 1);
-        return F[q] - sten_lds(s, x + q, P);
-    }, [&](int j, int i, T v) { r[(j + 1) * P + (i + 1)] = v; });
+    for (int k = 0; k < 9; ++k) s[k] = sc[k];
+    T w[U + 2][3];
+    load_rows<T, N, U>(x, j0, cc, w);
+    T val[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) val[u] = F[(min(j0 + u, N - 1) + 1) * P + cc + 1] - sten_win<T, U>(s, w, u);
+    if (c < N) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + u < N) r[(j0 + u + 1) * P + c + 1] = val[u];
+    }
 }
 
-// F_c = P^T r on the coarse level (nc = (n - 1) / 2 points per side)
-template <typename T>
-__device__ __noinline__ void ph_restrict(clds<T> __restrict__ r, lds<T> __restrict__ Fc, int n, bool single_c)
+// F_c = P^T r: coarse level NC = (N - 1) / 2 in the band mapping of NC (its own
+// NB); coarse point (J, I) is centred on fine padded point (2J + 2, 2I + 2)
+template <typename T, int NC, int NB>
+__device__ __noinline__ void ph_restrict(clds<T> __restrict__ r, lds<T> __restrict__ Fc, int t)
 {
-    const int nc = (n - 1) / 2;
-    const int P = n + 2, Pc = nc + 2;
-    for_points<4, T>(nc, single_c, [&](int J, int I) { return fw_lds<T>(r + (2 * J + 2) * P + (2 * I + 2), P); },
-                     [&](int J, int I, T v) { Fc[(J + 1) * Pc + (I + 1)] = v; });
+    using G = Band<NC, NB>;
+    constexpr int U = G::U, Pc = G::P, N = 2 * NC + 1, P = N + 2;
+    const int b = t / G::B, c = t % G::B;
+    const int J0 = b * U;
+    if (b >= NB || J0 >= NC) return;
+    const int cc = min(c, NC - 1);
+    // fine padded rows 2 J0 + 1 .. 2 (J0 + U - 1) + 3, columns 2 cc + 1 .. 2 cc + 3
+    T w[2 * U + 1][3];
+#pragma unroll
+    for (int k = 0; k < 2 * U + 1; ++k) {
+        const int pr = min(2 * J0 + 1 + k, N + 1);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) w[k][e] = r[pr * P + 2 * cc + 1 + e];
+    }
+    const T q = T(0.25), h = T(0.5);
+    T val[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int k = 2 * u;
+        T acc = T(0);
+        acc += q * w[k][0];
+        acc += h * w[k][1];
+        acc += q * w[k][2];
+        acc += h * w[k + 1][0];
+        acc += T(1) * w[k + 1][1];
+        acc += h * w[k + 1][2];
+        acc += q * w[k + 2][0];
+        acc += h * w[k + 2][1];
+        acc += q * w[k + 2][2];
+        val[u] = acc;
+    }
+    if (c < NC) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (J0 + u < NC) Fc[(J0 + u + 1) * Pc + c + 1] = val[u];
+    }
 }
 
 // x += P vc (each point reads only its own x)
-template <typename T>
-__device__ __noinline__ void ph_prolong(lds<T> __restrict__ x, clds<T> __restrict__ vc, int n, bool single)
+template <typename T, int N, int NB>
+__device__ __noinline__ void ph_prolong(lds<T> __restrict__ x, clds<T> __restrict__ vc, int t)
 {
-    const int P = n + 2, Pc = (n - 1) / 2 + 2;
-    for_points<4, T>(n, single, [&](int j, int i) {
-        const T e = prolong_at<T>(j, i, [&](int J, int I) { return vc[(J + 1) * Pc + (I + 1)]; });
-        return x[(j + 1) * P + (i + 1)] + e;
-    }, [&](int j, int i, T v) { x[(j + 1) * P + (i + 1)] = v; });
+    using G = Band<N, NB>;
+    constexpr int U = G::U, P = G::P, Pc = (N - 1) / 2 + 2;
+    const int b = t / G::B, c = t % G::B;
+    const int j0 = b * U;
+    if (b >= NB || j0 >= N) return;
+    const int cc = min(c, N - 1);
+    T val[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = min(j0 + u, N - 1);
+        const T e = prolong_at<T>(j, cc, [&](int J, int I) { return vc[(J + 1) * Pc + (I + 1)]; });
+        val[u] = x[(j + 1) * P + cc + 1] + e;
+    }
+    if (c < N) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j0 + u < N) x[(j0 + u + 1) * P + c + 1] = val[u];
+    }
 }
 
-template <typename T>
-__device__ __noinline__ void ph_zero(lds<T> __restrict__ x, int n, bool single)
+template <typename T, int N, int NB>
+__device__ __noinline__ void ph_zero(lds<T> __restrict__ x, int t)
 {
-    const int P = n + 2;
-    for_points<1, T>(n, single, [&](int, int) { return T(0); }, [&](int j, int i, T v) { x[(j + 1) * P + (i + 1)] = v; });
+    using G = Band<N, NB>;
+    constexpr int U = G::U, P = G::P;
+    const int b = t / G::B, c = t % G::B;
+    const int j0 = b * U;
+    if (b >= NB || j0 >= N || c >= N) return;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (j0 + u < N) x[(j0 + u + 1) * P + c + 1] = T(0);
 }
 
-template <typename T>
+// run phase PH on a level of size (1 << lg) - 1 in its band mapping: wave 0
+// alone (single; levels up to 15 x 15) or the whole block of THREADS
+#define KC_LEVEL_CASE(PH, LG, ...)                                                              \
+    case LG: {                                                                                   \
+        constexpr int NN = (1 << LG) - 1;                                                        \
+        constexpr int NBM = THREADS / (NN + 1) > 0 ? THREADS / (NN + 1) : 1;                     \
+        if constexpr (LG <= 4) {                                                                 \
+            if (single) PH<T, NN, 64 / (NN + 1)>(__VA_ARGS__, threadIdx.x & 63);                \
+            else PH<T, NN, NBM>(__VA_ARGS__, threadIdx.x);                                       \
+        } else if constexpr (LG == 5 || THREADS >= 512) {                                        \
+            PH<T, NN, NBM>(__VA_ARGS__, threadIdx.x);  /* 63 x 63 needs 512 threads */           \
+        }                                                                                        \
+        break;                                                                                   \
+    }
+#define KC_LEVEL_SWITCH(LGV, PH, ...)                                                           \
+    switch (LGV) {                                                                               \
+        KC_LEVEL_CASE(PH, 2, __VA_ARGS__)                                                        \
+        KC_LEVEL_CASE(PH, 3, __VA_ARGS__)                                                        \
+        KC_LEVEL_CASE(PH, 4, __VA_ARGS__)                                                        \
+        KC_LEVEL_CASE(PH, 5, __VA_ARGS__)                                                        \
+        KC_LEVEL_CASE(PH, 6, __VA_ARGS__)                                                        \
+        default: break;                                                                          \
+    }
+
+// sweep with the zero-guess flag last (it follows the thread index in the phase signature)
+template <typename T, int N, int NB>
+__device__ __forceinline__ void ph_sweep_zg0(clds<T> x, lds<T> y, clds<T> F, clds<T> sc, T om, int t)
+{
+    ph_sweep<T, N, NB>(x, y, F, sc, om, t, false);
+}
+template <typename T, int N, int NB>
+__device__ __forceinline__ void ph_sweep_zg1(clds<T> x, lds<T> y, clds<T> F, clds<T> sc, T om, int t)
+{
+    ph_sweep<T, N, NB>(x, y, F, sc, om, t, true);
+}
+
+template <typename T, int THREADS>
 struct Sub {
     T* sm;
     const SubParams<T>* pp;
@@ -838,61 +917,87 @@ struct Sub {
     uint32_t cur;           // bit d: current estimate of level d is in the second buffer
     bool pending = false;   // wave 0 has written LDS since the last workgroup barrier
 
-    __device__ __forceinline__ int n_(int d) const { return pp->n[d]; }
-    __device__ __forceinline__ T* buf(int d, int which) const
+    // level d of size n = 2^lg - 1 starts at LDS element off: buffers 0 and 1 (sweeps), 2 (F)
+    __device__ __forceinline__ T* bufp(int off, int lg, int which) const
     {
-        const int P = pp->n[d] + 2;
-        return sm + pp->off[d] + which * P * P;
+        const int P = (1 << lg) + 1;
+        return sm + off + which * P * P;
     }
-    __device__ __forceinline__ T* v(int d) const { return buf(d, (cur >> d) & 1); }
-    __device__ __forceinline__ T* o(int d) const { return buf(d, ((cur >> d) & 1) ^ 1); }
-    __device__ __forceinline__ T* f(int d) const { return buf(d, 2); }
-    __device__ __forceinline__ bool single(int d) const { return pp->n[d] <= wave_n; }
-    __device__ __forceinline__ void sten(int d, Sten<T>& s) const { s.load(pp->s[d]); }
-
-    __device__ __forceinline__ void sync(int d) const
+    __device__ __forceinline__ bool single_lg(int lg) const { return (1 << lg) - 1 <= wave_n; }
+    __device__ __forceinline__ void sync_lg(int lg) const
     {
-        if (single(d)) wave_sync();
+        if (single_lg(lg)) wave_sync();
         else __syncthreads();
     }
 
-    __device__ __forceinline__ void sweeps(int d, int nu, bool zg)
+    __device__ __forceinline__ void sweeps(int d, int lg, int off, int nu, bool zg)
     {
-        const int n = n_(d);
-        const bool sg = single(d);
+        const bool single = single_lg(lg);
+        const clds<T> F = to_lds<T>((const T*)bufp(off, lg, 2));
+        const clds<T> sc = to_lds<T>(&pp->s[d][0]);
+        const T om = pp->w[d];
         for (int k = 0; k < nu; ++k) {
-            ph_sweep<T>(to_lds<T>(v(d)), to_lds<T>(o(d)), to_lds<T>(f(d)), to_lds<T>(&pp->s[d][0]), pp->w[d], n, sg, zg && k == 0);
-            sync(d);
+            const int cb = (cur >> d) & 1;
+            const clds<T> x = to_lds<T>((const T*)bufp(off, lg, cb));
+            const lds<T> y = to_lds<T>(bufp(off, lg, cb ^ 1));
+            if (zg && k == 0) { KC_LEVEL_SWITCH(lg, ph_sweep_zg1, x, y, F, sc, om) }
+            else { KC_LEVEL_SWITCH(lg, ph_sweep_zg0, x, y, F, sc, om) }
+            sync_lg(lg);
             cur ^= 1u << d;
         }
         if (zg && nu == 0) {
-            ph_zero<T>(to_lds<T>(v(d)), n, sg);
-            sync(d);
+            const bool single = single_lg(lg);
+            const lds<T> x = to_lds<T>(bufp(off, lg, (cur >> d) & 1));
+            KC_LEVEL_SWITCH(lg, ph_zero, x)
+            sync_lg(lg);
         }
     }
 
-    __device__ __forceinline__ void pre(int d, bool zg)
+    __device__ __forceinline__ void pre(int d, int lg, int off, bool zg)
     {
-        sweeps(d, nu1, zg);
-        ph_resid<T>(to_lds<T>(v(d)), to_lds<T>(o(d)), to_lds<T>(f(d)), to_lds<T>(&pp->s[d][0]), n_(d), single(d));
-        sync(d);
-        ph_restrict<T>(to_lds<T>((const T*)o(d)), to_lds<T>(f(d + 1)), n_(d), single(d + 1));
-        sync(d + 1);
+        sweeps(d, lg, off, nu1, zg);
+        const int P = (1 << lg) + 1, offc = off + 3 * P * P;
+        const int cb = (cur >> d) & 1;
+        {
+            const bool single = single_lg(lg);
+            KC_LEVEL_SWITCH(lg, ph_resid, to_lds<T>((const T*)bufp(off, lg, cb)), to_lds<T>(bufp(off, lg, cb ^ 1)),
+                            to_lds<T>((const T*)bufp(off, lg, 2)), to_lds<T>(&pp->s[d][0]))
+            sync_lg(lg);
+        }
+        {
+            const int lgc = lg - 1;
+            const bool single = single_lg(lgc);
+            const clds<T> r = to_lds<T>((const T*)bufp(off, lg, cb ^ 1));
+            const lds<T> Fc = to_lds<T>(bufp(offc, lgc, 2));
+            if (lgc == 1) {
+                if (single) ph_restrict<T, 1, 32>(r, Fc, threadIdx.x & 63);
+                else ph_restrict<T, 1, THREADS / 2>(r, Fc, threadIdx.x);
+            } else {
+                KC_LEVEL_SWITCH(lgc, ph_restrict, r, Fc)
+            }
+            sync_lg(lgc);
+        }
     }
 
-    __device__ __forceinline__ void post(int d)
+    __device__ __forceinline__ void post(int d, int lg, int off)
     {
-        ph_prolong<T>(to_lds<T>(v(d)), to_lds<T>((const T*)v(d + 1)), n_(d), single(d));
-        sync(d);
-        sweeps(d, nu2, false);
+        const int P = (1 << lg) + 1, offc = off + 3 * P * P;
+        {
+            const bool single = single_lg(lg);
+            const lds<T> x = to_lds<T>(bufp(off, lg, (cur >> d) & 1));
+            const clds<T> vc = to_lds<T>((const T*)bufp(offc, lg - 1, (cur >> (d + 1)) & 1));
+            KC_LEVEL_SWITCH(lg, ph_prolong, x, vc)
+            sync_lg(lg);
+        }
+        sweeps(d, lg, off, nu2, false);
     }
 
-    __device__ __forceinline__ void solve(int d)
+    __device__ __forceinline__ void solve(int d, int lg, int off)
     {
-        const int n = n_(d);
+        const int n = (1 << lg) - 1;
         const T* Lc = (n * n * n * n <= SubParams<T>::CH) ? pp->chol : P<T>::chol(*I);
-        if (threadIdx.x == 0) chol_solve_padded<T>(n, Lc, f(d), v(d), n + 2);
-        sync(d);
+        if (threadIdx.x == 0) chol_solve_padded<T>(n, Lc, bufp(off, lg, 2), bufp(off, lg, (cur >> d) & 1), n + 2);
+        sync_lg(lg);
     }
 
     // waves that skip a wave-0 operation still follow its buffer swaps
@@ -912,9 +1017,9 @@ struct Sub {
         const bool w0 = (threadIdx.x >> 6) == 0;
         for (int o = 0; o < nops; ++o) {
             const uint32_t op = pp->ops[base + o];
-            const int kind = op & 15, d = (op >> 4) & 255;
-            const bool zg = (op >> 12) & 1;
-            const bool sg = single(d);
+            const int kind = sop_kind(op), d = sop_depth(op), lg = sop_lg(op), off = sop_off(op);
+            const bool zg = sop_zg(op);
+            const bool sg = single_lg(lg);
             if (sg && !w0) {
                 skip(kind, d, zg);
                 pending = true;
@@ -924,16 +1029,16 @@ struct Sub {
                 __syncthreads();
                 pending = false;
             }
-            if (kind == SOP_PRE) pre(d, zg);
-            else if (kind == SOP_POST) post(d);
-            else solve(d);
-            if (sg || (kind == SOP_PRE && single(d + 1))) pending = true;
+            if (kind == SOP_PRE) pre(d, lg, off, zg);
+            else if (kind == SOP_POST) post(d, lg, off);
+            else solve(d, lg, off);
+            if (sg || (kind == SOP_PRE && single_lg(lg - 1))) pending = true;
         }
     }
 };
 
-template <typename T>
-__global__ void __launch_bounds__(512) k_subtree(SubArgs a)
+template <typename T, int THREADS>
+__global__ void __launch_bounds__(THREADS) k_subtree(SubArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ SubParams<T> pp;
@@ -967,14 +1072,15 @@ __global__ void __launch_bounds__(512) k_subtree(SubArgs a)
     for (int p = threadIdx.x; p < I.sub_lds; p += blockDim.x) sm[p] = T(0);
     __syncthreads();
 
-    Sub<T> S{sm, &pp, &I, a.nu1, a.nu2, a.wave_n, 0u};
+    Sub<T, THREADS> S{sm, &pp, &I, a.nu1, a.nu2, a.wave_n, 0u};
     const LevelDev& Lv = I.lev[d0];
-    const int n = pp.n[d0], Pst = n + 2;
+    const int n = pp.n[d0], Pst = n + 2, off0 = pp.off[d0];
+    const int lg0 = 32 - __clz(n);   // n = 2^lg0 - 1
     const T fs = (T)Lv.fscale;
     const T* Fg = (const T*)Lv.F;
     T* Ag = (T*)Lv.A;
-    T* v0 = S.v(d0);
-    T* f0 = S.f(d0);
+    T* v0 = S.bufp(off0, lg0, 0);
+    T* f0 = S.bufp(off0, lg0, 2);
     const bool zero = a.pair || a.zg;
     for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
         const int j = p / n, i = p - j * n;
@@ -987,7 +1093,7 @@ __global__ void __launch_bounds__(512) k_subtree(SubArgs a)
         __shared__ double red[16];
         __shared__ int stop;
         Sten<T> s;
-        S.sten(d0, s);
+        s.load(pp.s[d0]);
         double nrm = 0.0;
         for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
             const int j = p / n, i = p - j * n;
@@ -1012,7 +1118,7 @@ __global__ void __launch_bounds__(512) k_subtree(SubArgs a)
     S.call(0);
     if (n2 > 0) S.call(1);
     __syncthreads();
-    const T* vr = S.v(d0);
+    const T* vr = S.bufp(off0, lg0, (S.cur >> d0) & 1);
     for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
         const int j = p / n, i = p - j * n;
         Ag[(size_t)j * Lv.lda + i] = vr[(j + 1) * Pst + (i + 1)];
@@ -1251,8 +1357,15 @@ hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nb, h
 hipError_t launch_subtree(bool f32, const SubArgs& a, int32_t threads, int32_t lds_bytes, hipStream_t s)
 {
     if (a.count <= 0) return hipSuccess;
-    if (f32) k_subtree<float><<<a.count, threads, lds_bytes, s>>>(a);
-    else k_subtree<double><<<a.count, threads, lds_bytes, s>>>(a);
+    if (threads == 256) {
+        if (f32) k_subtree<float, 256><<<a.count, 256, lds_bytes, s>>>(a);
+        else k_subtree<double, 256><<<a.count, 256, lds_bytes, s>>>(a);
+    } else if (threads == 512) {
+        if (f32) k_subtree<float, 512><<<a.count, 512, lds_bytes, s>>>(a);
+        else k_subtree<double, 512><<<a.count, 512, lds_bytes, s>>>(a);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1266,8 +1379,17 @@ hipError_t launch_coarsest(bool f32, const SubArgs& a, hipStream_t s)
 
 hipError_t prepare_subtree(bool f32, int32_t lds_bytes)
 {
-    if (f32) return hipFuncSetAttribute((const void*)k_subtree<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    return hipFuncSetAttribute((const void*)k_subtree<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    hipError_t e;
+    if (f32) {
+        e = hipFuncSetAttribute((const void*)k_subtree<float, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_subtree<float, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    } else {
+        e = hipFuncSetAttribute((const void*)k_subtree<double, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_subtree<double, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    }
+    return e;
 }
 
 int32_t max_lds_bytes()

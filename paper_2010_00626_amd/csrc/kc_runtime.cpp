@@ -264,17 +264,25 @@ struct HostInst {
     int lds_off[MAXL] = {}, lds_elems = 0;
 };
 
+int lg_of(int n)
+{
+    int lg = 0;
+    while ((1 << lg) - 1 < n) ++lg;
+    return lg;
+}
+
 // op list of one call at depth d with counter k (Algorithm 3), levels in LDS
 void gen_sub_call(const HostInst& h, int d, int k, bool zg, std::vector<uint32_t>& out)
 {
+    const uint32_t lg = (uint32_t)lg_of(h.il.n[d]), off = (uint32_t)h.lds_off[d];
     if (d == h.il.L - 1) {
-        out.push_back(sop_make(SOP_SOLVE, d, 0));
+        out.push_back(sop_make(SOP_SOLVE, d, 0, lg, off));
         return;
     }
-    out.push_back(sop_make(SOP_PRE, d, zg ? 1 : 0));
+    out.push_back(sop_make(SOP_PRE, d, zg ? 1 : 0, lg, off));
     gen_sub_call(h, d + 1, k, true, out);
     if (k > 1) gen_sub_call(h, d + 1, k - 1, false, out);
-    out.push_back(sop_make(SOP_POST, d, 0));
+    out.push_back(sop_make(SOP_POST, d, 0, lg, off));
 }
 
 }  // namespace
@@ -506,6 +514,14 @@ kc_status plan_exec(kc_hier* h)
         hi.cut = cut;
         h->max_cut = std::max(h->max_cut, std::min(cut, L));
         h->max_L = std::max(h->max_L, L);
+        int off = 0;
+        for (int d = 0; d < MAXL; ++d) hi.lds_off[d] = 0;
+        if (cut < L) {
+            for (int d = cut; d < L; ++d) {   // two sweep buffers and F, each (n+2)^2 with a zero ring
+                hi.lds_off[d] = off;
+                off += 3 * (hi.il.n[d] + 2) * (hi.il.n[d] + 2);
+            }
+        }
         hi.ops.clear();
         for (int k = 1; k <= KMAX; ++k) {
             hi.ops_beg[k - 1] = (int)hi.ops.size();
@@ -521,14 +537,6 @@ kc_status plan_exec(kc_hier* h)
             hi.ops_len[k - 1] = (int)hi.ops.size() - hi.ops_beg[k - 1];
         }
         if ((int)hi.ops.size() > OPS_CAP) return fail(KC_ERR_ARG, "coarse cutover too large for the op buffer");
-        int off = 0;
-        for (int d = 0; d < MAXL; ++d) hi.lds_off[d] = 0;
-        if (cut < L) {
-            for (int d = cut; d < L; ++d) {   // two sweep buffers and F, each (n+2)^2 with a zero ring
-                hi.lds_off[d] = off;
-                off += 3 * (hi.il.n[d] + 2) * (hi.il.n[d] + 2);
-            }
-        }
         hi.lds_elems = off;
         h->sub_lds = std::max(h->sub_lds, (int)(off * T));
     }
