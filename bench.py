@@ -27,6 +27,41 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fine-grid unknowns/s to 1e-8 rel. residual per κ; batched+FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+VECTOR_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense vector peaks (FP32 counts packed issue)
+
+
+def traffic_of(kernel: str):
+    """HBM bytes per launch of `kernel` measured with rocprofv3 counters
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a copy of known size), from the
+    committed summary; None when there is none for this kernel or the kernel
+    source changed since it was taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "traffic.json")
+    src = os.path.join(here, "paper_2010_00626_amd", "csrc", "kc_kernels.hip")
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+        with open(src, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if data.get("kernels_source_sha256") != digest:
+        return None
+    v = data.get("bytes_per_launch", {}).get(kernel)
+    return round(v, 1) if v is not None else None
+
+
+def kernel_row(k, prec):
+    """Roofline entry of one kernel from the library's per-launch profile."""
+    avg_s = k["avg_ms"] * 1e-3
+    if k["name"].startswith("k_subtree"):
+        peak = VECTOR_PEAK_TFLOPS[prec]
+        ach = k["flops_per_launch"] / avg_s / 1e12 if avg_s > 0 else 0.0
+        return {"bound": "alu", "achieved": round(ach, 4), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 5)}
+    ach = k["bytes_per_launch"] / avg_s / 1e9 if avg_s > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4)}
 
 
 def parse():
@@ -41,6 +76,8 @@ def parse():
     ap.add_argument("--kappa", type=int, default=0, help="force the headline kappa (0 = fastest of the sweep)")
     ap.add_argument("--precision", default="", help="force the headline precision (f64 or f32)")
     ap.add_argument("--no-tune", action="store_true", help="skip the execution-option autotuner")
+    ap.add_argument("--exec", default="", help="JSON execution options for the headline configuration "
+                    "(instead of the autotuned ones)")
     ap.add_argument("--extras", default="c4,c3,c5,hbm",
                     help="extra measurements: c4 (batched uneven), c3 (PCG 4095^2), c5 (adjoint), hbm (8191^2 kernel)")
     return ap.parse_args()
@@ -122,6 +159,10 @@ def main():
     else:
         best_k, best_p = 3, (args.precision or "f32")
 
+    if args.exec:
+        tuned[(best_p, best_k)] = json.loads(args.exec)
+    elif (best_p, best_k) not in tuned and not args.no_tune:
+        tune(best_p, best_k)
     if (best_p, best_k) in tuned:
         H[best_p].set_exec(**tuned[(best_p, best_k)])
     for _ in range(args.warmup):
@@ -136,20 +177,30 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     value = N * args.steps / elapsed
 
-    # roofline of the fine-level smoothing kernel (the largest bandwidth consumer)
+    # per-kernel profile of one iteration of the headline configuration; the
+    # roofline object describes the kernel with the largest share of it
     Hb = H[best_p]
+    solve(best_p, best_k)
+    prof = Hb.profile_iteration("solve", kappa=best_k, nu1=w.nu1, nu2=w.nu2, omega=w.omega, reps=20)
     ms_pre, bytes_pre = Hb.time_stage(0, kappa=best_k, nu1=w.nu1, nu2=w.nu2, omega=w.omega, reps=200)
-    ms_post, bytes_post = Hb.time_stage(1, kappa=best_k, nu1=w.nu1, nu2=w.nu2, omega=w.omega, reps=200)
-    ms_sub, bytes_sub = Hb.time_stage(2, kappa=best_k, nu1=w.nu1, nu2=w.nu2, omega=w.omega, reps=50)
     solve(best_p, best_k)   # leave the hierarchy in a solved state
-    gbs = bytes_pre / (ms_pre * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": f"k_pre<{'float' if best_p == 'f32' else 'double'},{w.nu1}> (fine level)",
-                "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": bytes_pre, "avg_launch_ms": round(ms_pre, 5),
-                "note": "1023^2 levels are resident in the 256 MB Infinity Cache; GB/s is cache bandwidth"}
-    kernels = {"pre_fine": {"ms": round(ms_pre, 5), "GB_s": round(gbs, 1)},
-               "post_fine": {"ms": round(ms_post, 5), "GB_s": round(bytes_post / (ms_post * 1e-3) / 1e9, 1)},
-               "persistent_coarse": {"ms": round(ms_sub, 5)}}
+    it_ms = prof["iteration_ms"]
+    kernels = {}
+    for k in sorted(prof["kernels"], key=lambda r: -r["ms"]):
+        row = {"launches_per_iteration": k["launches"], "avg_us": round(k["avg_ms"] * 1e3, 2),
+               "share": round(k["ms"] / it_ms, 4)}
+        if k["bytes_per_launch"] > 0 or k["flops_per_launch"] > 0:
+            row.update(kernel_row(k, best_p))
+        kernels[k["name"]] = row
+    dom = max(prof["kernels"], key=lambda r: r["ms"])
+    roofline = dict(kernel_row(dom, best_p), traffic=traffic_of(dom["name"]), kernel=dom["name"],
+                    share_of_iteration=round(dom["ms"] / it_ms, 4), avg_launch_ms=round(dom["avg_ms"], 5),
+                    launches_per_iteration=dom["launches"], bytes_per_launch=dom["bytes_per_launch"],
+                    flops_per_launch=dom["flops_per_launch"],
+                    note="1023^2 levels stay in the 256 MB Infinity Cache; coarse levels are latency-bound on one CU "
+                         "per instance (the persistent kernel)")
+    fine = {"kernel": "fine-level pre-smoothing", "avg_us": round(ms_pre * 1e3, 2),
+            "GB_s": round(bytes_pre / (ms_pre * 1e-3) / 1e9, 1), "bytes_per_launch": bytes_pre}
 
     # run-time model (Section 3) fitted to the sweep's per-cycle times and the kappa it predicts
     model_info = None
@@ -193,8 +244,10 @@ def main():
         "config": {"workload": "1023x1023 rotated anisotropic diffusion, theta=pi/6, eps=1e-4, 10 levels, "
                                "damped Jacobi 0.8, nu=2+2, tol 1e-8",
                    "kappa": "W" if best_k == kcycle.KAPPA_W else best_k, "precision": best_p,
+                   "exec": tuned.get((best_p, best_k)),
                    "cycles": its[0], "unknowns": N},
-        "roofline": roofline, "kernels": kernels, "per_kappa": per, "model": model_info,
+        "roofline": roofline, "kernels": kernels, "iteration_ms": round(it_ms, 4), "fine_level": fine,
+        "per_kappa": per, "model": model_info,
         "extras": extras, "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -97,7 +97,9 @@ typedef struct {
     int32_t coarse_wave_n;  /* persistent-kernel levels with n <= this run on one wave (0..15; default 15) */
     int32_t small_tile_n;   /* fused grid kernels on levels whose largest n <= this use 16 x 16 tiles instead of
                                64 x 32 (0 = never; 0..4095; default 0); results do not depend on it */
-    int32_t reserved;
+    int32_t stream_n;       /* fused grid kernels on levels whose largest n >= this stream row strips through
+                               registers instead of staging tiles in LDS (0 = never; default 2047); results do
+                               not depend on it */
 } kc_exec;
 
 typedef struct kc_hier kc_hier;
@@ -198,6 +200,19 @@ kc_status kc_time_stage(kc_hier* h, int32_t which, const kc_cycle_params* c, int
  * FP64 hierarchies.  Synchronises. */
 kc_status kc_time_cycles(kc_hier* h, double* const* d_v, const int64_t* ldv, const double* const* d_f,
                          const int64_t* ldf, const kc_cycle_params* c, int32_t reps, double* ms_per_cycle);
+
+/* per-launch profile of one solver iteration (driver 0 = stand-alone kc_solve,
+ * 1 = kc_pcg; the same driver must have run last on h, whose arrays it keeps
+ * iterating on, so they are overwritten).  Runs one warm-up iteration, then
+ * repeats each launch of the iteration `reps` times back to back between two
+ * hip events (its finalize step likewise), every instance kept active
+ * (tolerance 0).  Writes JSON to out: iteration_ms and,
+ * per kernel (compiler names, as a profiler lists them), the launches per
+ * iteration, total and average ms, and the algorithmic bytes and flops per
+ * launch (each input read once, each output written once); the sequence of
+ * launches with depth and ms.  Synchronises. */
+kc_status kc_profile_iteration(kc_hier* h, int32_t driver, const kc_cycle_params* c, int32_t reps, char* out,
+                               size_t cap);
 
 /* JSON summary: sizes, launches per cycle, last solve's timings */
 kc_status kc_stats(const kc_hier* h, char* out, size_t cap);

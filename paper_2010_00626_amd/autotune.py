@@ -5,10 +5,11 @@ variant rounds each operation the same way), so the options can be chosen by
 measurement alone: for a hierarchy, a cycle (kappa, nu1, nu2) and a driver,
 each candidate runs a fixed number of iterations and the fastest is kept.  The
 search is coordinate descent over two groups of options, each searched with
-the best of the other fixed: the largest level size that the fused grid
-kernels run in 16 x 16 tiles, then the persistent-kernel options (coarse
-cutover, threads, single-wave level size), then the tile size again (the
-best cutover depends on how cheap the grid launches below it are).  Results are
+the best of the other fixed: the shapes of the fused grid kernels (the
+largest level size run in 16 x 16 tiles, the smallest level size streamed
+through registers), then the persistent-kernel options (coarse cutover,
+threads, single-wave level size), then the grid shapes again (the best
+cutover depends on how cheap the grid launches below it are).  Results are
 cached per (device, instance sizes, precision, driver, kappa, nu1, nu2) in
 memory and, when KC_AUTOTUNE_CACHE names a file, in that JSON file.
 """
@@ -25,9 +26,17 @@ COARSE_CANDIDATES = tuple(
     for c in (15, 31, 63) for t in (256, 512) for w in (7, 15)
     if not (c == 63 and t == 256)       # 63 rows need at least 8 waves
 )
-TILE_CANDIDATES = tuple(dict(small_tile_n=s) for s in (0, 127, 255, 511, 1023, 4095))
+TILE_CANDIDATES = tuple(dict(small_tile_n=s, stream_n=m) for s in (0, 127, 255, 511, 1023)
+                        for m in (0, 1023, 2047, 4095))
 DEFAULT_STAGES = (tuple(dict(coarse_cutover=31, coarse_threads=512, coarse_wave_n=15, **t) for t in TILE_CANDIDATES),
                   COARSE_CANDIDATES, TILE_CANDIDATES)
+
+
+def _relevant(cand: dict, nmax: int) -> bool:
+    """Skip shape options that cannot change the schedule of a hierarchy whose
+    largest level is nmax (streaming thresholds above it act like 'never')."""
+    m = cand.get("stream_n", 0)
+    return m == 0 or m <= nmax
 
 _memory: dict = {}
 
@@ -84,7 +93,7 @@ def tune(H: "kcycle.Hierarchy", u, f, kappa: int, nu1: int = 2, nu2: int = 2, om
         base = dict(best["exec"]) if best else {}
         for part in stage:
             cand = dict(base, **part)
-            if any(t["exec"] == cand for t in trials):
+            if not _relevant(cand, max(H.sizes)) or any(t["exec"] == cand for t in trials):
                 continue
             try:
                 H.set_exec(**dict(cand, poll_every=iters + 2))

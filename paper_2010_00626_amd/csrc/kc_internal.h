@@ -11,6 +11,7 @@ constexpr int MAXL = 16;          // levels per instance
 constexpr int TX = 64;            // grid-kernel tile width  (one wave64 row)
 constexpr int TY = 32;            // grid-kernel tile height
 constexpr int TS = 16;            // small-level tile side of the fused kernels
+constexpr int STRIP_BLOCK_W = 216; // columns of a streaming block (4 strips of 54)
 constexpr int GRID_THREADS = 256; // threads of the grid-wide kernels
 constexpr int HIST_CAP = 8192;    // relres history entries kept per instance
 
@@ -125,7 +126,7 @@ struct StageArgs {
     int32_t fin;              // Finalize kind of this launch's reduction
     int32_t nu;               // sweeps for fused pre/post kernels
     int32_t src, dst;         // buffer selectors for unfused kernels (0 = A, 1 = B)
-    int32_t flags;            // bit 0: fused kernels use 16 x 16 tiles (table built for that shape)
+    int32_t flags;            // fused kernels' shape: bit 0 = 16 x 16 tiles; bit 1 = streaming strips, rows 16 << bits 2-3
 };
 
 // arguments of a persistent coarse-kernel launch
@@ -170,7 +171,9 @@ enum GridKernel : int32_t {
     GK_ZERO_SELF = 22, // unfused: A[d] = 0 on the launch's own level
 };
 
-hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nblocks, hipStream_t s);
+// launches kernel k (and, when a.fin is set and with_finalize, the finalize kernel after it)
+hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nblocks, hipStream_t s, bool with_finalize = true);
+hipError_t launch_finalize(const StageArgs& a, hipStream_t s);
 hipError_t launch_subtree(bool f32, const SubArgs& a, int32_t threads, int32_t lds_bytes, hipStream_t s);
 hipError_t launch_coarsest(bool f32, const SubArgs& a, hipStream_t s);
 hipError_t prepare_subtree(bool f32, int32_t lds_bytes);

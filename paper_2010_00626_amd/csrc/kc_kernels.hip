@@ -646,6 +646,307 @@ __device__ inline void chol_solve_padded(int n, const T* Lc, const T* F, T* v, i
 }
 
 // ---------------------------------------------------------------------------
+// streaming fused kernels for large levels.  A wave owns a strip of SW output
+// columns; its 64 lanes hold the strip plus a halo (lane l is column
+// x0 - H + l) and it walks down the strip's R rows plus the halo rows.  Every
+// stage keeps the last three rows it produced in registers (a row window) and
+// produces one row per step, one row behind the stage feeding it, so each
+// input row is read from memory once; east / west neighbours come from lane
+// shuffles.  No LDS and no barriers: loads, arithmetic and stores of the many
+// resident waves overlap.  Arithmetic per point is the tile kernels' (same
+// expressions, same order), so results are identical.
+// ---------------------------------------------------------------------------
+constexpr int SW = 54;        // output columns per wave (pre-smoothing with nu <= 3 fits 64 lanes)
+constexpr int SWAVES = 4;     // strips per block, side by side
+static_assert(SW * SWAVES == STRIP_BLOCK_W, "strip geometry");
+
+template <typename T> struct Row3 {
+    T w, c, e;   // west neighbour, own column, east neighbour
+};
+
+template <typename T> __device__ __forceinline__ Row3<T> row3(T v)
+{
+    return Row3<T>{__shfl_up(v, 1, 64), v, __shfl_down(v, 1, 64)};
+}
+
+// fixed-order nine-point sum (south row first, west to east), as Sten::apply
+template <typename T>
+__device__ __forceinline__ T sten3(const Sten<T>& s, const Row3<T>& S, const Row3<T>& C, const Row3<T>& N)
+{
+    T acc = T(0);
+    acc += s.c[0] * S.w;
+    acc += s.c[1] * S.c;
+    acc += s.c[2] * S.e;
+    acc += s.c[3] * C.w;
+    acc += s.c[4] * C.c;
+    acc += s.c[5] * C.e;
+    acc += s.c[6] * N.w;
+    acc += s.c[7] * N.c;
+    acc += s.c[8] * N.e;
+    return acc;
+}
+
+// full weighting centred on window row C, as fw_sum
+template <typename T>
+__device__ __forceinline__ T fw3(const Row3<T>& S, const Row3<T>& C, const Row3<T>& N)
+{
+    const T q = T(0.25), h = T(0.5);
+    T acc = T(0);
+    acc += q * S.w;
+    acc += h * S.c;
+    acc += q * S.e;
+    acc += h * C.w;
+    acc += T(1) * C.c;
+    acc += h * C.e;
+    acc += q * N.w;
+    acc += h * N.c;
+    acc += q * N.e;
+    return acc;
+}
+
+struct Strip {
+    int inst, blk, x0, y0;
+    bool live;   // the strip has columns inside the level
+};
+
+template <int R>
+__device__ inline bool get_strip(const StageArgs& a, Strip& t)
+{
+    const int b = blockIdx.x;
+    const int i = find_inst(a.tile_off, a.count, b);
+    t.inst = i;
+    t.blk = b - a.tile_off[i];
+    const int n = a.inst[i].lev[a.depth].n;
+    const int nbx = (n + STRIP_BLOCK_W - 1) / STRIP_BLOCK_W;
+    t.x0 = ((t.blk % nbx) * SWAVES + (int)(threadIdx.x >> 6)) * SW;
+    t.y0 = (t.blk / nbx) * R;
+    t.live = t.x0 < n;
+    return a.st[i].done == 0;
+}
+
+template <typename T> struct RowF {
+    Row3<T> x;   // values of the row around this lane's column
+    T f;         // right-hand side of the row at this lane's column
+};
+
+// pre-smoothing: NU sweeps + residual + full weighting (+ input residual norm).
+// Step s reads input row i = y0 - H + s; sweep k produces row i - k, the
+// residual row i - NU - 1 and full weighting is centred on row i - NU - 2.
+// The loop body is unrolled over G = 6 steps (windows rotate with period 3,
+// row parity with period 2), so window rotation is register renaming; input
+// rows are loaded 3 steps ahead.  Steps past the strip compute rows that are
+// never stored.
+template <typename T, int NU, int R>
+__global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
+{
+    constexpr int H = NU + 1, G = 6;
+    constexpr int STEPS = R + 2 * H + 1, NG = (STEPS + G - 1) / G;
+    Strip t;
+    if (!get_strip<R>(a, t)) return;
+    const InstDev& I = a.inst[t.inst];
+    const int d = a.depth;
+    const LevelDev& Lv = I.lev[d];
+    const LevelDev& Lc = I.lev[d + 1];
+    const int n = Lv.n, nc = Lc.n;
+    const T* A = (const T*)Lv.A;
+    const T* F = (const T*)Lv.F;
+    T* B = (T*)Lv.B;
+    T* Fc = (T*)Lc.F;
+    const int lda = Lv.lda, ldf = Lv.ldf, ldb = Lv.ldb, ldc = Lc.ldf;
+    const T fs = (T)Lv.fscale;
+    Sten<T> s;
+    s.load(P<T>::s(I, d));
+    const T w = P<T>::w(I, d);
+    const bool zg = a.zg != 0, stop = a.fin == FIN_STOP;
+    const int lane = threadIdx.x & 63;
+    const int x = t.x0 - H + lane;
+    const bool col = t.live && (unsigned)x < (unsigned)n;
+    const bool own = t.live && lane >= H && lane < H + SW && (unsigned)x < (unsigned)n;
+    const bool fwc = own && (x & 1) && ((x - 1) >> 1) < nc;
+    const int ylo = t.y0, yhi = min(t.y0 + R, n);   // rows this strip stores
+    const int i0 = t.y0 - H;
+    double nrm = 0.0;
+
+    const Row3<T> z3{T(0), T(0), T(0)};
+    RowF<T> V0{z3, T(0)}, V1 = V0, V2 = V0;          // input rows i-2, i-1, i
+    RowF<T> Y[NU + 1][3];                             // Y[k]: rows after k sweeps (k >= 1)
+#pragma unroll
+    for (int k = 0; k <= NU; ++k) Y[k][0] = Y[k][1] = Y[k][2] = V0;
+    Row3<T> R0 = z3, R1 = z3, R2 = z3;                // residual rows
+
+    auto load = [&](int i, T& v, T& f) {
+        const bool in = col && (unsigned)i < (unsigned)n;
+        v = (in && !zg) ? A[(size_t)i * lda + x] : T(0);
+        f = in ? fs * F[(size_t)i * ldf + x] : T(0);
+    };
+    T pv[3], pf[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) load(i0 + u, pv[u], pf[u]);
+
+    for (int g = 0; g < NG; ++g) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int i = i0 + g * G + u;
+            const T vi = pv[u % 3], fi = pf[u % 3];
+            load(i + 3, pv[u % 3], pf[u % 3]);
+            V0 = V1;
+            V1 = V2;
+            V2 = RowF<T>{row3(vi), fi};
+#pragma unroll
+            for (int k = 1; k <= NU; ++k) {   // sweep k: row i - k
+                const int r = i - k;
+                const RowF<T>& S0 = (k == 1) ? V0 : Y[k - 1][0];
+                const RowF<T>& S1 = (k == 1) ? V1 : Y[k - 1][1];
+                const RowF<T>& S2 = (k == 1) ? V2 : Y[k - 1][2];
+                const bool in = (unsigned)r < (unsigned)n && (unsigned)x < (unsigned)n;
+                T val;
+                if (k == 1 && zg) {
+                    val = in ? w * S1.f : T(0);
+                } else {
+                    const T res = S1.f - sten3(s, S0.x, S1.x, S2.x);
+                    val = in ? S1.x.c + w * res : T(0);
+                    if (k == 1 && stop && own && r >= ylo && r < yhi) {
+                        const double rd = (double)res;
+                        nrm += rd * rd;
+                    }
+                }
+                const T fk = S1.f;
+                Y[k][0] = Y[k][1];
+                Y[k][1] = Y[k][2];
+                Y[k][2] = RowF<T>{row3(val), fk};
+            }
+            const RowF<T>& Q0 = (NU == 0) ? V0 : Y[NU][0];
+            const RowF<T>& Q1 = (NU == 0) ? V1 : Y[NU][1];
+            const RowF<T>& Q2 = (NU == 0) ? V2 : Y[NU][2];
+            {   // smoothed row i - NU (with no sweeps on a zero guess the window holds zeros)
+                const int r = i - NU;
+                if (own && r >= ylo && r < yhi) B[(size_t)r * ldb + x] = Q2.x.c;
+            }
+            {   // residual of row i - NU - 1
+                const int r = i - NU - 1;
+                const bool in = (unsigned)r < (unsigned)n && (unsigned)x < (unsigned)n;
+                const T res = Q1.f - sten3(s, Q0.x, Q1.x, Q2.x);
+                if (NU == 0 && stop && !zg && own && r >= ylo && r < yhi) {
+                    const double rd = (double)res;
+                    nrm += rd * rd;
+                }
+                R0 = R1;
+                R1 = R2;
+                R2 = row3(in ? res : T(0));
+            }
+            {   // full weighting centred on fine row c = i - NU - 2 (odd rows)
+                const int c = i - NU - 2;
+                if (((c & 1) != 0) && fwc && c >= ylo && c < yhi) {
+                    const int J = (c - 1) >> 1;
+                    if (J < nc) Fc[(size_t)J * ldc + ((x - 1) >> 1)] = fw3(R0, R1, R2);
+                }
+            }
+        }
+    }
+    if (stop) {
+        Tile tt;
+        tt.inst = t.inst;
+        tt.blk = t.blk;
+        reduce_partial(a, tt, nrm, 0.0);
+    }
+}
+
+// post-smoothing: prolong-add + NU sweeps.  Step s reads row i = y0 - H + s,
+// corrects it with the bilinear interpolant of the coarse solution and sweep
+// k produces row i - k.  A lane loads the coarse value at column
+// (x - 1) / 2 of each coarse row once (every second step) and takes the value
+// at the next coarse column from its east neighbour lane.
+template <typename T, int NU, int R>
+__global__ void __launch_bounds__(256) k_post_s(StageArgs a)
+{
+    constexpr int H = NU, G = 6;
+    constexpr int STEPS = R + 2 * H, NG = (STEPS + G - 1) / G;
+    Strip t;
+    if (!get_strip<R>(a, t)) return;
+    const InstDev& I = a.inst[t.inst];
+    const int d = a.depth;
+    const LevelDev& Lv = I.lev[d];
+    const LevelDev& Lc = I.lev[d + 1];
+    const int n = Lv.n, nc = Lc.n;
+    T* A = (T*)Lv.A;
+    const T* B = (const T*)Lv.B;
+    const T* F = (const T*)Lv.F;
+    const T* Vc = (const T*)Lc.A;
+    const int lda = Lv.lda, ldf = Lv.ldf, ldb = Lv.ldb, ldc = Lc.lda;
+    const T fs = (T)Lv.fscale;
+    Sten<T> s;
+    s.load(P<T>::s(I, d));
+    const T w = P<T>::w(I, d);
+    const int lane = threadIdx.x & 63;
+    const int x = t.x0 - H + lane;
+    const bool col = t.live && (unsigned)x < (unsigned)n;
+    const bool own = t.live && lane >= H && lane < H + SW && (unsigned)x < (unsigned)n;
+    const int ylo = t.y0, yhi = min(t.y0 + R, n);
+    const int i0 = t.y0 - H;
+    const int Is = (x - 1) >> 1;                       // coarse column west of (or at) x
+    const bool cin = t.live && (unsigned)Is < (unsigned)nc;
+    const bool xodd = (x & 1) != 0;
+
+    const Row3<T> z3{T(0), T(0), T(0)};
+    RowF<T> Y[NU + 1][3];
+#pragma unroll
+    for (int k = 0; k <= NU; ++k) Y[k][0] = Y[k][1] = Y[k][2] = RowF<T>{z3, T(0)};
+
+    auto load = [&](int i, T& v, T& f) {
+        const bool in = col && (unsigned)i < (unsigned)n;
+        v = in ? B[(size_t)i * ldb + x] : T(0);
+        f = in ? fs * F[(size_t)i * ldf + x] : T(0);
+    };
+    auto cload = [&](int J) -> T {
+        return (cin && (unsigned)J < (unsigned)nc) ? Vc[(size_t)J * ldc + Is] : T(0);
+    };
+    T pv[3], pf[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) load(i0 + u, pv[u], pf[u]);
+    // coarse rows Js = (i - 1) >> 1 and Js + 1 for the current row i: ca (west), cb (east neighbour)
+    T ca0 = cload((i0 - 1) >> 1), ca1 = cload(((i0 - 1) >> 1) + 1);
+    T cb0 = __shfl_down(ca0, 1, 64), cb1 = __shfl_down(ca1, 1, 64);
+
+    for (int g = 0; g < NG; ++g) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int i = i0 + g * G + u;
+            const T vi = pv[u % 3], fi = pf[u % 3];
+            load(i + 3, pv[u % 3], pf[u % 3]);
+            // i0 = y0 - H with y0 even, so the parity of i is that of H + u (known at compile time);
+            // an odd row starts a new coarse row pair (not at the first step: the pair is loaded)
+            if (((H + u) & 1) != 0 && (u > 0 || g > 0)) {
+                ca0 = ca1;
+                cb0 = cb1;
+                ca1 = cload((i + 1) >> 1);
+                cb1 = __shfl_down(ca1, 1, 64);
+            }
+            T e;
+            if ((i & 1) != 0) e = xodd ? ca0 : T(0.5) * (ca0 + cb0);
+            else e = xodd ? T(0.5) * (ca0 + ca1) : T(0.25) * (((ca0 + cb0) + ca1) + cb1);
+            const bool in = col && (unsigned)i < (unsigned)n;
+            const T uu = in ? vi + e : T(0);
+            Y[0][0] = Y[0][1];
+            Y[0][1] = Y[0][2];
+            Y[0][2] = RowF<T>{row3(uu), fi};
+#pragma unroll
+            for (int k = 1; k <= NU; ++k) {
+                const int r = i - k;
+                const bool rin = (unsigned)r < (unsigned)n && (unsigned)x < (unsigned)n;
+                const RowF<T>& S1 = Y[k - 1][1];
+                const T val = rin ? S1.x.c + w * (S1.f - sten3(s, Y[k - 1][0].x, S1.x, Y[k - 1][2].x)) : T(0);
+                const T fk = S1.f;
+                Y[k][0] = Y[k][1];
+                Y[k][1] = Y[k][2];
+                Y[k][2] = RowF<T>{row3(val), fk};
+            }
+            const int r = i - NU;
+            if (own && r >= ylo && r < yhi) A[(size_t)r * lda + x] = Y[NU][2].x.c;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // persistent coarse kernel: one workgroup runs whole calls of the cycle on the
 // coarse levels of one instance, every level resident in LDS.  Each level d has
 // three (n+2) x (n+2) arrays with a zero ring (two sweep buffers and F), so no
@@ -1253,19 +1554,38 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// tile shape of a grid launch: flags bit 0 set = 16 x 16 tiles (small levels), else 64 x 32
+// shape of a fused grid launch (flags): bit 1 = streaming strips with R = 16 << ((flags >> 2) & 3)
+// rows, else bit 0 = 16 x 16 tiles, else 64 x 32 tiles
 template <typename T, int NU>
 static void pre_shape(const StageArgs& a, int nb, hipStream_t s)
 {
-    if (a.flags & 1) k_pre<T, NU, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a);
-    else k_pre<T, NU, TX, TY><<<nb, GRID_THREADS, 0, s>>>(a);
+    if (a.flags & 2) {
+        switch ((a.flags >> 2) & 3) {
+        case 0: k_pre_s<T, NU, 16><<<nb, 256, 0, s>>>(a); break;
+        case 1: k_pre_s<T, NU, 32><<<nb, 256, 0, s>>>(a); break;
+        default: k_pre_s<T, NU, 64><<<nb, 256, 0, s>>>(a); break;
+        }
+    } else if (a.flags & 1) {
+        k_pre<T, NU, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a);
+    } else {
+        k_pre<T, NU, TX, TY><<<nb, GRID_THREADS, 0, s>>>(a);
+    }
 }
 
 template <typename T, int NU>
 static void post_shape(const StageArgs& a, int nb, hipStream_t s)
 {
-    if (a.flags & 1) k_post<T, NU, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a);
-    else k_post<T, NU, TX, TY><<<nb, GRID_THREADS, 0, s>>>(a);
+    if (a.flags & 2) {
+        switch ((a.flags >> 2) & 3) {
+        case 0: k_post_s<T, NU, 16><<<nb, 256, 0, s>>>(a); break;
+        case 1: k_post_s<T, NU, 32><<<nb, 256, 0, s>>>(a); break;
+        default: k_post_s<T, NU, 64><<<nb, 256, 0, s>>>(a); break;
+        }
+    } else if (a.flags & 1) {
+        k_post<T, NU, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a);
+    } else {
+        k_post<T, NU, TX, TY><<<nb, GRID_THREADS, 0, s>>>(a);
+    }
 }
 
 template <typename T>
@@ -1334,7 +1654,14 @@ static hipError_t launch_driver(GridKernel k, const StageArgs& a, int nb, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nb, hipStream_t s)
+hipError_t launch_finalize(const StageArgs& a, hipStream_t s)
+{
+    if (a.fin == FIN_NONE) return hipSuccess;
+    k_finalize<<<a.count, GRID_THREADS, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nb, hipStream_t s, bool with_finalize)
 {
     if (nb <= 0) return hipSuccess;
     hipError_t e;
@@ -1349,9 +1676,8 @@ hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nb, h
         e = f32 ? launch_driver<true>(k, a, nb, s) : launch_driver<false>(k, a, nb, s);
         break;
     }
-    if (e != hipSuccess || a.fin == FIN_NONE) return e;
-    k_finalize<<<a.count, GRID_THREADS, 0, s>>>(a);
-    return hipGetLastError();
+    if (e != hipSuccess || !with_finalize) return e;
+    return launch_finalize(a, s);
 }
 
 hipError_t launch_subtree(bool f32, const SubArgs& a, int32_t threads, int32_t lds_bytes, hipStream_t s)

@@ -183,6 +183,9 @@ struct Layout {
 
 int tiles_of(int n) { return ((n + TX - 1) / TX) * ((n + TY - 1) / TY); }
 int tiles_small(int n) { return ((n + TS - 1) / TS) * ((n + TS - 1) / TS); }
+// streaming blocks: STRIP_BLOCK_W columns x R rows, R = 16 << code
+int strip_rows_code(int n) { return n >= 4095 ? 2 : (n >= 2047 ? 1 : 0); }
+int tiles_stream(int n, int code) { return ((n + STRIP_BLOCK_W - 1) / STRIP_BLOCK_W) * ((n + (16 << code) - 1) / (16 << code)); }
 
 kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Layout& lay)
 {
@@ -206,7 +209,7 @@ kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Lay
         int L;
         kc_status st = check_problem(probs[i], L);
         if (st != KC_OK) return st;
-        tiles0 += std::max(tiles_of(probs[i].n), tiles_small(probs[i].n));   // either tile shape at depth 0
+        tiles0 += std::max(std::max(tiles_of(probs[i].n), tiles_small(probs[i].n)), tiles_stream(probs[i].n, 0));   // any shape at depth 0
     }
     lay.total_tiles0 = tiles0;
     lay.partial = take(sizeof(double) * 2 * (size_t)tiles0);
@@ -312,7 +315,9 @@ struct kc_hier {
     std::vector<std::vector<int32_t>> tiles;   // host copies of the tile tables
     std::vector<std::vector<int32_t>> lists;   // host copies of the instance lists
     int max_cut = 0, max_L = 0;
-    int small[MAXL] = {};                      // fused grid kernels at depth d use 16 x 16 tiles
+    int shape[MAXL] = {};                      // StageArgs::flags of the fused grid kernels at depth d
+    bool compacted = false;                    // the tables cover only the instances still iterating
+    int last_compactions = 0;                  // table compactions during the last driver call
     int sub_lds = 0;
     std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> graphs;
     double omega_set = -1.0;
@@ -365,7 +370,7 @@ Launch grid(kc_hier* h, GridKernel gk, bool f32, int table, int depth)
 Launch fused_grid(kc_hier* h, GridKernel gk, bool f32, int d)
 {
     Launch L = grid(h, gk, f32, tt_cut(d), d);
-    L.sa.flags = h->small[d];
+    L.sa.flags = h->shape[d];
     return L;
 }
 
@@ -494,6 +499,44 @@ void count_launches(const std::vector<Launch>& ls, int64_t& grid_n, int64_t& sub
     }
 }
 
+// tile prefix tables and instance lists of every stage, over the instances
+// marked in `active` (all when null): a finished instance can be left out of
+// the launches altogether, its blocks would only check its stop flag and exit
+kc_status build_tables(kc_hier* h, const std::vector<char>* active)
+{
+    const int cnt = h->count;
+    h->tiles.assign(1 + 2 * MAXL, std::vector<int32_t>(cnt + 1, 0));
+    h->lists.assign(2 * MAXL, std::vector<int32_t>());
+    for (int i = 0; i < cnt; ++i) {
+        if (active && !(*active)[i]) continue;
+        const HostInst& hi = h->hi[i];
+        const int L = hi.il.L;
+        h->tiles[tt_all0()][i + 1] = tiles_of(hi.il.n[0]);
+        for (int d = 0; d < MAXL; ++d) {
+            const int sh = h->shape[d];
+            const int tc = (sh & 2) ? tiles_stream(hi.il.n[d], (sh >> 2) & 3)
+                                    : ((sh & 1) ? tiles_small(hi.il.n[d]) : tiles_of(hi.il.n[d]));
+            h->tiles[tt_cut(d)][i + 1] = (d < L && hi.cut > d) ? tc : 0;
+            h->tiles[tt_lvl(d)][i + 1] = (d < L - 1) ? tiles_of(hi.il.n[d]) : 0;
+            if (hi.cut == d && d < L) h->lists[lt_sub(d)].push_back(i);
+            if (L - 1 == d) h->lists[lt_coarse(d)].push_back(i);
+        }
+    }
+    for (auto& t : h->tiles)
+        for (int i = 0; i < cnt; ++i) t[i + 1] += t[i];
+    std::vector<int32_t> flat((size_t)(1 + 2 * MAXL) * (cnt + 1));
+    for (size_t t = 0; t < h->tiles.size(); ++t) std::copy(h->tiles[t].begin(), h->tiles[t].end(), flat.begin() + t * (cnt + 1));
+    std::vector<int32_t> lflat((size_t)2 * MAXL * cnt, 0);
+    for (size_t t = 0; t < h->lists.size(); ++t) std::copy(h->lists[t].begin(), h->lists[t].end(), lflat.begin() + t * cnt);
+    h->compacted = active != nullptr;
+    if (h->d_tiles) {
+        HIPCHK(hipMemcpyAsync(h->d_tiles, flat.data(), flat.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->d_lists, lflat.data(), lflat.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    return KC_OK;
+}
+
 // ---------------------------------------------------------------------------
 // execution plan (depends on the exec options): cut depths, op lists, LDS
 // ---------------------------------------------------------------------------
@@ -546,37 +589,19 @@ kc_status plan_exec(kc_hier* h)
             return fail(KC_ERR_ARG, "coarse cutover needs " + std::to_string(h->sub_lds) + " B of LDS, device allows " +
                                         std::to_string(maxl));
     }
-    // tables
     const int cnt = h->count;
-    h->tiles.assign(1 + 2 * MAXL, std::vector<int32_t>(cnt + 1, 0));
-    h->lists.assign(2 * MAXL, std::vector<int32_t>());
     for (int d = 0; d < MAXL; ++d) {
         int maxn = 0;
         for (int i = 0; i < cnt; ++i)
             if (d < h->hi[i].il.L && h->hi[i].cut > d) maxn = std::max(maxn, h->hi[i].il.n[d]);
-        h->small[d] = (maxn > 0 && maxn <= h->ex.small_tile_n) ? 1 : 0;
+        int f = 0;
+        if (maxn > 0 && h->ex.stream_n > 0 && maxn >= h->ex.stream_n) f = 2 | (strip_rows_code(maxn) << 2);
+        else if (maxn > 0 && maxn <= h->ex.small_tile_n) f = 1;
+        h->shape[d] = f;
     }
-    for (int i = 0; i < cnt; ++i) {
-        const HostInst& hi = h->hi[i];
-        const int L = hi.il.L;
-        h->tiles[tt_all0()][i + 1] = tiles_of(hi.il.n[0]);
-        for (int d = 0; d < MAXL; ++d) {
-            const int tc = h->small[d] ? tiles_small(hi.il.n[d]) : tiles_of(hi.il.n[d]);
-            h->tiles[tt_cut(d)][i + 1] = (d < L && hi.cut > d) ? tc : 0;
-            h->tiles[tt_lvl(d)][i + 1] = (d < L - 1) ? tiles_of(hi.il.n[d]) : 0;
-            if (hi.cut == d && d < L) h->lists[lt_sub(d)].push_back(i);
-            if (L - 1 == d) h->lists[lt_coarse(d)].push_back(i);
-        }
-    }
-    for (auto& t : h->tiles)
-        for (int i = 0; i < cnt; ++i) t[i + 1] += t[i];
-    std::vector<int32_t> flat((size_t)(1 + 2 * MAXL) * (cnt + 1));
-    for (size_t t = 0; t < h->tiles.size(); ++t) std::copy(h->tiles[t].begin(), h->tiles[t].end(), flat.begin() + t * (cnt + 1));
-    std::vector<int32_t> lflat((size_t)2 * MAXL * cnt, 0);
-    for (size_t t = 0; t < h->lists.size(); ++t) std::copy(h->lists[t].begin(), h->lists[t].end(), lflat.begin() + t * cnt);
+    kc_status st = build_tables(h, nullptr);
+    if (st != KC_OK) return st;
     if (h->d_tiles) {
-        HIPCHK(hipMemcpyAsync(h->d_tiles, flat.data(), flat.size() * 4, hipMemcpyHostToDevice, h->stream));
-        HIPCHK(hipMemcpyAsync(h->d_lists, lflat.data(), lflat.size() * 4, hipMemcpyHostToDevice, h->stream));
         for (int i = 0; i < cnt; ++i) {
             const HostInst& hi = h->hi[i];
             HIPCHK(hipMemcpyAsync(h->ws + hi.il.ops, hi.ops.data(), hi.ops.size() * 4, hipMemcpyHostToDevice, h->stream));
@@ -790,6 +815,7 @@ kc_status drive(kc_hier* h, int drv, const kc_cycle_params& c, int maxit, int32_
 {
     HIPCHK(hipEventRecord(h->t0, h->stream));
     int launched = 0;
+    h->last_compactions = 0;
     int batch = h->ex.poll_every > 0 ? h->ex.poll_every : 2;
     std::vector<double> prev_rel(h->count, -1.0);
     std::vector<int> prev_it(h->count, 0);
@@ -827,6 +853,23 @@ kc_status drive(kc_hier* h, int drv, const kc_cycle_params& c, int maxit, int32_
         }
         if (all) break;
         if (h->ex.poll_every <= 0) batch = std::max(1, std::min(256, (int)std::ceil(need * 0.9)));
+        if (h->count > 1) {   // drop finished instances from the launches once they are half of them
+            std::vector<char> act(h->count, 0);
+            int64_t live = 0;
+            for (int i = 0; i < h->count; ++i)
+                if (!h->h_st[i].done) { act[i] = 1; live += tiles_of(h->hi[i].il.n[0]); }
+            if (2 * live <= (int64_t)ntiles(h, tt_all0())) {
+                kc_status s3 = build_tables(h, &act);
+                if (s3 != KC_OK) return s3;
+                drop_graphs(h);
+                ++h->last_compactions;
+            }
+        }
+    }
+    if (h->compacted) {   // later calls start from every instance again
+        kc_status s3 = build_tables(h, nullptr);
+        if (s3 != KC_OK) return s3;
+        drop_graphs(h);
     }
     HIPCHK(hipEventRecord(h->t1, h->stream));
     HIPCHK(hipEventSynchronize(h->t1));
@@ -890,6 +933,92 @@ void record_counts(kc_hier* h, int drv, const kc_cycle_params& c)
     h->last_sub_stages = st;
 }
 
+
+// ---------------------------------------------------------------------------
+// per-launch profile of one driver iteration: kernel names as the compiler
+// emits them (so they match a profiler's), algorithmic bytes and flops
+// ---------------------------------------------------------------------------
+constexpr double FL_SWEEP = 20.0;     // 9 mul + 8 add + sub + mul + add per point
+constexpr double FL_RESID = 18.0;     // 9 mul + 8 add + sub
+constexpr double FL_FW = 17.0;        // 9 mul + 8 add per coarse point
+constexpr double FL_PROLONG = 3.0;    // average over injected, edge and centre points
+
+std::string launch_name(const kc_hier* h, const Launch& L)
+{
+    const char* T = L.f32 ? "float" : "double";
+    if (L.type == L_SUB) return std::string("k_subtree<") + T + ", " + std::to_string(L.threads) + ">";
+    if (L.type == L_COARSEST) return std::string("k_coarsest<") + T + ">";
+    if (L.gk == GK_PRE || L.gk == GK_POST) {
+        const std::string k = L.gk == GK_PRE ? "k_pre" : "k_post";
+        const std::string nu = std::to_string(L.sa.nu);
+        if (L.sa.flags & 2) return k + "_s<" + T + ", " + nu + ", " + std::to_string(16 << ((L.sa.flags >> 2) & 3)) + ">";
+        if (L.sa.flags & 1) return k + "<" + T + ", " + nu + ", 16, 16>";
+        return k + "<" + T + ", " + nu + ", 64, 32>";
+    }
+    if (L.gk <= GK_NORM || L.gk == GK_ZERO_SELF) return std::string("k_unfused<") + T + ", " + std::to_string(L.gk) + ">";
+    return std::string("k_driver<") + (L.f32 ? "true" : "false") + ", " + std::to_string(L.gk) + ">";
+    (void)h;
+}
+
+// algorithmic bytes and flops of one launch (every input read once, every output written once)
+void launch_work(const kc_hier* h, const Launch& L, double& bytes, double& flops)
+{
+    bytes = flops = 0.0;
+    const double T = L.f32 ? 4.0 : 8.0;
+    if (L.type == L_SUB) {
+        for (int idx : h->lists[lt_sub(L.ba.depth)]) {
+            const HostInst& hi = h->hi[idx];
+            const double nt = hi.il.n[L.ba.depth];
+            bytes += 2.0 * nt * nt * T;
+            auto add_list = [&](int k) {
+                const int kk = std::min(k, KMAX);
+                for (int o = 0; o < hi.ops_len[kk - 1]; ++o) {
+                    const uint32_t op = hi.ops[hi.ops_beg[kk - 1] + o];
+                    const double n = hi.il.n[sop_depth(op)], n2 = n * n;
+                    if (sop_kind(op) == SOP_PRE) {
+                        const double nc = (n - 1) / 2;
+                        const double sw = L.ba.nu1 > 0 ? (sop_zg(op) ? 1.0 + FL_SWEEP * (L.ba.nu1 - 1) : FL_SWEEP * L.ba.nu1) : 0.0;
+                        flops += n2 * (sw + FL_RESID) + nc * nc * FL_FW;
+                    } else if (sop_kind(op) == SOP_POST) {
+                        flops += n2 * (FL_PROLONG + FL_SWEEP * L.ba.nu2);
+                    } else {
+                        flops += 2.0 * n2 * n2;   // triangular solves with the dense factor
+                    }
+                }
+            };
+            add_list(L.ba.kappa);
+            if (L.ba.pair && L.ba.kappa > 1) add_list(L.ba.kappa - 1);
+        }
+        return;
+    }
+    if (L.type == L_COARSEST) return;
+    const int d = L.sa.depth;
+    for (int i = 0; i < h->count; ++i) {
+        const HostInst& hi = h->hi[i];
+        if (L.gk == GK_PRE || L.gk == GK_POST) {
+            if (hi.cut <= d) continue;
+            const double nf = hi.il.n[d], nc = hi.il.n[d + 1];
+            bytes += (3.0 * nf * nf + nc * nc) * T;
+            flops += (L.gk == GK_PRE) ? nf * nf * (FL_SWEEP * L.sa.nu + FL_RESID) + nc * nc * FL_FW
+                                      : nf * nf * (FL_PROLONG + FL_SWEEP * L.sa.nu);
+            continue;
+        }
+        const double n0 = hi.il.n[0], N = n0 * n0;
+        switch (L.gk) {
+        case GK_IR_RESID: bytes += N * 20.0; break;          // read u, f; write the FP32 right-hand side
+        case GK_IR_UPDATE: bytes += N * 20.0; break;         // read e (FP32) and u; write u
+        case GK_SSF: bytes += N * 8.0; break;
+        case GK_PCG_INIT: bytes += N * 24.0; break;          // read f; write u, r
+        case GK_PCG_PRECIN: bytes += N * (L.f32 ? 12.0 : 0.0); break;
+        case GK_PCG_RZ: bytes += N * (L.f32 ? 20.0 : 24.0); break;
+        case GK_PCG_P: bytes += N * 24.0; break;
+        case GK_PCG_AP: bytes += N * 16.0; break;
+        case GK_PCG_UPD: bytes += N * 48.0; break;
+        default: break;
+        }
+    }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -907,6 +1036,7 @@ void kc_exec_default(kc_exec* e)
     e->coarse_threads = 512;
     e->poll_every = 0;
     e->coarse_wave_n = 15;
+    e->stream_n = 2047;
 }
 
 const char* kc_status_string(kc_status s)
@@ -964,6 +1094,7 @@ static kc_status validate_exec(const kc_exec* e)
     if (e->poll_every < 0) return fail(KC_ERR_ARG, "poll_every must be >= 0");
     if (e->coarse_wave_n < 0 || e->coarse_wave_n > 15) return fail(KC_ERR_ARG, "coarse_wave_n must be in 0..15");
     if (e->small_tile_n < 0 || e->small_tile_n > 4095) return fail(KC_ERR_ARG, "small_tile_n must be in 0..4095");
+    if (e->stream_n < 0) return fail(KC_ERR_ARG, "stream_n must be >= 0");
     if (e->coarse_threads * 8 < 64 * e->coarse_cutover) return fail(KC_ERR_ARG, "coarse_threads too small for the cutover");
     return KC_OK;
 }
@@ -1409,6 +1540,106 @@ kc_status kc_time_cycles(kc_hier* h, double* const* d_v, const int64_t* ldv, con
     return leave(h);
 }
 
+kc_status kc_profile_iteration(kc_hier* h, int32_t driver, const kc_cycle_params* c, int32_t reps, char* out, size_t cap)
+{
+    if (!h || !out || cap == 0 || reps < 1) return fail(KC_ERR_ARG, "bad argument");
+    if (driver != 0 && driver != 1) return fail(KC_ERR_ARG, "driver must be 0 (stand-alone) or 1 (pcg)");
+    const bool want_pcg = driver == 1;
+    if (h->last_driver.empty() || (h->last_driver.rfind("pcg", 0) == 0) != want_pcg)
+        return fail(KC_ERR_STATE, want_pcg ? "run kc_pcg on this hierarchy first" : "run kc_solve on this hierarchy first");
+    kc_status s;
+    if ((s = prepare_call(h, c)) != KC_OK) return s;
+    if ((s = enter(h)) != KC_OK) return s;
+    const bool f32 = h->prec == KC_F32_CYCLE;
+    if ((s = upload_inst(h)) != KC_OK) return s;
+    if ((s = upload_state(h, 0.0, 1 << 30)) != KC_OK) return s;   // tol 0: every instance stays active
+    {
+        Launch L0 = want_pcg ? grid(h, GK_PCG_INIT, f32, tt_all0(), 0) : grid(h, GK_SSF, f32, tt_all0(), 0);
+        L0.sa.fin = want_pcg ? FIN_PCG_INIT : FIN_SSF;
+        HIPCHK(launch_grid(L0.gk, L0.f32, L0.sa, L0.nblocks, h->stream));
+    }
+    const int drv = want_pcg ? DRV_PCG : (f32 ? DRV_IR : DRV_SOLVE64);
+    std::vector<Launch> ls;
+    iteration(h, drv, *c, ls);
+    // each launch of the iteration repeated `reps` times back to back between
+    // two events (then its finalize step likewise), in iteration order
+    std::vector<hipEvent_t> ev(3 * ls.size(), nullptr);
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    std::vector<double> t_main(ls.size(), 0.0), t_fin(ls.size(), 0.0);
+    hipError_t err = run(h, ls);   // warm-up iteration
+    for (size_t k = 0; k < ls.size() && err == hipSuccess; ++k) {
+        const Launch& L = ls[k];
+        err = hipEventRecord(ev[3 * k], h->stream);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) {
+            if (L.type == L_GRID) err = launch_grid(L.gk, L.f32, L.sa, L.nblocks, h->stream, false);
+            else if (L.type == L_SUB) err = launch_subtree(L.f32, L.ba, L.threads, L.lds, h->stream);
+            else err = launch_coarsest(L.f32, L.ba, h->stream);
+        }
+        if (err == hipSuccess) err = hipEventRecord(ev[3 * k + 1], h->stream);
+        for (int r = 0; r < reps && err == hipSuccess; ++r)
+            if (L.type == L_GRID && L.nblocks > 0) err = launch_finalize(L.sa, h->stream);
+        if (err == hipSuccess) err = hipEventRecord(ev[3 * k + 2], h->stream);
+    }
+    if (err == hipSuccess) err = hipStreamSynchronize(h->stream);
+    for (size_t k = 0; k < ls.size() && err == hipSuccess; ++k) {
+        float a = 0.f, b = 0.f;
+        err = hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
+        if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
+        t_main[k] = a;   // ms of `reps` repetitions
+        t_fin[k] = b;
+    }
+    struct Agg { int launches = 0; double ms = 0.0, bytes = 0.0, flops = 0.0; };
+    std::map<std::string, Agg> agg;
+    std::vector<std::string> order;
+    std::string seq;
+    double total = 0.0;
+    for (size_t k = 0; k < ls.size(); ++k) {
+        const Launch& L = ls[k];
+        const bool empty = (L.type == L_GRID) ? L.nblocks <= 0 : L.ba.count <= 0;
+        if (empty) continue;
+        const std::string nm = launch_name(h, L);
+        double b, f;
+        launch_work(h, L, b, f);
+        if (!agg.count(nm)) order.push_back(nm);
+        Agg& A = agg[nm];
+        A.launches += 1;
+        A.ms += t_main[k] / reps;
+        A.bytes += b;
+        A.flops += f;
+        total += t_main[k] / reps;
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "%s[\"%s\", %d, %.5f]", seq.empty() ? "" : ", ", nm.c_str(),
+                      L.type == L_GRID ? L.sa.depth : L.ba.depth, t_main[k] / reps);
+        seq += buf;
+        if (L.type == L_GRID && L.sa.fin != FIN_NONE) {
+            if (!agg.count("k_finalize")) order.push_back("k_finalize");
+            Agg& F = agg["k_finalize"];
+            F.launches += 1;
+            F.ms += t_fin[k] / reps;
+            total += t_fin[k] / reps;
+        }
+    }
+    std::string js = "{\"driver\": \"" + std::string(want_pcg ? "pcg" : (f32 ? "solve_ir_f32" : "solve_f64")) + "\"";
+    char buf[256];
+    std::snprintf(buf, sizeof buf, ", \"reps\": %d, \"iteration_ms\": %.6f, \"kernels\": [", reps, total);
+    js += buf;
+    bool first = true;
+    for (const std::string& nm : order) {
+        const Agg& A = agg[nm];
+        std::snprintf(buf, sizeof buf,
+                      "%s{\"name\": \"%s\", \"launches\": %d, \"ms\": %.6f, \"avg_ms\": %.6f, \"bytes_per_launch\": %.1f, "
+                      "\"flops_per_launch\": %.1f}",
+                      first ? "" : ", ", nm.c_str(), A.launches, A.ms, A.ms / A.launches, A.bytes / A.launches,
+                      A.flops / A.launches);
+        js += buf;
+        first = false;
+    }
+    js += "], \"sequence\": [" + seq + "]}";
+    if (js.size() + 1 > cap) return fail(KC_ERR_ARG, "profile buffer too small");
+    std::memcpy(out, js.c_str(), js.size() + 1);
+    return leave(h);
+}
+
 kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
 {
     if (!h || !out || cap == 0) return fail(KC_ERR_ARG, "null argument");
@@ -1421,6 +1652,7 @@ kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
     js += ", \"coarse_threads\": " + std::to_string(h->ex.coarse_threads);
     js += ", \"coarse_wave_n\": " + std::to_string(h->ex.coarse_wave_n);
     js += ", \"small_tile_n\": " + std::to_string(h->ex.small_tile_n);
+    js += ", \"stream_n\": " + std::to_string(h->ex.stream_n);
     js += ", \"subtree_lds_bytes\": " + std::to_string(h->sub_lds);
     js += ", \"workspace_bytes\": " + std::to_string(h->lay.total);
     js += ", \"driver\": \"" + h->last_driver + "\"";
@@ -1428,6 +1660,7 @@ kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
     js += ", \"subtree_launches_per_iteration\": " + std::to_string(h->last_sub);
     js += ", \"subtree_stages_per_iteration\": " + std::to_string(h->last_sub_stages);
     js += ", \"iterations_launched\": " + std::to_string(h->last_launched);
+    js += ", \"compactions\": " + std::to_string(h->last_compactions);
     js += ", \"max_iterations\": " + std::to_string(h->last_cycles);
     char buf[64];
     std::snprintf(buf, sizeof buf, "%.6f", h->last_ms);

@@ -46,7 +46,7 @@ class CycleParams(C.Structure):
 class Exec(C.Structure):
     _fields_ = [("mode", C.c_int32), ("use_graph", C.c_int32), ("coarse_cutover", C.c_int32),
                 ("coarse_threads", C.c_int32), ("poll_every", C.c_int32), ("coarse_wave_n", C.c_int32),
-                ("small_tile_n", C.c_int32), ("reserved", C.c_int32)]
+                ("small_tile_n", C.c_int32), ("stream_n", C.c_int32)]
 
 
 _lib = None
@@ -78,6 +78,7 @@ def lib():
         L.kc_level_stencils.argtypes = [P(Problem), i32, P(i32), P(dbl)]
         L.kc_schedule_counts.argtypes = [P(Problem), i32, P(Exec), P(CycleParams), P(i64), P(i64), P(i64)]
         L.kc_stats.argtypes = [vp, C.c_char_p, sz]
+        L.kc_profile_iteration.argtypes = [vp, i32, P(CycleParams), i32, C.c_char_p, sz]
         L.kc_time_stage.argtypes = [vp, i32, P(CycleParams), i32, P(dbl), P(dbl)]
         L.kc_time_cycles.argtypes = arr + [P(CycleParams), i32, P(dbl)]
         L.kc_status_string.argtypes = [i32]
@@ -86,7 +87,7 @@ def lib():
         L.kc_last_error.restype = C.c_char_p
         for name in ("kc_workspace_bytes", "kc_create", "kc_destroy", "kc_set_exec", "kc_cycle", "kc_solve",
                      "kc_pcg", "kc_apply_A", "kc_residual_history", "kc_grad_params", "kc_level_stencils", "kc_schedule_counts",
-                     "kc_stats", "kc_time_stage", "kc_time_cycles"):
+                     "kc_stats", "kc_time_stage", "kc_time_cycles", "kc_profile_iteration"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -100,7 +101,7 @@ def _check(status: int, allow_positive: bool = False) -> int:
 
 def exec_options(mode: int | str = 0, use_graph: bool = True, coarse_cutover: int = 31,
                  coarse_threads: int = 512, poll_every: int = 0, coarse_wave_n: int = 15,
-                 small_tile_n: int = 0) -> Exec:
+                 small_tile_n: int = 0, stream_n: int = 2047) -> Exec:
     e = Exec()
     lib().kc_exec_default(C.byref(e))
     e.mode = {"fused": 0, "paper": 1}.get(mode, mode) if isinstance(mode, str) else int(mode)
@@ -110,6 +111,7 @@ def exec_options(mode: int | str = 0, use_graph: bool = True, coarse_cutover: in
     e.poll_every = int(poll_every)
     e.coarse_wave_n = int(coarse_wave_n)
     e.small_tile_n = int(small_tile_n)
+    e.stream_n = int(stream_n)
     return e
 
 
@@ -284,6 +286,14 @@ class Hierarchy:
         ms = C.c_double()
         _check(lib().kc_time_cycles(self._h, pv, lv, pf, lf, C.byref(c), int(reps), C.byref(ms)))
         return ms.value
+
+    def profile_iteration(self, driver: str = "solve", kappa=1, nu1=2, nu2=2, omega=0.8, reps=5) -> dict:
+        """Per-kernel times of one solver iteration ("solve" or "pcg"; that
+        driver must have run last on this hierarchy, whose arrays keep iterating)."""
+        c = self._params(kappa, nu1, nu2, omega)
+        buf = C.create_string_buffer(1 << 20)
+        _check(lib().kc_profile_iteration(self._h, 1 if driver == "pcg" else 0, C.byref(c), int(reps), buf, len(buf)))
+        return json.loads(buf.value.decode())
 
     def stats(self) -> dict:
         buf = C.create_string_buffer(1 << 16)

@@ -119,6 +119,57 @@ def test_small_tile_option(n, kappa, small):
     assert np.array_equal(host(u), u_ref)
 
 
+STREAM_CASES = [
+    # n, kappa, nu1, nu2, stream_n
+    (255, 2, 2, 2, 63),
+    (511, 3, 1, 1, 127),
+    (255, 1, 3, 3, 31),
+    (127, 2, 0, 2, 15),
+    (511, 2 ** 31 - 1, 2, 1, 255),
+]
+
+
+@pytest.mark.parametrize("n,kappa,nu1,nu2,stream", STREAM_CASES)
+def test_stream_kernels_one_cycle(n, kappa, nu1, nu2, stream):
+    """Streaming strip kernels on every level >= stream_n give the oracle's bits."""
+    banner(f"streaming n={n} kappa={kappa} nu={nu1}+{nu2} stream_n={stream}")
+    rng = np.random.default_rng(n * 3 + kappa)
+    th, ep = 0.35, 5e-3
+    v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
+    H = K().Hierarchy([(n, th, ep)], exec=dict(stream_n=stream))
+    v = dev(v0)
+    H.cycle(v, dev(f), kappa=kappa, nu1=nu1, nu2=nu2)
+    ref = O.Hierarchy(n, th, ep).cycle(v0, f, kappa=min(kappa, 64), nu1=nu1, nu2=nu2)[0]
+    assert np.array_equal(host(v), ref)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_stream_kernels_solve_and_batch(prec):
+    """Stop-test norms from the streaming kernel, FP32 refinement and ragged batches."""
+    banner(f"streaming solve + batch prec={prec}")
+    specs = [(511, 0.3, 1e-3), (127, 1.2, 1e-2), (255, 2.0, 1e-4)]
+    rng = np.random.default_rng(11)
+    fs = [inputs.uniform_rhs(rng, s[0]) for s in specs]
+    Hb = K().Hierarchy(specs, prec, exec=dict(stream_n=63))
+    us = [torch.zeros((s[0], s[0]), dtype=torch.float64, device="cuda") for s in specs]
+    iters, relres, status = Hb.solve(us, [dev(f) for f in fs], kappa=2, tol=1e-7, maxit=3000)
+    assert status == [0] * len(specs)
+    for k, (sp, f) in enumerate(zip(specs, fs)):
+        Ho = O.Hierarchy(*sp)
+        if prec == "f64":
+            u_ref, rc, it_ref, hist = Ho.solve(f, kappa=2, tol=1e-7, maxit=3000)
+            check_stop_margin(hist, 1e-7)
+            assert iters[k] == it_ref, k
+            assert np.array_equal(host(us[k]), u_ref), k
+        else:
+            Hs = K().Hierarchy([sp], prec, exec=dict(stream_n=0))
+            u1 = torch.zeros_like(us[k])
+            it1, rr1, st1 = Hs.solve(u1, dev(f), kappa=2, tol=1e-7, maxit=3000)
+            assert st1 == [0] and it1[0] == iters[k] and torch.equal(u1, us[k]), k
+            true_rel = np.linalg.norm(f - Ho.apply(host(us[k]))) / np.linalg.norm(f)
+            assert true_rel < 1.01e-7
+
+
 def check_stop_margin(hist, tol):
     """No relative residual of the run lies within 1e-12 (relative) of tol."""
     h = np.asarray(hist)
@@ -285,3 +336,51 @@ def test_deterministic_rerun():
         outs.append((it[0], rr[0], host(u)))
     assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
     assert np.array_equal(outs[0][2], outs[1][2])
+
+
+@pytest.mark.parametrize("prec,driver", [("f64", "solve"), ("f32", "solve"), ("f64", "pcg")])
+def test_profile_iteration_covers_every_launch(prec, driver):
+    """The per-launch profile lists every launch of one iteration once."""
+    banner(f"profile iteration prec={prec} driver={driver}")
+    n = 255
+    f = inputs.uniform_rhs(np.random.default_rng(4), n)
+    H = K().Hierarchy([(n, 0.5, 1e-3)], prec)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    run = H.pcg if driver == "pcg" else H.solve
+    run(u, dev(f), kappa=2, nu1=1, nu2=1, tol=1e-6, maxit=200)
+    st = H.stats()
+    prof = H.profile_iteration(driver, kappa=2, nu1=1, nu2=1, reps=3)
+    ks = prof["kernels"]
+    launches = sum(k["launches"] for k in ks if k["name"] != "k_finalize")
+    assert launches == st["grid_launches_per_iteration"] + st["subtree_launches_per_iteration"]
+    assert abs(sum(k["ms"] for k in ks) - prof["iteration_ms"]) <= 1e-5 * (len(ks) + prof["iteration_ms"])
+    assert all(k["avg_ms"] > 0 for k in ks)
+    assert any(k["name"].startswith("k_subtree") for k in ks)
+    assert all(k["bytes_per_launch"] > 0 for k in ks if k["name"].startswith(("k_pre", "k_post")))
+    assert all(k["flops_per_launch"] > 0 for k in ks if k["name"].startswith("k_subtree"))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_compaction_keeps_results(prec):
+    """Finished instances dropped from the launches mid-solve: every instance's
+    iterate and count equal its stand-alone solve."""
+    banner(f"batch compaction prec={prec}")
+    specs = [(255, 0.7, 0.5), (255, 1.9, 0.4), (255, 2.5, 0.6), (127, 0.3, 2e-3), (255, 1.1, 1e-3)]
+    rng = np.random.default_rng(12)
+    fs = [inputs.uniform_rhs(rng, s[0]) for s in specs]
+    Hb = K().Hierarchy(specs, prec)
+    us = [torch.zeros((s[0], s[0]), dtype=torch.float64, device="cuda") for s in specs]
+    iters, relres, status = Hb.solve(us, [dev(f) for f in fs], kappa=2, tol=1e-9, maxit=4000)
+    assert status == [0] * len(specs)
+    assert Hb.stats()["compactions"] >= 1
+    assert max(iters) > 2 * min(iters)
+    for k, (sp, f) in enumerate(zip(specs, fs)):
+        Hs = K().Hierarchy([sp], prec)
+        u1 = torch.zeros_like(us[k])
+        it1, _, st1 = Hs.solve(u1, dev(f), kappa=2, tol=1e-9, maxit=4000)
+        assert st1 == [0] and it1[0] == iters[k] and torch.equal(u1, us[k]), k
+    # a second solve on the same handle starts from the full tables again
+    for x in us:
+        x.zero_()
+    iters2, _, status2 = Hb.solve(us, [dev(f) for f in fs], kappa=2, tol=1e-9, maxit=4000)
+    assert iters2 == iters and status2 == status
