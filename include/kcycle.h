@@ -100,6 +100,10 @@ typedef struct {
     int32_t stream_n;       /* fused grid kernels on levels whose largest n >= this stream row strips through
                                registers instead of staging tiles in LDS (0 = never; default 2047); results do
                                not depend on it */
+    int32_t wave_regs;      /* 1 = whole calls on the levels wave 0 runs alone (n <= coarse_wave_n) run in
+                               registers (instances with n_coarsest = 1; default 1); 0 = phase by phase in LDS;
+                               results do not depend on it */
+    int32_t reserved[3];
 } kc_exec;
 
 typedef struct kc_hier kc_hier;

@@ -97,21 +97,26 @@ enum Finalize : int32_t {
 
 // persistent coarse kernel operations
 enum SubOp : uint32_t {
+    SOP_WCALL = 0,    // a whole call (counter k) on a level that wave 0 runs in registers
     SOP_PRE = 1,      // nu1 sweeps (zero guess flag) + residual + full weighting to depth+1
     SOP_POST = 2,     // prolong-add from depth+1 + nu2 sweeps
     SOP_SOLVE = 3,    // coarsest direct solve
 };
 // op word: kind (bits 0-1) | depth (2-5) | zero-guess flag (6) | lg = log2(n + 1)
-// of the level (7-9) | LDS element offset of the level's three arrays (10-31)
-__host__ __device__ inline uint32_t sop_make(uint32_t op, uint32_t depth, uint32_t zg, uint32_t lg, uint32_t off)
+// of the level (7-9) | counter k of a register call (10-14) | LDS element
+// offset of the level's three arrays (15-31)
+constexpr uint32_t SOP_KMAX = 31, SOP_OFFMAX = (1u << 17) - 1;
+__host__ __device__ inline uint32_t sop_make(uint32_t op, uint32_t depth, uint32_t zg, uint32_t lg, uint32_t off,
+                                             uint32_t k = 0)
 {
-    return op | (depth << 2) | (zg << 6) | (lg << 7) | (off << 10);
+    return op | (depth << 2) | (zg << 6) | (lg << 7) | (k << 10) | (off << 15);
 }
 __host__ __device__ inline int sop_kind(uint32_t w) { return (int)(w & 3u); }
 __host__ __device__ inline int sop_depth(uint32_t w) { return (int)((w >> 2) & 15u); }
 __host__ __device__ inline bool sop_zg(uint32_t w) { return ((w >> 6) & 1u) != 0; }
 __host__ __device__ inline int sop_lg(uint32_t w) { return (int)((w >> 7) & 7u); }
-__host__ __device__ inline int sop_off(uint32_t w) { return (int)(w >> 10); }
+__host__ __device__ inline int sop_k(uint32_t w) { return (int)((w >> 10) & 31u); }
+__host__ __device__ inline int sop_off(uint32_t w) { return (int)(w >> 15); }
 
 // arguments of a grid-wide stage launch
 struct StageArgs {

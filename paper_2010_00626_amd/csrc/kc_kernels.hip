@@ -1209,6 +1209,249 @@ __device__ __forceinline__ void ph_sweep_zg1(clds<T> x, lds<T> y, clds<T> F, cld
     ph_sweep<T, N, NB>(x, y, F, sc, om, t, true);
 }
 
+// ---------------------------------------------------------------------------
+// register engine: a whole call on a level that wave 0 runs alone (n <= 15),
+// with every coarser level of that call, held in registers.  Level N uses
+// bands of B = N + 1 lanes: lane b B + c is column c of rows b U .. b U + U - 1
+// (U = 4 for N = 15, else 1); column N and rows >= N are the zero ring.
+// East / west neighbours come from DPP row shifts (a band never straddles a
+// 16-lane DPP row, and the lane across a band edge holds a ring zero), north /
+// south ones across bands from lane permutes; restriction and prolongation
+// gather between the layouts of two levels with lane permutes.  No LDS access
+// and no synchronisation inside the call; arithmetic as in the LDS phases.
+// ---------------------------------------------------------------------------
+constexpr int DPP_WEST = 0x111;   // row_shr:1 -> value of lane - 1 (0 at a row start)
+constexpr int DPP_EAST = 0x101;   // row_shl:1 -> value of lane + 1 (0 at a row end)
+
+template <int CTRL> __device__ __forceinline__ float dpp(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int N> struct WL {
+    static constexpr int B = N + 1, U = (N == 15) ? 4 : 1, LOGB = (N == 15) ? 4 : (N == 7) ? 3 : (N == 3) ? 2 : 1;
+};
+
+template <typename T> struct WRow {   // one row around a lane: west, centre, east
+    T w, c, e;
+};
+template <typename T> __device__ __forceinline__ WRow<T> wrow(T v)
+{
+    return WRow<T>{dpp<DPP_WEST>(v), v, dpp<DPP_EAST>(v)};
+}
+
+// rows -1 .. U of this lane's band for a level of size N, from the lane's U values
+template <typename T, int N>
+__device__ __forceinline__ void wwin(const T (&v)[WL<N>::U], WRow<T> (&r)[WL<N>::U + 2])
+{
+    constexpr int B = WL<N>::B, U = WL<N>::U;
+    const int lane = threadIdx.x & 63;
+    const T s = __shfl_up(v[U - 1], B, 64);     // last row of the band below
+    const T n = __shfl_down(v[0], B, 64);       // first row of the band above
+    r[0] = wrow(lane >= B ? s : T(0));
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u + 1] = wrow(v[u]);
+    r[U + 1] = wrow(n);
+}
+
+template <typename T>
+__device__ __forceinline__ T wsten(const T (&s)[9], const WRow<T>& S, const WRow<T>& C, const WRow<T>& N)
+{
+    T acc = T(0);
+    acc += s[0] * S.w;
+    acc += s[1] * S.c;
+    acc += s[2] * S.e;
+    acc += s[3] * C.w;
+    acc += s[4] * C.c;
+    acc += s[5] * C.e;
+    acc += s[6] * N.w;
+    acc += s[7] * N.c;
+    acc += s[8] * N.e;
+    return acc;
+}
+
+template <int N> __device__ __forceinline__ bool wvalid(int u)
+{
+    const int lane = threadIdx.x & 63;
+    const int b = lane >> WL<N>::LOGB, c = lane & (WL<N>::B - 1);
+    return b * WL<N>::U + u < N && c < N;
+}
+
+// stencils and Jacobi weights of the levels below a register call, relative depth 0 = the call's level
+template <typename T> struct WPar {
+    T s[4][9];
+    T w[4];
+    T chol;   // coarsest 1 x 1 factor
+    int nu1, nu2;
+};
+
+template <typename T, int N>
+__device__ __forceinline__ void wsweep(T (&v)[WL<N>::U], const T (&f)[WL<N>::U], const T (&s)[9], T om, bool zg)
+{
+    constexpr int U = WL<N>::U;
+    T nv[U];
+    if (zg) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) nv[u] = wvalid<N>(u) ? om * f[u] : T(0);
+    } else {
+        WRow<T> r[U + 2];
+        wwin<T, N>(v, r);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            nv[u] = wvalid<N>(u) ? r[u + 1].c + om * (f[u] - wsten(s, r[u], r[u + 1], r[u + 2])) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = nv[u];
+}
+
+template <typename T, int N, int REL>
+__device__ __forceinline__ void wcycle(T (&v)[WL<N>::U], const T (&f)[WL<N>::U], int k, bool zg, const WPar<T>& P)
+{
+    constexpr int U = WL<N>::U, B = WL<N>::B;
+    const int lane = threadIdx.x & 63;
+    if constexpr (N == 1) {
+        // direct solve of the 1 x 1 level (Cholesky factor L: v = (f / L) / L); ignores the input v
+        T x = f[0] / P.chol;
+        x = x / P.chol;
+        v[0] = (lane == 0) ? x : T(0);
+        (void)k;
+        (void)zg;
+        (void)B;
+    } else {
+        constexpr int NC = (N - 1) / 2, BC = WL<NC>::B;
+        static_assert(WL<NC>::U == 1, "coarse levels of a register call hold one row per band");
+        const T(&s)[9] = P.s[REL];
+        const T om = P.w[REL];
+        // pre-smoothing
+        for (int q = 0; q < P.nu1; ++q) wsweep<T, N>(v, f, s, om, zg && q == 0);
+        if (zg && P.nu1 == 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = T(0);
+        }
+        // residual and its full weighting (kept at every fine point; the centres are gathered)
+        T r[U];
+        {
+            WRow<T> w[U + 2];
+            wwin<T, N>(v, w);
+#pragma unroll
+            for (int u = 0; u < U; ++u) r[u] = wvalid<N>(u) ? f[u] - wsten(s, w[u], w[u + 1], w[u + 2]) : T(0);
+        }
+        T fw[U];
+        {
+            WRow<T> w[U + 2];
+            wwin<T, N>(r, w);
+            const T qq = T(0.25), hh = T(0.5);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                T acc = T(0);
+                acc += qq * w[u].w;
+                acc += hh * w[u].c;
+                acc += qq * w[u].e;
+                acc += hh * w[u + 1].w;
+                acc += T(1) * w[u + 1].c;
+                acc += hh * w[u + 1].e;
+                acc += qq * w[u + 2].w;
+                acc += hh * w[u + 2].c;
+                acc += qq * w[u + 2].e;
+                fw[u] = acc;
+            }
+        }
+        T fc[1], vc[1];
+        {
+            const int J = lane >> WL<NC>::LOGB, I = lane & (BC - 1);
+            const bool cval = J < NC && I < NC;
+            const int jf = 2 * J + 1, cf = 2 * I + 1;
+            const int src = cval ? (jf / U) * B + cf : 0;
+            T g = __shfl(fw[0], src, 64);
+            if constexpr (U == 4) {
+                const T g3 = __shfl(fw[3], src, 64);
+                const T g1 = __shfl(fw[1], src, 64);
+                g = ((jf & 3) == 1) ? g1 : g3;
+            }
+            fc[0] = cval ? g : T(0);
+            vc[0] = T(0);
+        }
+        wcycle<T, NC, REL + 1>(vc, fc, k, true, P);
+        if (k > 1) wcycle<T, NC, REL + 1>(vc, fc, k - 1, false, P);
+        // prolongation: coarse value (J, I) lives on lane J BC + I of the coarse layout
+        {
+            const int b = lane >> WL<N>::LOGB, c = lane & (B - 1);
+            const int Is = (c - 1) >> 1;
+            const bool io = (c & 1) != 0;
+            auto cv = [&](int J, int I) -> T {
+                const bool ok = J >= 0 && I >= 0;
+                const T x = __shfl(vc[0], ok ? J * BC + I : 0, 64);
+                return ok ? x : T(0);
+            };
+            // coarse rows (j - 1) >> 1 and the one above for the band's rows
+            constexpr int NR = (U == 4) ? 3 : 2;
+            T a0[NR], a1[NR];
+            const int J0 = (U == 4) ? 2 * b - 1 : (b - 1) >> 1;
+#pragma unroll
+            for (int m = 0; m < NR; ++m) {
+                a0[m] = cv(J0 + m, Is);
+                a1[m] = cv(J0 + m, Is + 1);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = b * U + u;
+                const int m = ((j - 1) >> 1) - J0;   // row index of (j - 1) >> 1 in a0 / a1
+                const T A0 = a0[m < 0 ? 0 : (m >= NR ? NR - 1 : m)], A1 = a1[m < 0 ? 0 : (m >= NR ? NR - 1 : m)];
+                const int m1 = (m + 1 >= NR) ? NR - 1 : m + 1;
+                const T C0 = a0[m1 < 0 ? 0 : m1], C1 = a1[m1 < 0 ? 0 : m1];
+                T e;
+                if (j & 1) e = io ? A0 : T(0.5) * (A0 + A1);
+                else e = io ? T(0.5) * (A0 + C0) : T(0.25) * (((A0 + A1) + C0) + C1);
+                v[u] = wvalid<N>(u) ? v[u] + e : T(0);
+            }
+        }
+        for (int q = 0; q < P.nu2; ++q) wsweep<T, N>(v, f, s, om, false);
+    }
+}
+
+// a register call on level d (size N) of the persistent kernel: f (and v
+// unless zg) from the level's LDS arrays, the result back to buffer `cb`
+template <typename T, int N>
+__device__ __noinline__ void wcall_level(lds<T> vbuf, clds<T> fbuf, clds<T> sd, clds<T> wd, clds<T> chol, int nu1,
+                                         int nu2, int k, bool zg)
+{
+    constexpr int U = WL<N>::U, P = N + 2;
+    const int lane = threadIdx.x & 63;
+    const int b = lane >> WL<N>::LOGB, c = lane & (WL<N>::B - 1);
+    WPar<T> par;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) par.s[l][q] = sd[l * 9 + q];
+        par.w[l] = wd[l];
+    }
+    par.chol = chol[0];
+    par.nu1 = nu1;
+    par.nu2 = nu2;
+    T v[U], f[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = b * U + u;
+        const bool ok = j < N && c < N;
+        const int q = ok ? (j + 1) * P + c + 1 : 0;
+        f[u] = ok ? fbuf[q] : T(0);
+        v[u] = (ok && !zg) ? vbuf[q] : T(0);
+    }
+    wcycle<T, N, 0>(v, f, k, zg, par);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = b * U + u;
+        if (j < N && c < N) vbuf[(j + 1) * P + c + 1] = v[u];
+    }
+}
+
 template <typename T, int THREADS>
 struct Sub {
     T* sm;
@@ -1301,6 +1544,24 @@ struct Sub {
         sync_lg(lg);
     }
 
+    // a whole call on level d in registers (wave 0); the result goes to the level's current buffer
+    __device__ __forceinline__ void wcall(int d, int lg, int off, int k, bool zg)
+    {
+        const lds<T> vb = to_lds<T>(bufp(off, lg, (cur >> d) & 1));
+        const clds<T> fb = to_lds<T>((const T*)bufp(off, lg, 2));
+        const clds<T> sd = to_lds<T>(&pp->s[d][0]);
+        const clds<T> wd = to_lds<T>(&pp->w[d]);
+        const clds<T> ch = to_lds<T>(&pp->chol[0]);
+        switch (lg) {
+        case 4: wcall_level<T, 15>(vb, fb, sd, wd, ch, nu1, nu2, k, zg); break;
+        case 3: wcall_level<T, 7>(vb, fb, sd, wd, ch, nu1, nu2, k, zg); break;
+        case 2: wcall_level<T, 3>(vb, fb, sd, wd, ch, nu1, nu2, k, zg); break;
+        case 1: wcall_level<T, 1>(vb, fb, sd, wd, ch, nu1, nu2, k, zg); break;
+        default: break;
+        }
+        wave_sync();
+    }
+
     // waves that skip a wave-0 operation still follow its buffer swaps
     __device__ __forceinline__ void skip(int kind, int d, bool zg)
     {
@@ -1330,7 +1591,8 @@ struct Sub {
                 __syncthreads();
                 pending = false;
             }
-            if (kind == SOP_PRE) pre(d, lg, off, zg);
+            if (kind == SOP_WCALL) wcall(d, lg, off, sop_k(op), zg);
+            else if (kind == SOP_PRE) pre(d, lg, off, zg);
             else if (kind == SOP_POST) post(d, lg, off);
             else solve(d, lg, off);
             if (sg || (kind == SOP_PRE && single_lg(lg - 1))) pending = true;

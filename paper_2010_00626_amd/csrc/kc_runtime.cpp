@@ -274,17 +274,22 @@ int lg_of(int n)
     return lg;
 }
 
-// op list of one call at depth d with counter k (Algorithm 3), levels in LDS
-void gen_sub_call(const HostInst& h, int d, int k, bool zg, std::vector<uint32_t>& out)
+// op list of one call at depth d with counter k (Algorithm 3), levels in LDS;
+// a call on a level of at most reg_n points per side becomes one register call
+void gen_sub_call(const HostInst& h, int d, int k, bool zg, int reg_n, std::vector<uint32_t>& out)
 {
     const uint32_t lg = (uint32_t)lg_of(h.il.n[d]), off = (uint32_t)h.lds_off[d];
+    if (h.il.n[d] <= reg_n) {
+        out.push_back(sop_make(SOP_WCALL, d, zg ? 1 : 0, lg, off, (uint32_t)std::min<int>(k, SOP_KMAX)));
+        return;
+    }
     if (d == h.il.L - 1) {
         out.push_back(sop_make(SOP_SOLVE, d, 0, lg, off));
         return;
     }
     out.push_back(sop_make(SOP_PRE, d, zg ? 1 : 0, lg, off));
-    gen_sub_call(h, d + 1, k, true, out);
-    if (k > 1) gen_sub_call(h, d + 1, k - 1, false, out);
+    gen_sub_call(h, d + 1, k, true, reg_n, out);
+    if (k > 1) gen_sub_call(h, d + 1, k - 1, false, reg_n, out);
     out.push_back(sop_make(SOP_POST, d, 0, lg, off));
 }
 
@@ -565,12 +570,15 @@ kc_status plan_exec(kc_hier* h)
                 off += 3 * (hi.il.n[d] + 2) * (hi.il.n[d] + 2);
             }
         }
+        if (off > (int)SOP_OFFMAX) return fail(KC_ERR_ARG, "coarse levels too large for the op encoding");
+        // levels wave 0 runs alone go to registers (the register engine's coarsest solve is 1 x 1)
+        const int reg_n = (h->ex.wave_regs && hi.p.n_coarsest == 1) ? std::min(h->ex.coarse_wave_n, 15) : 0;
         hi.ops.clear();
         for (int k = 1; k <= KMAX; ++k) {
             hi.ops_beg[k - 1] = (int)hi.ops.size();
             if (cut < L) {
                 const int below = L - cut;
-                if (k <= below + 1 || k == 1) gen_sub_call(hi, cut, k, false, hi.ops);
+                if (k <= below + 1 || k == 1) gen_sub_call(hi, cut, k, false, reg_n, hi.ops);
                 else {   // same as the W-cycle list
                     hi.ops_beg[k - 1] = hi.ops_beg[below];
                     hi.ops_len[k - 1] = hi.ops_len[below];
@@ -1037,6 +1045,7 @@ void kc_exec_default(kc_exec* e)
     e->poll_every = 0;
     e->coarse_wave_n = 15;
     e->stream_n = 2047;
+    e->wave_regs = 1;
 }
 
 const char* kc_status_string(kc_status s)
@@ -1095,6 +1104,7 @@ static kc_status validate_exec(const kc_exec* e)
     if (e->coarse_wave_n < 0 || e->coarse_wave_n > 15) return fail(KC_ERR_ARG, "coarse_wave_n must be in 0..15");
     if (e->small_tile_n < 0 || e->small_tile_n > 4095) return fail(KC_ERR_ARG, "small_tile_n must be in 0..4095");
     if (e->stream_n < 0) return fail(KC_ERR_ARG, "stream_n must be >= 0");
+    if (e->wave_regs != 0 && e->wave_regs != 1) return fail(KC_ERR_ARG, "wave_regs must be 0 or 1");
     if (e->coarse_threads * 8 < 64 * e->coarse_cutover) return fail(KC_ERR_ARG, "coarse_threads too small for the cutover");
     return KC_OK;
 }
@@ -1653,6 +1663,7 @@ kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
     js += ", \"coarse_wave_n\": " + std::to_string(h->ex.coarse_wave_n);
     js += ", \"small_tile_n\": " + std::to_string(h->ex.small_tile_n);
     js += ", \"stream_n\": " + std::to_string(h->ex.stream_n);
+    js += ", \"wave_regs\": " + std::to_string(h->ex.wave_regs);
     js += ", \"subtree_lds_bytes\": " + std::to_string(h->sub_lds);
     js += ", \"workspace_bytes\": " + std::to_string(h->lay.total);
     js += ", \"driver\": \"" + h->last_driver + "\"";

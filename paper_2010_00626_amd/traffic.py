@@ -1,8 +1,8 @@
 """HBM traffic per kernel launch from rocprofv3 counters.
 
 Run mode (the program rocprofv3 profiles): a device copy of a known size,
-then one solve of the 1023^2 stand-alone workload with the given precision,
-kappa and execution options.  Profile it once per counter, e.g.
+then a fixed number of iterations of the 1023^2 stand-alone solve with the
+given precision, kappa and execution options.  Profile it once per counter, e.g.
 
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR_F -- python3 -m paper_2010_00626_amd.traffic run ...
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR_W -- python3 -m paper_2010_00626_amd.traffic run ...
@@ -75,7 +75,8 @@ def run(args) -> None:
     f = torch.from_numpy(inst.f).to("cuda")
     u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
     kappa = kcycle.KAPPA_W if args.kappa == "W" else int(args.kappa)
-    it, rr, st = H.solve(u, f, kappa=kappa, nu1=w.nu1, nu2=w.nu2, omega=w.omega, tol=w.tol, maxit=8000)
+    # a fixed number of iterations: counter collection serialises every dispatch
+    it, rr, st = H.solve(u, f, kappa=kappa, nu1=w.nu1, nu2=w.nu2, omega=w.omega, tol=0.0, maxit=args.cycles)
     torch.cuda.synchronize()
     print(json.dumps({"iterations": it[0], "relres": rr[0], "status": st[0]}), flush=True)
 
@@ -146,6 +147,7 @@ def main(argv=None):
     r.add_argument("--precision", default="f32")
     r.add_argument("--kappa", default="2")
     r.add_argument("--exec", default="", help="JSON execution options")
+    r.add_argument("--cycles", type=int, default=20)
     s = sub.add_parser("summarise")
     s.add_argument("dir_fetch")
     s.add_argument("dir_write")

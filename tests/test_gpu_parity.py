@@ -384,3 +384,41 @@ def test_batch_compaction_keeps_results(prec):
         x.zero_()
     iters2, _, status2 = Hb.solve(us, [dev(f) for f in fs], kappa=2, tol=1e-9, maxit=4000)
     assert iters2 == iters and status2 == status
+
+
+REG_CASES = [
+    # n, kappa, nu1, nu2, cutover, wave_n, precision
+    (255, 2, 2, 2, 15, 15, "f64"),
+    (255, 3, 1, 1, 31, 7, "f64"),
+    (127, 2 ** 31 - 1, 2, 1, 31, 3, "f64"),
+    (255, 1, 0, 3, 63, 15, "f64"),
+    (511, 4, 3, 0, 31, 15, "f64"),
+    (255, 2, 2, 2, 15, 15, "f32"),
+    (255, 3, 1, 2, 31, 7, "f32"),
+]
+
+
+@pytest.mark.parametrize("n,kappa,nu1,nu2,cut,wave_n,prec", REG_CASES)
+def test_register_calls_match_lds_phases(n, kappa, nu1, nu2, cut, wave_n, prec):
+    """Whole calls of the small levels in registers give the bits of the
+    phase-by-phase LDS execution (and, in FP64, of the oracle)."""
+    banner(f"register calls n={n} kappa={kappa} nu={nu1}+{nu2} cut={cut} wave_n={wave_n} {prec}")
+    rng = np.random.default_rng(n + 17 * kappa)
+    th, ep = 1.3, 2e-3
+    f = rng.uniform(-1, 1, (n, n))
+    res = []
+    for regs in (1, 0):
+        H = K().Hierarchy([(n, th, ep)], prec, exec=dict(coarse_cutover=cut, coarse_wave_n=wave_n, wave_regs=regs,
+                                                         coarse_threads=512))
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        it, rr, st = H.solve(u, dev(f), kappa=kappa, nu1=nu1, nu2=nu2, tol=1e-6, maxit=400)
+        assert st == [0]
+        res.append((it[0], host(u)))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1])
+    if prec == "f64":
+        u_ref, rc, it_ref, hist = O.Hierarchy(n, th, ep).solve(f, kappa=min(kappa, 64), nu1=nu1, nu2=nu2, tol=1e-6,
+                                                                maxit=400)
+        check_stop_margin(hist, 1e-6)
+        assert res[0][0] == it_ref
+        assert np.array_equal(res[0][1], u_ref)
