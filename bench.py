@@ -202,20 +202,23 @@ def main():
     fine = {"kernel": "fine-level pre-smoothing", "avg_us": round(ms_pre * 1e3, 2),
             "GB_s": round(bytes_pre / (ms_pre * 1e-3) / 1e9, 1), "bytes_per_launch": bytes_pre}
 
-    # run-time model (Section 3) fitted to the sweep's per-cycle times and the kappa it predicts
+    # run-time model (Section 3) fitted to the sweep's per-cycle times and the kappa it predicts.
+    # A call of the fused schedule is a grid launch or a stage (pre, post or solve op) of the
+    # persistent kernel: each is one serialised step whose cost is the model's alpha.
     model_info = None
     if per:
         rows = []
         for key, d in per.items():
             r = d[best_p]
             k = kcycle.KAPPA_W if key == "W" else int(key)
-            calls = r["grid_launches_per_cycle"] + r["persistent_launches_per_cycle"]
+            calls = r["grid_launches_per_cycle"] + r["persistent_stages_per_cycle"]
             rows.append((key, calls, model.n_ops_2d(k, levels), r["ms_per_cycle"]))
         fitted = model.fit(rows)
         cyc = {row[0]: per[row[0]][best_p]["cycles"] for row in rows}
         pred = {row[0]: fitted.predict(row[1], row[2]) * cyc[row[0]] for row in rows}
-        model_info = {"alpha_ms": fitted.alpha, "beta_ms": fitted.beta,
+        model_info = {"alpha_ms": fitted.alpha, "beta_ms": fitted.beta, "calls": "grid launches + persistent stages",
                       "predicted_best_kappa": min(pred, key=pred.get),
+                      "predicted_solve_ms": {k: round(v, 2) for k, v in pred.items()},
                       "measured_best_kappa": "W" if best_k == kcycle.KAPPA_W else str(best_k),
                       "rel_errors": {k: round(v, 4) for k, v in fitted.rel_errors.items()}}
 

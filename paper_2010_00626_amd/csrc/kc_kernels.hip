@@ -67,15 +67,54 @@ template <typename T> struct Sten {
 
 __device__ inline bool inside(int j, int i, int n) { return (unsigned)j < (unsigned)n && (unsigned)i < (unsigned)n; }
 
+// Loads whose result may be masked read a clamped (always valid) address and
+// select afterwards: a load inside a branch makes the compiler wait for it at
+// the branch's end, which serialises loads that could all be in flight.
+__device__ __forceinline__ int clampi(int v, int n) { return min(max(v, 0), n - 1); }
+
+
+// Arrays reached through the instance table are global memory, but a pointer
+// loaded from memory is generic to the compiler, which then emits FLAT
+// accesses; those count against the LDS wait counter as well, so every wait
+// for a lane shuffle or LDS access would also wait for all loads in flight.
+// The kernels therefore convert them to global-address-space pointers.
+template <typename T> using gp = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gp<T> glob(void* p) { return (gp<T>)p; }
+template <typename T> __device__ __forceinline__ gp<const T> glob(const void* p) { return (gp<const T>)p; }
+
+template <typename T>
+__device__ inline T gload(gp<const T> p, int ld, int n, int j, int i)
+{
+    const T v = p[(size_t)clampi(j, n) * ld + clampi(i, n)];
+    return inside(j, i, n) ? v : T(0);
+}
+
 template <typename T>
 __device__ inline T gload(const T* p, int ld, int n, int j, int i)
 {
-    return inside(j, i, n) ? p[(size_t)j * ld + i] : T(0);
+    const T v = p[(size_t)clampi(j, n) * ld + clampi(i, n)];
+    return inside(j, i, n) ? v : T(0);
 }
 
 // stencil sum reading global memory with zero outside the grid
 template <typename T>
 __device__ inline T gapply(const Sten<T>& s, const T* x, int ld, int n, int j, int i)
+{
+    T acc = T(0);
+    acc += s.c[0] * gload(x, ld, n, j - 1, i - 1);
+    acc += s.c[1] * gload(x, ld, n, j - 1, i);
+    acc += s.c[2] * gload(x, ld, n, j - 1, i + 1);
+    acc += s.c[3] * gload(x, ld, n, j, i - 1);
+    acc += s.c[4] * gload(x, ld, n, j, i);
+    acc += s.c[5] * gload(x, ld, n, j, i + 1);
+    acc += s.c[6] * gload(x, ld, n, j + 1, i - 1);
+    acc += s.c[7] * gload(x, ld, n, j + 1, i);
+    acc += s.c[8] * gload(x, ld, n, j + 1, i + 1);
+    return acc;
+}
+
+template <typename T>
+__device__ inline T gapply(const Sten<T>& s, gp<const T> x, int ld, int n, int j, int i)
 {
     T acc = T(0);
     acc += s.c[0] * gload(x, ld, n, j - 1, i - 1);
@@ -424,15 +463,18 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
     const int d = a.depth;
     const LevelDev& Lv = I.lev[d];
     const int n = Lv.n;
-    const T* A = (const T*)Lv.A;
-    T* B = (T*)Lv.B;
-    const T* F = (const T*)Lv.F;
+    const gp<const T> A = glob<T>((const void*)Lv.A);
+    const gp<T> B = glob<T>(Lv.B);
+    const gp<const T> F = glob<T>((const void*)Lv.F);
     const T fs = (T)Lv.fscale;
     const int rx0 = t.x0 - H, ry0 = t.y0 - H;
     Sten<T> s;
     s.load(P<T>::s(I, d));
     const T w = P<T>::w(I, d);
     const bool zg = a.zg != 0;
+    // a zero guess reads no estimate: F, with its own leading dimension, is a valid stand-in address
+    const gp<const T> Av = zg ? F : A;
+    const size_t ldav = zg ? (size_t)Lv.ldf : (size_t)Lv.lda;
 
     {   // every load of the region in flight before the LDS stores
         constexpr int NR = RH * RW, NPT = (NR + GRID_THREADS - 1) / GRID_THREADS;
@@ -443,8 +485,11 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
             const int rj = p / RW, ri = p - rj * RW;
             const int j = ry0 + rj, i = rx0 + ri;
             const bool in = p < NR && inside(j, i, n);
-            fa[k] = in ? fs * F[(size_t)j * Lv.ldf + i] : T(0);
-            va[k] = (in && !zg) ? A[(size_t)j * Lv.lda + i] : T(0);
+            const size_t jc = (size_t)clampi(j, n), ic = (size_t)clampi(i, n);
+            const T lf = F[jc * Lv.ldf + ic];
+            const T lv = Av[jc * ldav + ic];
+            fa[k] = in ? fs * lf : T(0);
+            va[k] = (in && !zg) ? lv : T(0);
         }
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
@@ -504,7 +549,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
     {
         const LevelDev& Lc = I.lev[d + 1];
         const int nc = Lc.n, ldc = Lc.ldf;
-        T* Fc = (T*)Lc.F;
+        const gp<T> Fc = glob<T>(Lc.F);
         for (int p = threadIdx.x; p < (TX / 2) * (TY / 2); p += GRID_THREADS) {
             const int Ic = (t.x0 >> 1) + (p % (TX / 2)), Jc = (t.y0 >> 1) + (p / (TX / 2));
             if (Ic >= nc || Jc >= nc) continue;
@@ -534,10 +579,10 @@ __global__ void __launch_bounds__(GRID_THREADS) k_post(StageArgs a)
     const LevelDev& Lv = I.lev[d];
     const LevelDev& Lc = I.lev[d + 1];
     const int n = Lv.n, nc = Lc.n, ldc = Lc.lda;
-    T* A = (T*)Lv.A;
-    const T* B = (const T*)Lv.B;
-    const T* F = (const T*)Lv.F;
-    const T* Vc = (const T*)Lc.A;
+    const gp<T> A = glob<T>(Lv.A);
+    const gp<const T> B = glob<T>((const void*)Lv.B);
+    const gp<const T> F = glob<T>((const void*)Lv.F);
+    const gp<const T> Vc = glob<T>((const void*)Lc.A);
     const T fs = (T)Lv.fscale;
     const int rx0 = t.x0 - H, ry0 = t.y0 - H;
     const int cx0 = (rx0 - 1) >> 1, cy0 = (ry0 - 1) >> 1;
@@ -555,14 +600,18 @@ __global__ void __launch_bounds__(GRID_THREADS) k_post(StageArgs a)
             const int rj = p / RW, ri = p - rj * RW;
             const int j = ry0 + rj, i = rx0 + ri;
             const bool in = p < NR && inside(j, i, n);
-            fa[k] = in ? fs * F[(size_t)j * Lv.ldf + i] : T(0);
-            va[k] = in ? B[(size_t)j * Lv.ldb + i] : T(0);
+            const size_t jc = (size_t)clampi(j, n), ic = (size_t)clampi(i, n);
+            const T lf = F[jc * Lv.ldf + ic];
+            const T lv = B[jc * Lv.ldb + ic];
+            fa[k] = in ? fs * lf : T(0);
+            va[k] = in ? lv : T(0);
         }
 #pragma unroll
         for (int k = 0; k < NPC; ++k) {
             const int p = threadIdx.x + k * GRID_THREADS;
             const int cj = p / CW, ci = p - cj * CW;
-            ca[k] = (p < NC) ? gload(Vc, ldc, nc, cy0 + cj, cx0 + ci) : T(0);
+            const T cv = gload(Vc, ldc, nc, cy0 + cj, cx0 + ci);
+            ca[k] = (p < NC) ? cv : T(0);
         }
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
@@ -748,10 +797,10 @@ __global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
     const LevelDev& Lv = I.lev[d];
     const LevelDev& Lc = I.lev[d + 1];
     const int n = Lv.n, nc = Lc.n;
-    const T* A = (const T*)Lv.A;
-    const T* F = (const T*)Lv.F;
-    T* B = (T*)Lv.B;
-    T* Fc = (T*)Lc.F;
+    const gp<const T> A = glob<T>((const void*)Lv.A);
+    const gp<const T> F = glob<T>((const void*)Lv.F);
+    const gp<T> B = glob<T>(Lv.B);
+    const gp<T> Fc = glob<T>(Lc.F);
     const int lda = Lv.lda, ldf = Lv.ldf, ldb = Lv.ldb, ldc = Lc.ldf;
     const T fs = (T)Lv.fscale;
     Sten<T> s;
@@ -774,10 +823,15 @@ __global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
     for (int k = 0; k <= NU; ++k) Y[k][0] = Y[k][1] = Y[k][2] = V0;
     Row3<T> R0 = z3, R1 = z3, R2 = z3;                // residual rows
 
+    // raw rows from clamped (always valid) addresses, masked when they become current;
+    // a zero guess reads no estimate (F, with its own leading dimension, stands in)
+    const gp<const T> Av = zg ? F : A;
+    const size_t ldav = zg ? (size_t)ldf : (size_t)lda;
+    const size_t xc = (size_t)clampi(x, n);
     auto load = [&](int i, T& v, T& f) {
-        const bool in = col && (unsigned)i < (unsigned)n;
-        v = (in && !zg) ? A[(size_t)i * lda + x] : T(0);
-        f = in ? fs * F[(size_t)i * ldf + x] : T(0);
+        const size_t ic = (size_t)clampi(i, n);
+        v = Av[ic * ldav + xc];
+        f = F[ic * ldf + xc];
     };
     T pv[3], pf[3];
 #pragma unroll
@@ -787,8 +841,10 @@ __global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int i = i0 + g * G + u;
-            const T vi = pv[u % 3], fi = pf[u % 3];
+            const T rv = pv[u % 3], rf = pf[u % 3];
             load(i + 3, pv[u % 3], pf[u % 3]);
+            const bool rin = col && (unsigned)i < (unsigned)n;
+            const T vi = (rin && !zg) ? rv : T(0), fi = rin ? fs * rf : T(0);
             V0 = V1;
             V1 = V2;
             V2 = RowF<T>{row3(vi), fi};
@@ -868,10 +924,10 @@ __global__ void __launch_bounds__(256) k_post_s(StageArgs a)
     const LevelDev& Lv = I.lev[d];
     const LevelDev& Lc = I.lev[d + 1];
     const int n = Lv.n, nc = Lc.n;
-    T* A = (T*)Lv.A;
-    const T* B = (const T*)Lv.B;
-    const T* F = (const T*)Lv.F;
-    const T* Vc = (const T*)Lc.A;
+    const gp<T> A = glob<T>(Lv.A);
+    const gp<const T> B = glob<T>((const void*)Lv.B);
+    const gp<const T> F = glob<T>((const void*)Lv.F);
+    const gp<const T> Vc = glob<T>((const void*)Lc.A);
     const int lda = Lv.lda, ldf = Lv.ldf, ldb = Lv.ldb, ldc = Lc.lda;
     const T fs = (T)Lv.fscale;
     Sten<T> s;
@@ -892,34 +948,42 @@ __global__ void __launch_bounds__(256) k_post_s(StageArgs a)
 #pragma unroll
     for (int k = 0; k <= NU; ++k) Y[k][0] = Y[k][1] = Y[k][2] = RowF<T>{z3, T(0)};
 
+    // raw rows from clamped (always valid) addresses, masked when they become current
+    const size_t xc = (size_t)clampi(x, n), Ic = (size_t)clampi(Is, nc);
     auto load = [&](int i, T& v, T& f) {
-        const bool in = col && (unsigned)i < (unsigned)n;
-        v = in ? B[(size_t)i * ldb + x] : T(0);
-        f = in ? fs * F[(size_t)i * ldf + x] : T(0);
+        const size_t ic = (size_t)clampi(i, n);
+        v = B[ic * ldb + xc];
+        f = F[ic * ldf + xc];
     };
-    auto cload = [&](int J) -> T {
-        return (cin && (unsigned)J < (unsigned)nc) ? Vc[(size_t)J * ldc + Is] : T(0);
-    };
+    auto craw = [&](int J) -> T { return Vc[(size_t)clampi(J, nc) * ldc + Ic]; };
+    auto cmask = [&](int J, T v) -> T { return (cin && (unsigned)J < (unsigned)nc) ? v : T(0); };
     T pv[3], pf[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) load(i0 + u, pv[u], pf[u]);
-    // coarse rows Js = (i - 1) >> 1 and Js + 1 for the current row i: ca (west), cb (east neighbour)
-    T ca0 = cload((i0 - 1) >> 1), ca1 = cload(((i0 - 1) >> 1) + 1);
+    // coarse rows Js = (i - 1) >> 1 and Js + 1 of the current row i: ca (this lane's coarse
+    // column), cb (the next one, from the east lane); row Js + 2 is prefetched raw
+    int Jn = ((i0 - 1) >> 1) + 2;
+    T ca0 = cmask(Jn - 2, craw(Jn - 2)), ca1 = cmask(Jn - 1, craw(Jn - 1));
     T cb0 = __shfl_down(ca0, 1, 64), cb1 = __shfl_down(ca1, 1, 64);
+    T cr2 = craw(Jn);
 
     for (int g = 0; g < NG; ++g) {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int i = i0 + g * G + u;
-            const T vi = pv[u % 3], fi = pf[u % 3];
+            const T rv = pv[u % 3], rf = pf[u % 3];
             load(i + 3, pv[u % 3], pf[u % 3]);
+            const bool rin = col && (unsigned)i < (unsigned)n;
+            const T vi = rin ? rv : T(0), fi = rin ? fs * rf : T(0);
             // i0 = y0 - H with y0 even, so the parity of i is that of H + u (known at compile time);
             // an odd row starts a new coarse row pair (not at the first step: the pair is loaded)
             if (((H + u) & 1) != 0 && (u > 0 || g > 0)) {
                 ca0 = ca1;
                 cb0 = cb1;
-                ca1 = cload((i + 1) >> 1);
+                ca1 = cmask(Jn, cr2);
                 cb1 = __shfl_down(ca1, 1, 64);
+                ++Jn;
+                cr2 = craw(Jn);
             }
             T e;
             if ((i & 1) != 0) e = xodd ? ca0 : T(0.5) * (ca0 + cb0);
@@ -1640,8 +1704,8 @@ __global__ void __launch_bounds__(THREADS) k_subtree(SubArgs a)
     const int n = pp.n[d0], Pst = n + 2, off0 = pp.off[d0];
     const int lg0 = 32 - __clz(n);   // n = 2^lg0 - 1
     const T fs = (T)Lv.fscale;
-    const T* Fg = (const T*)Lv.F;
-    T* Ag = (T*)Lv.A;
+    const gp<const T> Fg = glob<T>((const void*)Lv.F);
+    const gp<T> Ag = glob<T>(Lv.A);
     T* v0 = S.bufp(off0, lg0, 0);
     T* f0 = S.bufp(off0, lg0, 2);
     const bool zero = a.pair || a.zg;
@@ -1729,6 +1793,14 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
     const double scale = st.scale, scale_used = st.scale_used;
     const double alpha = st.alpha, beta = st.beta;
     const bool first = st.iters == 0;
+    const gp<double> U = glob<double>(I.u), R = glob<double>(I.r), Z = glob<double>(I.z), Pv = glob<double>(I.p),
+                     Q = glob<double>(I.q), Y = glob<double>(I.y);
+    const gp<const double> Fv = glob<double>((const void*)I.f), X = glob<double>((const void*)I.x);
+    const gp<const double> Yc = glob<double>((const void*)I.y), Pc = glob<double>((const void*)I.p),
+                           Uc = glob<double>((const void*)I.u);
+    const gp<float> F32f = glob<float>(L0.F);
+    const gp<const float> A32 = glob<float>((const void*)L0.A);
+    const gp<const double> A64 = glob<double>((const void*)L0.A);
 #pragma unroll
     for (int k = ty; k < TY; k += GRID_THREADS / 64) {
         const int j = t.y0 + k, i = t.x0 + tx;
@@ -1737,71 +1809,71 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
         const size_t g0 = (size_t)j * L0.lda + i;   // FP32 level-0 arrays share one leading dimension
         switch (kind) {
         case GK_SSF: {
-            const double F = h2 * I.f[gf];
+            const double F = h2 * Fv[gf];
             acc0 += F * F;
             break;
         }
         case GK_IR_RESID: {
-            const double r = h2 * I.f[gf] - gapply(s, (const double*)I.u, I.ldu, n, j, i);
+            const double r = h2 * Fv[gf] - gapply(s, Uc, I.ldu, n, j, i);
             acc0 += r * r;
-            if (F32) ((float*)L0.F)[g0] = (float)(scale * r);
+            if (F32) F32f[g0] = (float)(scale * r);
             break;
         }
         case GK_IR_UPDATE: {
-            const double e = F32 ? (double)((const float*)L0.A)[g0] : ((const double*)L0.A)[g0];
-            I.u[gu] = I.u[gu] + e / scale_used;
+            const double e = F32 ? (double)A32[g0] : A64[g0];
+            U[gu] = U[gu] + e / scale_used;
             break;
         }
         case GK_PCG_INIT: {
-            const double F = h2 * I.f[gf];
-            I.u[gu] = 0.0;
-            I.r[gv] = F;
+            const double F = h2 * Fv[gf];
+            U[gu] = 0.0;
+            R[gv] = F;
             acc0 += F * F;
             break;
         }
         case GK_PCG_PRECIN: {
-            ((float*)L0.F)[g0] = (float)(scale * I.r[gv]);
+            F32f[g0] = (float)(scale * R[gv]);
             break;
         }
         case GK_PCG_RZ: {
             double z;
             if (F32) {
-                z = (double)((const float*)L0.A)[g0] / scale;
-                I.z[gv] = z;
+                z = (double)A32[g0] / scale;
+                Z[gv] = z;
             } else {
-                z = I.z[gv];
+                z = Z[gv];
             }
-            acc0 += I.r[gv] * z;
+            acc0 += R[gv] * z;
             break;
         }
         case GK_PCG_P: {
-            I.p[gv] = first ? I.z[gv] : I.z[gv] + beta * I.p[gv];
+            Pv[gv] = first ? Z[gv] : Z[gv] + beta * Pv[gv];
             break;
         }
         case GK_PCG_AP: {
-            const double q = gapply(s, (const double*)I.p, I.ldv, n, j, i);
-            I.q[gv] = q;
-            acc0 += I.p[gv] * q;
+            const double q = gapply(s, Pc, I.ldv, n, j, i);
+            Q[gv] = q;
+            acc0 += Pv[gv] * q;
             break;
         }
         case GK_PCG_UPD: {
-            I.u[gu] = I.u[gu] + alpha * I.p[gv];
-            const double r = I.r[gv] - alpha * I.q[gv];
-            I.r[gv] = r;
+            U[gu] = U[gu] + alpha * Pv[gv];
+            const double r = R[gv] - alpha * Q[gv];
+            R[gv] = r;
             acc0 += r * r;
             break;
         }
         case GK_APPLY: {
-            I.y[(size_t)j * I.ldy + i] = gapply(s, I.x, I.ldx, n, j, i) * I.h2inv;
+            Y[(size_t)j * I.ldy + i] = gapply(s, X, I.ldx, n, j, i) * I.h2inv;
             break;
         }
         case GK_GRAD: {
             Sten<double> dt, de;
             dt.load(I.ds_th);
             de.load(I.ds_ep);
-            const double lam = I.x[(size_t)j * I.ldx + i];
-            const double yt = gapply(dt, (const double*)I.y, I.ldy, n, j, i) * I.h2inv;
-            const double ye = gapply(de, (const double*)I.y, I.ldy, n, j, i) * I.h2inv;
+            const double lam = X[(size_t)j * I.ldx + i];
+            const double yt = gapply(dt, Yc, I.ldy, n, j, i) * I.h2inv;
+            const double ye = gapply(de, Yc, I.ldy, n, j, i) * I.h2inv;
             acc0 += lam * yt;
             acc1 += lam * ye;
             break;

@@ -87,11 +87,16 @@ class Fit:
 
 
 def fit(samples: Iterable[tuple]) -> Fit:
-    """Least squares for (alpha, beta) over samples (key, calls, ops, time)."""
+    """Least squares for (alpha, beta) over samples (key, calls, ops, time),
+    both constrained to be non-negative (a per-call cost and a per-operation
+    cost cannot be negative; with few samples the unconstrained fit can be)."""
     rows = list(samples)
     M = np.array([[r[1], r[2]] for r in rows], dtype=np.float64)
     t = np.array([r[3] for r in rows], dtype=np.float64)
     (alpha, beta), *_ = np.linalg.lstsq(M, t, rcond=None)
+    if alpha < 0 or beta < 0:
+        from scipy.optimize import nnls
+        (alpha, beta), _ = nnls(M, t)
     errs = {r[0]: (predict(alpha, beta, r[1], r[2]) - r[3]) / r[3] for r in rows}
     return Fit(float(alpha), float(beta), errs)
 

@@ -28,7 +28,7 @@ import re
 import sys
 from collections import defaultdict
 
-COPY_BYTES = 1 << 30          # bytes read (and written) by the calibration copy
+COPY_BYTES = 1 << 30          # bytes read (and written) by the calibration kernel
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
@@ -58,11 +58,13 @@ def run(args) -> None:
     import torch
     from . import inputs, kcycle
 
+    # calibration: an elementwise kernel that reads COPY_BYTES and writes COPY_BYTES (a same-type
+    # copy_ would go to the DMA engines, which the counters do not see)
     x = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     y = torch.empty_like(x)
     torch.cuda.synchronize()
     for _ in range(3):
-        y.copy_(x)
+        torch.mul(x, 1.5, out=y)
     torch.cuda.synchronize()
     del x, y
     torch.cuda.empty_cache()
@@ -100,9 +102,13 @@ def per_kernel(root: str, counter: str) -> dict:
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
 
 
-def calibration(table: dict) -> float:
-    """bytes per counter unit: the copy kernel is the one whose average is
-    closest to the copy's byte count in KiB (within a factor of 2)"""
+def calibration(table: dict, name_hint: str = "Mul") -> tuple:
+    """bytes per counter unit: the calibration kernel is the elementwise
+    multiply (by name), else the kernel whose average is closest to the
+    calibration byte count in KiB (within a factor of 2)"""
+    for k, (avg, cnt) in table.items():
+        if name_hint in k and avg > 0 and 0.5 < avg / (COPY_BYTES / 1024.0) < 2.0:
+            return COPY_BYTES / avg, k
     want = COPY_BYTES / 1024.0
     best = None
     for k, (avg, cnt) in table.items():
@@ -112,7 +118,9 @@ def calibration(table: dict) -> float:
         if 0.5 < ratio < 2.0 and (best is None or abs(math.log(ratio)) < abs(math.log(best[1] / want))):
             best = (k, avg)
     if best is None:
-        raise SystemExit("calibration copy not found in the counters")
+        top = sorted(table.items(), key=lambda kv: -kv[1][0])[:8]
+        raise SystemExit("calibration kernel not found in the counters; largest averages (KiB): " +
+                         "; ".join(f"{k}: {v[0]:.0f} x{v[1]}" for k, v in top))
     return COPY_BYTES / best[1], best[0]
 
 
@@ -120,24 +128,27 @@ def summarise(dir_fetch: str, dir_write: str, out: str) -> None:
     fetch = per_kernel(dir_fetch, "FETCH_SIZE")
     write = per_kernel(dir_write, "WRITE_SIZE")
     cf, copy_k = calibration(fetch)
-    cw, _ = calibration(write)
+    cw, copy_w = calibration(write)
     res = {}
     for k in sorted(set(fetch) | set(write)):
-        if k == copy_k:
+        if k in (copy_k, copy_w):
             continue
         fb = fetch.get(k, (0.0, 0))[0] * cf
         wb = write.get(k, (0.0, 0))[0] * cw
         res[k] = fb + wb
-    data = {"kernels_source_sha256": kernel_source_digest(), "copy_kernel": copy_k,
+    data = {"kernels_source_sha256": kernel_source_digest(), "calibration_kernel": copy_k,
             "bytes_per_kib_fetch": cf, "bytes_per_kib_write": cw,
-            "fetch_bytes_per_launch": {k: fetch[k][0] * cf for k in fetch if k != copy_k},
-            "write_bytes_per_launch": {k: write[k][0] * cw for k in write if k != copy_k},
+            "fetch_bytes_per_launch": {k: fetch[k][0] * cf for k in fetch if k not in (copy_k, copy_w)},
+            "write_bytes_per_launch": {k: write[k][0] * cw for k in write if k not in (copy_k, copy_w)},
             "bytes_per_launch": res}
     with open(out, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
-    print(f"calibration: {cf:.1f} B per FETCH_SIZE unit, {cw:.1f} B per WRITE_SIZE unit (copy kernel {copy_k})")
+    print(f"calibration: {cf:.1f} B per FETCH_SIZE unit, {cw:.1f} B per WRITE_SIZE unit (kernel {copy_k}, "
+          f"{COPY_BYTES} B read and written)")
+    print(f"{'kernel':60s} {'launches':>8s} {'fetch MB':>10s} {'write MB':>10s} {'total MB':>10s}")
     for k, v in sorted(res.items(), key=lambda kv: -kv[1])[:20]:
-        print(f"{k:60s} {v / 1e6:12.3f} MB/launch")
+        print(f"{k:60s} {fetch.get(k, (0, 0))[1]:8d} {fetch.get(k, (0.0, 0))[0] * cf / 1e6:10.3f} "
+              f"{write.get(k, (0.0, 0))[0] * cw / 1e6:10.3f} {v / 1e6:10.3f}")
 
 
 def main(argv=None):
