@@ -96,14 +96,17 @@ typedef struct {
     int32_t poll_every;     /* cycles launched between host polls of the stop flags (default 0 = adaptive) */
     int32_t coarse_wave_n;  /* persistent-kernel levels with n <= this run on one wave (0..15; default 15) */
     int32_t small_tile_n;   /* fused grid kernels on levels whose largest n <= this use 16 x 16 tiles instead of
-                               64 x 32 (0 = never; 0..4095; default 0); results do not depend on it */
+                               64 x 32 (0 = never; 0..4095; default 511); results do not depend on it */
     int32_t stream_n;       /* fused grid kernels on levels whose largest n >= this stream row strips through
                                registers instead of staging tiles in LDS (0 = never; default 2047); results do
                                not depend on it */
     int32_t wave_regs;      /* 1 = whole calls on the levels wave 0 runs alone (n <= coarse_wave_n) run in
                                registers (instances with n_coarsest = 1; default 1); 0 = phase by phase in LDS;
                                results do not depend on it */
-    int32_t reserved[3];
+    int32_t fuse_junctions; /* 1 = on levels run in 16 x 16 tiles, the post-smoothing of a call's first child and the
+                               pre-smoothing of its second child (kappa >= 2) run as one kernel (default 1); results
+                               do not depend on it */
+    int32_t reserved[2];
 } kc_exec;
 
 typedef struct kc_hier kc_hier;

@@ -174,6 +174,7 @@ enum GridKernel : int32_t {
     GK_APPLY = 19,     // y = S x / h^2
     GK_GRAD = 20,      // -lam^T dS u / h^2 for theta and eps
     GK_ZERO_SELF = 22, // unfused: A[d] = 0 on the launch's own level
+    GK_POSTPRE = 23,   // fused junction of sibling calls: post (nu2 = src) of the first + pre (nu) of the second
 };
 
 // launches kernel k (and, when a.fin is set and with_finalize, the finalize kernel after it)

@@ -658,6 +658,126 @@ __global__ void __launch_bounds__(GRID_THREADS) k_post(StageArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// fused junction of two sibling calls on one level (kappa >= 2): the first
+// call's prolong-add + NU2 sweeps and the second call's NU1 sweeps + residual +
+// full weighting, in one tile kernel.  The first call's result would be
+// written to A only for the second call's pre-smoothing to read it back, so it
+// stays in LDS; the input is the first call's pre-smoothed estimate (B), the
+// output goes to B and F of the coarse level, as the pre-smoothing writes them.
+// Input region = tile + halo NU2 + NU1 + 1 (+1 on the high side for the
+// residual ring of the full weighting).
+// ---------------------------------------------------------------------------
+template <typename T, int NU2, int NU1, int TX, int TY>
+__global__ void __launch_bounds__(GRID_THREADS) k_postpre(StageArgs a)
+{
+    constexpr int NUT = NU2 + NU1, H = NUT + 1;
+    constexpr int RW = TX + 2 * H + 1, RH = TY + 2 * H + 1;
+    constexpr int CW = TX / 2 + H + 3, CH = TY / 2 + H + 3;
+    __shared__ T sv[2][RH * RW];
+    __shared__ T sf[RH * RW];
+    __shared__ T sc[CH * CW];
+    Tile t;
+    if (!get_tile<TX, TY>(a, a.depth, false, t)) return;
+    const InstDev& I = a.inst[t.inst];
+    const int d = a.depth;
+    const LevelDev& Lv = I.lev[d];
+    const LevelDev& Lc = I.lev[d + 1];
+    const int n = Lv.n, nc = Lc.n;
+    const gp<T> B = glob<T>(Lv.B);
+    const gp<const T> F = glob<T>((const void*)Lv.F);
+    const gp<const T> Vc = glob<T>((const void*)Lc.A);
+    const gp<T> Fc = glob<T>(Lc.F);
+    const T fs = (T)Lv.fscale;
+    const int rx0 = t.x0 - H, ry0 = t.y0 - H;
+    const int cx0 = (rx0 - 1) >> 1, cy0 = (ry0 - 1) >> 1;
+    Sten<T> s;
+    s.load(P<T>::s(I, d));
+    const T w = P<T>::w(I, d);
+
+    {   // every load of the region in flight before the LDS stores
+        constexpr int NR = RH * RW, NPT = (NR + GRID_THREADS - 1) / GRID_THREADS;
+        constexpr int NC = CH * CW, NPC = (NC + GRID_THREADS - 1) / GRID_THREADS;
+        T fa[NPT], va[NPT], ca[NPC];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int p = threadIdx.x + k * GRID_THREADS;
+            const int rj = p / RW, ri = p - rj * RW;
+            const int j = ry0 + rj, i = rx0 + ri;
+            const bool in = p < NR && inside(j, i, n);
+            const size_t jc = (size_t)clampi(j, n), ic = (size_t)clampi(i, n);
+            const T lf = F[jc * Lv.ldf + ic];
+            const T lv = B[jc * Lv.ldb + ic];
+            fa[k] = in ? fs * lf : T(0);
+            va[k] = in ? lv : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NPC; ++k) {
+            const int p = threadIdx.x + k * GRID_THREADS;
+            const int cj = p / CW, ci = p - cj * CW;
+            const T cv = gload(Vc, Lc.lda, nc, cy0 + cj, cx0 + ci);
+            ca[k] = (p < NC) ? cv : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int p = threadIdx.x + k * GRID_THREADS;
+            if (p < NR) {
+                sf[p] = fa[k];
+                sv[0][p] = va[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NPC; ++k) {
+            const int p = threadIdx.x + k * GRID_THREADS;
+            if (p < NC) sc[p] = ca[k];
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < RH * RW; p += GRID_THREADS) {
+        const int rj = p / RW, ri = p - rj * RW;
+        const int j = ry0 + rj, i = rx0 + ri;
+        if (!inside(j, i, n)) continue;
+        const T e = prolong_at<T>(j, i, [&](int J, int II) { return sc[(J - cy0) * CW + (II - cx0)]; });
+        sv[0][p] = sv[0][p] + e;
+    }
+    __syncthreads();
+    // NU2 post-sweeps of the first call, then NU1 pre-sweeps of the second: the same Jacobi sweeps
+#pragma unroll
+    for (int k = 1; k <= NUT; ++k) {
+        const int ww = RW - 2 * k, hh = RH - 2 * k;
+        T* src = sv[(k - 1) & 1];
+        T* dst = sv[k & 1];
+        for (int p = threadIdx.x; p < ww * hh; p += GRID_THREADS) {
+            const int rj = k + p / ww, ri = k + (p % ww);
+            const int q = rj * RW + ri;
+            T val = T(0);
+            if (inside(ry0 + rj, rx0 + ri, n)) val = src[q] + w * (sf[q] - s.apply(&src[q], RW));
+            dst[q] = val;
+        }
+        __syncthreads();
+    }
+    const T* vs = sv[NUT & 1];
+    T* rs = sv[(NUT + 1) & 1];
+    for (int p = threadIdx.x; p < TX * TY; p += GRID_THREADS) {
+        const int y = p / TX, x = p % TX;
+        const int j = t.y0 + y, i = t.x0 + x;
+        if (j < n && i < n) B[(size_t)j * Lv.ldb + i] = vs[(H + y) * RW + (H + x)];
+    }
+    for (int p = threadIdx.x; p < (TX + 1) * (TY + 1); p += GRID_THREADS) {
+        const int y = p / (TX + 1), x = p % (TX + 1);
+        const int q = (H + y) * RW + (H + x);
+        rs[q] = inside(t.y0 + y, t.x0 + x, n) ? sf[q] - s.apply(&vs[q], RW) : T(0);
+    }
+    __syncthreads();
+    const int ldc = Lc.ldf;
+    for (int p = threadIdx.x; p < (TX / 2) * (TY / 2); p += GRID_THREADS) {
+        const int Ic = (t.x0 >> 1) + (p % (TX / 2)), Jc = (t.y0 >> 1) + (p / (TX / 2));
+        if (Ic >= nc || Jc >= nc) continue;
+        const int q = (2 * Jc + 1 - ry0) * RW + (2 * Ic + 1 - rx0);
+        Fc[(size_t)Jc * ldc + Ic] = fw_sum(&rs[q], RW);
+    }
+}
+
 // exact coarsest solve with the lower Cholesky factor Lc (m x m, row-major):
 // L y = F, then L^T v = y, both by substitution in index order (one thread);
 // F and v are read and written through strides sf / sv
@@ -1988,6 +2108,32 @@ static hipError_t launch_driver(GridKernel k, const StageArgs& a, int nb, hipStr
     return hipGetLastError();
 }
 
+template <typename T, int NU2>
+static hipError_t launch_postpre_nu1(const StageArgs& a, int nb, hipStream_t s)
+{
+    switch (a.nu) {   // a.nu = nu1 of the second call; a.src = nu2 of the first
+    case 0: k_postpre<T, NU2, 0, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a); break;
+    case 1: k_postpre<T, NU2, 1, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a); break;
+    case 2: k_postpre<T, NU2, 2, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a); break;
+    case 3: k_postpre<T, NU2, 3, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_postpre(const StageArgs& a, int nb, hipStream_t s)
+{
+    if ((a.flags & 3) != 1) return hipErrorInvalidValue;   // 16 x 16 tiles only
+    switch (a.src) {
+    case 0: return launch_postpre_nu1<T, 0>(a, nb, s);
+    case 1: return launch_postpre_nu1<T, 1>(a, nb, s);
+    case 2: return launch_postpre_nu1<T, 2>(a, nb, s);
+    case 3: return launch_postpre_nu1<T, 3>(a, nb, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_finalize(const StageArgs& a, hipStream_t s)
 {
     if (a.fin == FIN_NONE) return hipSuccess;
@@ -2002,6 +2148,7 @@ hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nb, h
     switch (k) {
     case GK_PRE: e = f32 ? launch_pre<float>(a, nb, s) : launch_pre<double>(a, nb, s); break;
     case GK_POST: e = f32 ? launch_post<float>(a, nb, s) : launch_post<double>(a, nb, s); break;
+    case GK_POSTPRE: e = f32 ? launch_postpre<float>(a, nb, s) : launch_postpre<double>(a, nb, s); break;
     case GK_SWEEP: case GK_RESID: case GK_RESTRICT: case GK_ZERO: case GK_PROLONG: case GK_ADD: case GK_COPY:
     case GK_NORM: case GK_ZERO_SELF:
         e = f32 ? launch_unfused<float>(k, a, nb, s) : launch_unfused<double>(k, a, nb, s);

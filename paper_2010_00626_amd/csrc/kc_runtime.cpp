@@ -422,10 +422,37 @@ void gen_fused(kc_hier* h, int d, int k, bool zg, int fin, const kc_cycle_params
     out.push_back(post);
 }
 
+// a post-smoothing launch followed by the pre-smoothing of the next sibling call on the same
+// level (16 x 16 tiles) becomes one fused junction launch
+void fuse_junctions(std::vector<Launch>& ls, size_t from)
+{
+    std::vector<Launch> out(ls.begin(), ls.begin() + from);
+    for (size_t k = from; k < ls.size(); ++k) {
+        const Launch& L = ls[k];
+        if (k + 1 < ls.size()) {
+            const Launch& M = ls[k + 1];
+            if (L.type == L_GRID && M.type == L_GRID && L.gk == GK_POST && M.gk == GK_PRE && L.f32 == M.f32 &&
+                L.sa.depth == M.sa.depth && L.sa.tile_off == M.sa.tile_off && L.sa.flags == 1 && M.sa.flags == 1 &&
+                M.sa.zg == 0 && M.sa.fin == FIN_NONE && L.sa.fin == FIN_NONE) {
+                Launch F = M;
+                F.gk = GK_POSTPRE;
+                F.sa.src = L.sa.nu;   // nu2 of the first call
+                out.push_back(F);
+                ++k;
+                continue;
+            }
+        }
+        out.push_back(L);
+    }
+    ls.swap(out);
+}
+
 void cycle_fused(kc_hier* h, const kc_cycle_params& c, int kappa, bool zg, int fin, bool f32, std::vector<Launch>& out)
 {
+    const size_t from = out.size();
     if (nlist(h, lt_sub(0)) > 0) out.push_back(sub(h, f32, 0, kappa, false, c.nu1, c.nu2, zg, fin));
     if (h->max_cut > 0) gen_fused(h, 0, kappa, zg, fin, c, f32, out);
+    if (h->ex.fuse_junctions) fuse_junctions(out, from);
 }
 
 // Algorithm 4: one launch per operation; cur[d] tracks which buffer holds v_d
@@ -956,6 +983,8 @@ std::string launch_name(const kc_hier* h, const Launch& L)
     const char* T = L.f32 ? "float" : "double";
     if (L.type == L_SUB) return std::string("k_subtree<") + T + ", " + std::to_string(L.threads) + ">";
     if (L.type == L_COARSEST) return std::string("k_coarsest<") + T + ">";
+    if (L.gk == GK_POSTPRE)
+        return std::string("k_postpre<") + T + ", " + std::to_string(L.sa.src) + ", " + std::to_string(L.sa.nu) + ", 16, 16>";
     if (L.gk == GK_PRE || L.gk == GK_POST) {
         const std::string k = L.gk == GK_PRE ? "k_pre" : "k_post";
         const std::string nu = std::to_string(L.sa.nu);
@@ -1003,6 +1032,13 @@ void launch_work(const kc_hier* h, const Launch& L, double& bytes, double& flops
     const int d = L.sa.depth;
     for (int i = 0; i < h->count; ++i) {
         const HostInst& hi = h->hi[i];
+        if (L.gk == GK_POSTPRE) {
+            if (hi.cut <= d) continue;
+            const double nf = hi.il.n[d], nc = hi.il.n[d + 1];
+            bytes += (3.0 * nf * nf + 2.0 * nc * nc) * T;   // read v, f, v_c; write v, f_c
+            flops += nf * nf * (FL_PROLONG + FL_SWEEP * (L.sa.src + L.sa.nu) + FL_RESID) + nc * nc * FL_FW;
+            continue;
+        }
         if (L.gk == GK_PRE || L.gk == GK_POST) {
             if (hi.cut <= d) continue;
             const double nf = hi.il.n[d], nc = hi.il.n[d + 1];
@@ -1044,8 +1080,10 @@ void kc_exec_default(kc_exec* e)
     e->coarse_threads = 512;
     e->poll_every = 0;
     e->coarse_wave_n = 15;
+    e->small_tile_n = 511;
     e->stream_n = 2047;
     e->wave_regs = 1;
+    e->fuse_junctions = 1;
 }
 
 const char* kc_status_string(kc_status s)
@@ -1105,6 +1143,7 @@ static kc_status validate_exec(const kc_exec* e)
     if (e->small_tile_n < 0 || e->small_tile_n > 4095) return fail(KC_ERR_ARG, "small_tile_n must be in 0..4095");
     if (e->stream_n < 0) return fail(KC_ERR_ARG, "stream_n must be >= 0");
     if (e->wave_regs != 0 && e->wave_regs != 1) return fail(KC_ERR_ARG, "wave_regs must be 0 or 1");
+    if (e->fuse_junctions != 0 && e->fuse_junctions != 1) return fail(KC_ERR_ARG, "fuse_junctions must be 0 or 1");
     if (e->coarse_threads * 8 < 64 * e->coarse_cutover) return fail(KC_ERR_ARG, "coarse_threads too small for the cutover");
     return KC_OK;
 }
@@ -1664,6 +1703,7 @@ kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
     js += ", \"small_tile_n\": " + std::to_string(h->ex.small_tile_n);
     js += ", \"stream_n\": " + std::to_string(h->ex.stream_n);
     js += ", \"wave_regs\": " + std::to_string(h->ex.wave_regs);
+    js += ", \"fuse_junctions\": " + std::to_string(h->ex.fuse_junctions);
     js += ", \"subtree_lds_bytes\": " + std::to_string(h->sub_lds);
     js += ", \"workspace_bytes\": " + std::to_string(h->lay.total);
     js += ", \"driver\": \"" + h->last_driver + "\"";

@@ -422,3 +422,29 @@ def test_register_calls_match_lds_phases(n, kappa, nu1, nu2, cut, wave_n, prec):
         check_stop_margin(hist, 1e-6)
         assert res[0][0] == it_ref
         assert np.array_equal(res[0][1], u_ref)
+
+
+@pytest.mark.parametrize("n,kappa,nu1,nu2,prec", [(255, 2, 2, 2, "f64"), (511, 3, 1, 2, "f64"),
+                                                  (255, 2 ** 31 - 1, 3, 0, "f64"), (255, 4, 0, 3, "f64"),
+                                                  (511, 2, 2, 2, "f32")])
+def test_junction_fusion_bitwise(n, kappa, nu1, nu2, prec):
+    """Fused sibling junctions give the bits of separate post / pre launches (and of the oracle in FP64)."""
+    banner(f"junction fusion n={n} kappa={kappa} nu={nu1}+{nu2} {prec}")
+    rng = np.random.default_rng(n + 31 * kappa + nu1)
+    th, ep = 0.6, 4e-3
+    f = rng.uniform(-1, 1, (n, n))
+    res = []
+    for fuse in (1, 0):
+        H = K().Hierarchy([(n, th, ep)], prec, exec=dict(small_tile_n=4095, coarse_cutover=15, fuse_junctions=fuse))
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        it, rr, st = H.solve(u, dev(f), kappa=kappa, nu1=nu1, nu2=nu2, tol=1e-6, maxit=400)
+        assert st == [0]
+        res.append((it[0], host(u), H.stats()["grid_launches_per_iteration"]))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1])
+    assert res[0][2] < res[1][2]   # the fused schedule has fewer launches
+    if prec == "f64":
+        u_ref, rc, it_ref, hist = O.Hierarchy(n, th, ep).solve(f, kappa=min(kappa, 64), nu1=nu1, nu2=nu2, tol=1e-6,
+                                                                maxit=400)
+        check_stop_margin(hist, 1e-6)
+        assert res[0][0] == it_ref and np.array_equal(res[0][1], u_ref)

@@ -88,9 +88,47 @@ def test_fused_mode_launch_count(L, cutover):
     sizes = [2 ** (L - d) - 1 for d in range(L)]
     cut = next(d for d, s in enumerate(sizes) if s <= cutover)
     for kappa in (1, 2, 3, 4, K.KAPPA_W):
-        c = K.schedule_counts([(n, 0.4, 1e-3)], kappa, coarse_cutover=cutover)
+        c = K.schedule_counts([(n, 0.4, 1e-3)], kappa, coarse_cutover=cutover, fuse_junctions=0)
         kk = min(kappa, 10 ** 6)
         grid = 2 * sum(M.level_calls(kk, d + 1) for d in range(cut))
         subs = M.level_calls(kk, cut) if cut > 0 else 1
         assert c["grid_launches"] == grid
         assert c["subtree_launches"] == subs
+
+
+def _grid_sequence(sizes, cut, kappa):
+    """Grid-wide launches of one fused cycle, in order: ('pre' | 'post', depth, zero_guess),
+    written from Algorithm 3's call structure (the persistent launches are left out)."""
+    seq = []
+
+    def call(d, k, zg):
+        if d >= cut:
+            return
+        seq.append(("pre", d, zg))
+        call(d + 1, k, True)
+        if k > 1:
+            call(d + 1, k - 1, False)
+        seq.append(("post", d, False))
+    call(0, kappa, False)
+    return seq
+
+
+@pytest.mark.parametrize("L,cutover,small", [(10, 31, 511), (10, 15, 255), (9, 31, 0), (8, 15, 4095)])
+def test_junction_fusion_launch_count(L, cutover, small):
+    """With junction fusion, every post-smoothing launch followed by the next
+    sibling's (non-zero-guess) pre-smoothing on a 16 x 16-tile level is one launch."""
+    n = 2 ** L - 1
+    sizes = [2 ** (L - d) - 1 for d in range(L)]
+    cut = next(d for d, s in enumerate(sizes) if s <= cutover)
+    for kappa in (1, 2, 3, 4, K.KAPPA_W):
+        seq = _grid_sequence(sizes, cut, min(kappa, L + 1))
+        fused = 0
+        for a, b in zip(seq, seq[1:]):
+            if a[0] == "post" and b[0] == "pre" and a[1] == b[1] and not b[2] and sizes[a[1]] <= small:
+                fused += 1
+        c0 = K.schedule_counts([(n, 0.4, 1e-3)], kappa, coarse_cutover=cutover, small_tile_n=small, fuse_junctions=0)
+        c1 = K.schedule_counts([(n, 0.4, 1e-3)], kappa, coarse_cutover=cutover, small_tile_n=small, fuse_junctions=1)
+        assert c0["grid_launches"] == len(seq)
+        assert c1["grid_launches"] == len(seq) - fused
+        if kappa > 1 and any(sizes[e] <= small for e in range(1, cut)):
+            assert fused > 0
