@@ -118,6 +118,7 @@ def main():
 
     kappas = [1, 2, 3, 4, 6, kcycle.KAPPA_W]
     per = {}
+    u64 = {}   # FP64 solutions by kappa (bit-identical to the CPU oracle's), to state the FP32 path's error
     if not args.no_sweep:
         for prec in ("f64", "f32"):
             for k in kappas:
@@ -134,8 +135,13 @@ def main():
                 med = statistics.median(times)
                 stats = H[prec].stats()
                 key = "W" if k == kcycle.KAPPA_W else str(k)
+                err = None
+                if prec == "f64":
+                    u64[key] = u.clone()
+                elif key in u64:   # max-norm error of the FP32-cycle solution against the FP64 one
+                    err = float((u - u64[key]).abs().max() / u64[key].abs().max())
                 per.setdefault(key, {})[prec] = {
-                    "cycles": its[0], "relres": rr[0], "ms": round(med * 1e3, 3),
+                    "cycles": its[0], "relres": rr[0], "ms": round(med * 1e3, 3), "err_vs_f64_oracle": err,
                     "ms_per_cycle": round(med * 1e3 / max(its[0], 1), 4),
                     "unknowns_per_s": N / med,
                     "grid_launches_per_cycle": stats["grid_launches_per_iteration"],
@@ -224,7 +230,7 @@ def main():
 
     extras = {}
     ex = set(x for x in args.extras.split(",") if x)
-    del H
+    del H, u64
     torch.cuda.empty_cache()
     if "hbm" in ex:
         extras["fine_kernel_8191"] = hbm_kernel(kcycle, torch)
@@ -304,6 +310,7 @@ def c4_batched(inputs, kcycle, autotune, torch):
     assert all(x == 0 for x in st), st
     tb = statistics.median(times)
     grid_b = Hb.stats()["grid_launches_per_iteration"]
+    ub = [x.clone() for x in us]   # batched FP32-cycle solutions, compared with the FP64 loop's below
     Hb.close()
     del Hb
     # plain per-instance FP64 loop
@@ -323,6 +330,8 @@ def c4_batched(inputs, kcycle, autotune, torch):
     tl = time.perf_counter() - t0
     for h_ in Hs:
         h_.close()
+    errs = [float((a - b).abs().max() / b.abs().max()) for a, b in zip(ub, us)]
+    del ub
     sizes = sorted(set(p[0] for p in probs))
     return {"instances": len(probs), "sizes": {str(s): sum(1 for p in probs if p[0] == s) for s in sizes},
             "unknowns": N, "kappa": 3, "batched_f32_ms": round(tb * 1e3, 2),
@@ -331,6 +340,7 @@ def c4_batched(inputs, kcycle, autotune, torch):
             "batched_grid_launches_per_cycle": grid_b,
             "per_instance_f64_loop_ms": round(tl * 1e3, 2), "per_instance_unknowns_per_s": N / tl,
             "per_instance_max_cycles": max(its64), "per_instance_median_cycles": statistics.median(its64),
+            "max_err_batched_f32_vs_f64": max(errs),
             "speedup_batched_f32_vs_loop_f64": round(tl / tb, 3)}
 
 
@@ -356,6 +366,16 @@ def c3_pcg(inputs, kcycle, torch):
         out[str(k)] = {"iterations": it[0], "relres": rr[0], "status": st[0], "ms": round(dt * 1e3, 2),
                        "ms_per_iteration": round(dt * 1e3 / max(it[0], 1), 4), "unknowns_per_s": n * n / dt}
     Hc.close()
+    # error of the FP32-preconditioned result against the FP64-preconditioned one (kappa = 2, same tolerance)
+    u.zero_()
+    H64 = kcycle.Hierarchy([(n, inst.theta, inst.eps)], "f64")
+    H64.pcg(u, f, kappa=2, nu1=1, nu2=1, omega=wl.omega, tol=wl.tol, maxit=1000)
+    u32 = torch.zeros_like(u)
+    Hc = kcycle.Hierarchy([(n, inst.theta, inst.eps)], "f32")
+    Hc.pcg(u32, f, kappa=2, nu1=1, nu2=1, omega=wl.omega, tol=wl.tol, maxit=1000)
+    out["2"]["err_vs_f64"] = float((u32 - u).abs().max() / u.abs().max())
+    Hc.close()
+    H64.close()
     return out
 
 

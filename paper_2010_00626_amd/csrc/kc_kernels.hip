@@ -447,6 +447,85 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// band-mapped passes over an LDS region (small tiles): the block's threads
+// form bands of BW consecutive lanes, lane l of a band is column C0 + l and
+// band b owns the U consecutive rows from R0 + b U.  A thread loads the
+// 3 x (U + 2) window around its rows once and computes its U points (U
+// independent chains) before storing any.  Same arithmetic as Sten::apply.
+// ---------------------------------------------------------------------------
+template <int C0, int C1, int R0, int R1>
+struct RBand {
+    static constexpr int W = C1 - C0;
+    static constexpr int BW = W <= 16 ? 16 : (W <= 32 ? 32 : 64);
+    static constexpr int NB = GRID_THREADS / BW;
+    static constexpr int U = (R1 - R0 + NB - 1) / NB;
+};
+
+// dst = src + w (F - S src) on rows [R0, R1) x columns [C0, C1) of a region with row
+// stride RW (zero outside the grid); zg: dst = w F; resid: dst = F - S src
+template <typename T, int RW, int C0, int C1, int R0, int R1, int MODE>   // MODE 0 sweep, 1 zero-guess sweep, 2 residual
+__device__ __forceinline__ void band_pass(const T* src, T* dst, const T* sf, const Sten<T>& s, T w, int ry0, int rx0, int n)
+{
+    using G = RBand<C0, C1, R0, R1>;
+    constexpr int U = G::U;
+    const int b = threadIdx.x / G::BW, l = threadIdx.x % G::BW;
+    const int c = C0 + l, r0 = R0 + b * U;
+    if (c >= C1 || r0 >= R1) return;
+    const bool colin = (unsigned)(rx0 + c) < (unsigned)n;
+    T val[U];
+    if (MODE == 1) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = min(r0 + u, R1 - 1);
+            val[u] = (colin && (unsigned)(ry0 + r) < (unsigned)n) ? w * sf[r * RW + c] : T(0);
+        }
+    } else {
+        T win[U + 2][3];
+#pragma unroll
+        for (int k = 0; k < U + 2; ++k) {
+            const int r = min(r0 - 1 + k, R1);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) win[k][e] = src[r * RW + c - 1 + e];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = min(r0 + u, R1 - 1);
+            T acc = T(0);
+            acc += s.c[0] * win[u][0];
+            acc += s.c[1] * win[u][1];
+            acc += s.c[2] * win[u][2];
+            acc += s.c[3] * win[u + 1][0];
+            acc += s.c[4] * win[u + 1][1];
+            acc += s.c[5] * win[u + 1][2];
+            acc += s.c[6] * win[u + 2][0];
+            acc += s.c[7] * win[u + 2][1];
+            acc += s.c[8] * win[u + 2][2];
+            const bool in = colin && (unsigned)(ry0 + r) < (unsigned)n;
+            const T fr = sf[r * RW + c];
+            if (MODE == 2) val[u] = in ? fr - acc : T(0);
+            else val[u] = in ? win[u + 1][1] + w * (fr - acc) : T(0);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (r0 + u < R1) dst[(r0 + u) * RW + c] = val[u];
+}
+
+// NU sweeps of a region of RW x RH (sweep k covers [k, RW - k) x [k, RH - k)), ping-pong in sv
+template <typename T, int NU, int RW, int RH, int K = 1>
+__device__ __forceinline__ void band_sweeps(T (*sv)[RW * RH], const T* sf, const Sten<T>& s, T w, bool zg, int ry0, int rx0, int n)
+{
+    if constexpr (K <= NU) {
+        const T* src = sv[(K - 1) & 1];
+        T* dst = sv[K & 1];
+        if (K == 1 && zg) band_pass<T, RW, K, RW - K, K, RH - K, 1>(src, dst, sf, s, w, ry0, rx0, n);
+        else band_pass<T, RW, K, RW - K, K, RH - K, 0>(src, dst, sf, s, w, ry0, rx0, n);
+        __syncthreads();
+        band_sweeps<T, NU, RW, RH, K + 1>(sv, sf, s, w, zg, ry0, rx0, n);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // fused pre-smoothing: nu sweeps + residual + full weighting in one pass
 // (input region = tile + halo nu+1, swept in LDS); optional input norm
 // ---------------------------------------------------------------------------
@@ -513,22 +592,26 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
         }
     }
 
+    if constexpr (TX == 16) {
+        band_sweeps<T, NU, RW, RH>(sv, sf, s, w, zg, ry0, rx0, n);
+    } else {
 #pragma unroll
-    for (int k = 1; k <= NU; ++k) {
-        const int ww = RW - 2 * k, hh = RH - 2 * k;
-        T* src = sv[(k - 1) & 1];
-        T* dst = sv[k & 1];
-        for (int p = threadIdx.x; p < ww * hh; p += GRID_THREADS) {
-            const int rj = k + p / ww, ri = k + (p % ww);
-            const int q = rj * RW + ri;
-            T val = T(0);
-            if (inside(ry0 + rj, rx0 + ri, n)) {
-                if (k == 1 && zg) val = w * sf[q];
-                else val = src[q] + w * (sf[q] - s.apply(&src[q], RW));
+        for (int k = 1; k <= NU; ++k) {
+            const int ww = RW - 2 * k, hh = RH - 2 * k;
+            T* src = sv[(k - 1) & 1];
+            T* dst = sv[k & 1];
+            for (int p = threadIdx.x; p < ww * hh; p += GRID_THREADS) {
+                const int rj = k + p / ww, ri = k + (p % ww);
+                const int q = rj * RW + ri;
+                T val = T(0);
+                if (inside(ry0 + rj, rx0 + ri, n)) {
+                    if (k == 1 && zg) val = w * sf[q];
+                    else val = src[q] + w * (sf[q] - s.apply(&src[q], RW));
+                }
+                dst[q] = val;
             }
-            dst[q] = val;
+            __syncthreads();
         }
-        __syncthreads();
     }
     const T* vs = sv[NU & 1];
     T* rs = sv[(NU + 1) & 1];
@@ -540,10 +623,14 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
         if (j < n && i < n) B[(size_t)j * Lv.ldb + i] = vs[(H + y) * RW + (H + x)];
     }
     // residual on [x0, x0+TX] x [y0, y0+TY]
-    for (int p = threadIdx.x; p < (TX + 1) * (TY + 1); p += GRID_THREADS) {
-        const int y = p / (TX + 1), x = p % (TX + 1);
-        const int q = (H + y) * RW + (H + x);
-        rs[q] = inside(t.y0 + y, t.x0 + x, n) ? sf[q] - s.apply(&vs[q], RW) : T(0);
+    if constexpr (TX == 16) {
+        band_pass<T, RW, H, H + TX + 1, H, H + TY + 1, 2>(vs, rs, sf, s, w, ry0, rx0, n);
+    } else {
+        for (int p = threadIdx.x; p < (TX + 1) * (TY + 1); p += GRID_THREADS) {
+            const int y = p / (TX + 1), x = p % (TX + 1);
+            const int q = (H + y) * RW + (H + x);
+            rs[q] = inside(t.y0 + y, t.x0 + x, n) ? sf[q] - s.apply(&vs[q], RW) : T(0);
+        }
     }
     __syncthreads();
     {
@@ -636,19 +723,23 @@ __global__ void __launch_bounds__(GRID_THREADS) k_post(StageArgs a)
         sv[0][p] = sv[0][p] + e;
     }
     __syncthreads();
+    if constexpr (TX == 16) {
+        band_sweeps<T, NU, RW, RH>(sv, sf, s, w, false, ry0, rx0, n);
+    } else {
 #pragma unroll
-    for (int k = 1; k <= NU; ++k) {
-        const int ww = RW - 2 * k, hh = RH - 2 * k;
-        T* src = sv[(k - 1) & 1];
-        T* dst = sv[k & 1];
-        for (int p = threadIdx.x; p < ww * hh; p += GRID_THREADS) {
-            const int rj = k + p / ww, ri = k + (p % ww);
-            const int q = rj * RW + ri;
-            T val = T(0);
-            if (inside(ry0 + rj, rx0 + ri, n)) val = src[q] + w * (sf[q] - s.apply(&src[q], RW));
-            dst[q] = val;
+        for (int k = 1; k <= NU; ++k) {
+            const int ww = RW - 2 * k, hh = RH - 2 * k;
+            T* src = sv[(k - 1) & 1];
+            T* dst = sv[k & 1];
+            for (int p = threadIdx.x; p < ww * hh; p += GRID_THREADS) {
+                const int rj = k + p / ww, ri = k + (p % ww);
+                const int q = rj * RW + ri;
+                T val = T(0);
+                if (inside(ry0 + rj, rx0 + ri, n)) val = src[q] + w * (sf[q] - s.apply(&src[q], RW));
+                dst[q] = val;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     const T* vs = sv[NU & 1];
     for (int p = threadIdx.x; p < TX * TY; p += GRID_THREADS) {
@@ -742,20 +833,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_postpre(StageArgs a)
     }
     __syncthreads();
     // NU2 post-sweeps of the first call, then NU1 pre-sweeps of the second: the same Jacobi sweeps
-#pragma unroll
-    for (int k = 1; k <= NUT; ++k) {
-        const int ww = RW - 2 * k, hh = RH - 2 * k;
-        T* src = sv[(k - 1) & 1];
-        T* dst = sv[k & 1];
-        for (int p = threadIdx.x; p < ww * hh; p += GRID_THREADS) {
-            const int rj = k + p / ww, ri = k + (p % ww);
-            const int q = rj * RW + ri;
-            T val = T(0);
-            if (inside(ry0 + rj, rx0 + ri, n)) val = src[q] + w * (sf[q] - s.apply(&src[q], RW));
-            dst[q] = val;
-        }
-        __syncthreads();
-    }
+    band_sweeps<T, NUT, RW, RH>(sv, sf, s, w, false, ry0, rx0, n);
     const T* vs = sv[NUT & 1];
     T* rs = sv[(NUT + 1) & 1];
     for (int p = threadIdx.x; p < TX * TY; p += GRID_THREADS) {
@@ -763,11 +841,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_postpre(StageArgs a)
         const int j = t.y0 + y, i = t.x0 + x;
         if (j < n && i < n) B[(size_t)j * Lv.ldb + i] = vs[(H + y) * RW + (H + x)];
     }
-    for (int p = threadIdx.x; p < (TX + 1) * (TY + 1); p += GRID_THREADS) {
-        const int y = p / (TX + 1), x = p % (TX + 1);
-        const int q = (H + y) * RW + (H + x);
-        rs[q] = inside(t.y0 + y, t.x0 + x, n) ? sf[q] - s.apply(&vs[q], RW) : T(0);
-    }
+    band_pass<T, RW, H, H + TX + 1, H, H + TY + 1, 2>(vs, rs, sf, s, w, ry0, rx0, n);
     __syncthreads();
     const int ldc = Lc.ldf;
     for (int p = threadIdx.x; p < (TX / 2) * (TY / 2); p += GRID_THREADS) {
