@@ -1970,6 +1970,41 @@ __global__ void __launch_bounds__(64) k_coarsest(SubArgs a)
 // ---------------------------------------------------------------------------
 // driver kernels on the fine level (FP64 vectors)
 // ---------------------------------------------------------------------------
+// Each thread owns DR = TY / 4 consecutive rows of one column of a 64 x 32
+// tile.  All loads of a thread are issued before its first store (clamped
+// addresses, masked at use), so they are in flight together; a store between
+// two rows' loads would make the second row wait for the first (the compiler
+// cannot tell the arrays apart).  Stencil kinds keep a three-column window of
+// DR + 2 rows; every point is summed in the order of gapply.
+constexpr int DR = TY / (GRID_THREADS / 64);
+
+template <typename T>
+struct DWin {
+    double v[DR + 2][3];
+    __device__ __forceinline__ void load(gp<const T> x, int ld, int n, int jb, int i)
+    {
+#pragma unroll
+        for (int r = 0; r < DR + 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[r][c] = (double)gload(x, ld, n, jb - 1 + r, i - 1 + c);
+    }
+    // stencil sum at the window's row r (grid row jb + r)
+    __device__ __forceinline__ double apply(const Sten<double>& s, int r) const
+    {
+        double acc = 0.0;
+        acc += s.c[0] * v[r][0];
+        acc += s.c[1] * v[r][1];
+        acc += s.c[2] * v[r][2];
+        acc += s.c[3] * v[r + 1][0];
+        acc += s.c[4] * v[r + 1][1];
+        acc += s.c[5] * v[r + 1][2];
+        acc += s.c[6] * v[r + 2][0];
+        acc += s.c[7] * v[r + 2][1];
+        acc += s.c[8] * v[r + 2][2];
+        return acc;
+    }
+};
+
 template <bool F32, int kind>
 __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
 {
@@ -1979,6 +2014,8 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
     InstState& st = a.st[t.inst];
     const int n = I.n0;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int i = t.x0 + tx, jb = t.y0 + ty * DR;
+    const int ic = clampi(i, n);
     Sten<double> s;
     s.load(I.s64[0]);
     const double h2 = I.h2;
@@ -1991,89 +2028,150 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
                      Q = glob<double>(I.q), Y = glob<double>(I.y);
     const gp<const double> Fv = glob<double>((const void*)I.f), X = glob<double>((const void*)I.x);
     const gp<const double> Yc = glob<double>((const void*)I.y), Pc = glob<double>((const void*)I.p),
-                           Uc = glob<double>((const void*)I.u);
+                           Uc = glob<double>((const void*)I.u), Rc = glob<double>((const void*)I.r),
+                           Zc = glob<double>((const void*)I.z), Qc = glob<double>((const void*)I.q);
     const gp<float> F32f = glob<float>(L0.F);
     const gp<const float> A32 = glob<float>((const void*)L0.A);
     const gp<const double> A64 = glob<double>((const void*)L0.A);
+    // row offsets (clamped rows: every address is inside the arrays)
+    auto rowu = [&](int r) { return (size_t)clampi(jb + r, n) * I.ldu + ic; };
+    auto rowf = [&](int r) { return (size_t)clampi(jb + r, n) * I.ldf + ic; };
+    auto rowv = [&](int r) { return (size_t)clampi(jb + r, n) * I.ldv + ic; };
+    auto row0 = [&](int r) { return (size_t)clampi(jb + r, n) * L0.lda + ic; };   // FP32 level-0 arrays share one ld
+    auto ok = [&](int r) { return jb + r < n && i < n; };
+
+    if constexpr (kind == GK_SSF) {
+        double F[DR];
 #pragma unroll
-    for (int k = ty; k < TY; k += GRID_THREADS / 64) {
-        const int j = t.y0 + k, i = t.x0 + tx;
-        if (j >= n || i >= n) continue;
-        const size_t gu = (size_t)j * I.ldu + i, gf = (size_t)j * I.ldf + i, gv = (size_t)j * I.ldv + i;
-        const size_t g0 = (size_t)j * L0.lda + i;   // FP32 level-0 arrays share one leading dimension
-        switch (kind) {
-        case GK_SSF: {
-            const double F = h2 * Fv[gf];
-            acc0 += F * F;
-            break;
+        for (int r = 0; r < DR; ++r) F[r] = Fv[rowf(r)];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            const double f = h2 * F[r];
+            if (ok(r)) acc0 += f * f;
         }
-        case GK_IR_RESID: {
-            const double r = h2 * Fv[gf] - gapply(s, Uc, I.ldu, n, j, i);
-            acc0 += r * r;
-            if (F32) F32f[g0] = (float)(scale * r);
-            break;
-        }
-        case GK_IR_UPDATE: {
-            const double e = F32 ? (double)A32[g0] : A64[g0];
-            U[gu] = U[gu] + e / scale_used;
-            break;
-        }
-        case GK_PCG_INIT: {
-            const double F = h2 * Fv[gf];
-            U[gu] = 0.0;
-            R[gv] = F;
-            acc0 += F * F;
-            break;
-        }
-        case GK_PCG_PRECIN: {
-            F32f[g0] = (float)(scale * R[gv]);
-            break;
-        }
-        case GK_PCG_RZ: {
-            double z;
-            if (F32) {
-                z = (double)A32[g0] / scale;
-                Z[gv] = z;
-            } else {
-                z = Z[gv];
+    } else if constexpr (kind == GK_IR_RESID) {
+        DWin<double> w;
+        w.load(Uc, I.ldu, n, jb, i);
+        double F[DR];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) F[r] = Fv[rowf(r)];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            const double res = h2 * F[r] - w.apply(s, r);
+            if (ok(r)) {
+                acc0 += res * res;
+                if (F32) F32f[row0(r)] = (float)(scale * res);
             }
-            acc0 += R[gv] * z;
-            break;
         }
-        case GK_PCG_P: {
-            Pv[gv] = first ? Z[gv] : Z[gv] + beta * Pv[gv];
-            break;
+    } else if constexpr (kind == GK_IR_UPDATE) {
+        double E[DR], V[DR];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            E[r] = F32 ? (double)A32[row0(r)] : A64[row0(r)];
+            V[r] = Uc[rowu(r)];
         }
-        case GK_PCG_AP: {
-            const double q = gapply(s, Pc, I.ldv, n, j, i);
-            Q[gv] = q;
-            acc0 += Pv[gv] * q;
-            break;
+#pragma unroll
+        for (int r = 0; r < DR; ++r)
+            if (ok(r)) U[rowu(r)] = V[r] + E[r] / scale_used;
+    } else if constexpr (kind == GK_PCG_INIT) {
+        double F[DR];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) F[r] = Fv[rowf(r)];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            const double f = h2 * F[r];
+            if (ok(r)) {
+                U[rowu(r)] = 0.0;
+                R[rowv(r)] = f;
+                acc0 += f * f;
+            }
         }
-        case GK_PCG_UPD: {
-            U[gu] = U[gu] + alpha * Pv[gv];
-            const double r = R[gv] - alpha * Q[gv];
-            R[gv] = r;
-            acc0 += r * r;
-            break;
+    } else if constexpr (kind == GK_PCG_PRECIN) {
+        double V[DR];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) V[r] = Rc[rowv(r)];
+#pragma unroll
+        for (int r = 0; r < DR; ++r)
+            if (ok(r)) F32f[row0(r)] = (float)(scale * V[r]);
+    } else if constexpr (kind == GK_PCG_RZ) {
+        double E[DR], V[DR];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            E[r] = F32 ? (double)A32[row0(r)] : Zc[rowv(r)];
+            V[r] = Rc[rowv(r)];
         }
-        case GK_APPLY: {
-            Y[(size_t)j * I.ldy + i] = gapply(s, X, I.ldx, n, j, i) * I.h2inv;
-            break;
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            const double z = F32 ? E[r] / scale : E[r];
+            if (ok(r)) {
+                if (F32) Z[rowv(r)] = z;
+                acc0 += V[r] * z;
+            }
         }
-        case GK_GRAD: {
-            Sten<double> dt, de;
-            dt.load(I.ds_th);
-            de.load(I.ds_ep);
-            const double lam = X[(size_t)j * I.ldx + i];
-            const double yt = gapply(dt, Yc, I.ldy, n, j, i) * I.h2inv;
-            const double ye = gapply(de, Yc, I.ldy, n, j, i) * I.h2inv;
-            acc0 += lam * yt;
-            acc1 += lam * ye;
-            break;
+    } else if constexpr (kind == GK_PCG_P) {
+        double E[DR], V[DR];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            E[r] = Zc[rowv(r)];
+            V[r] = first ? 0.0 : Pc[rowv(r)];
         }
-        default:
-            break;
+#pragma unroll
+        for (int r = 0; r < DR; ++r)
+            if (ok(r)) Pv[rowv(r)] = first ? E[r] : E[r] + beta * V[r];
+    } else if constexpr (kind == GK_PCG_AP) {
+        DWin<double> w;
+        w.load(Pc, I.ldv, n, jb, i);
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            const double q = w.apply(s, r);
+            if (ok(r)) {
+                Q[rowv(r)] = q;
+                acc0 += w.v[r + 1][1] * q;
+            }
+        }
+    } else if constexpr (kind == GK_PCG_UPD) {
+        double V[DR], Pp[DR], Rr[DR], Qq[DR];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            V[r] = Uc[rowu(r)];
+            Pp[r] = Pc[rowv(r)];
+            Rr[r] = Rc[rowv(r)];
+            Qq[r] = Qc[rowv(r)];
+        }
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            const double res = Rr[r] - alpha * Qq[r];
+            if (ok(r)) {
+                U[rowu(r)] = V[r] + alpha * Pp[r];
+                R[rowv(r)] = res;
+                acc0 += res * res;
+            }
+        }
+    } else if constexpr (kind == GK_APPLY) {
+        DWin<double> w;
+        w.load(X, I.ldx, n, jb, i);
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            const double y = w.apply(s, r) * I.h2inv;
+            if (ok(r)) Y[(size_t)(jb + r) * I.ldy + i] = y;
+        }
+    } else if constexpr (kind == GK_GRAD) {
+        Sten<double> dt, de;
+        dt.load(I.ds_th);
+        de.load(I.ds_ep);
+        DWin<double> w;
+        w.load(Yc, I.ldy, n, jb, i);
+        double Lm[DR];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) Lm[r] = X[(size_t)clampi(jb + r, n) * I.ldx + ic];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            const double yt = w.apply(dt, r) * I.h2inv;
+            const double ye = w.apply(de, r) * I.h2inv;
+            if (ok(r)) {
+                acc0 += Lm[r] * yt;
+                acc1 += Lm[r] * ye;
+            }
         }
     }
     if (a.fin != FIN_NONE) reduce_partial(a, t, acc0, acc1);

@@ -448,3 +448,38 @@ def test_junction_fusion_bitwise(n, kappa, nu1, nu2, prec):
                                                                 maxit=400)
         check_stop_margin(hist, 1e-6)
         assert res[0][0] == it_ref and np.array_equal(res[0][1], u_ref)
+
+
+def test_autotuner_keeps_results():
+    """The autotuner picks valid execution options; results under them are the default options' bits."""
+    banner("autotuner")
+    from paper_2010_00626_amd import autotune
+    n = 255
+    f = inputs.uniform_rhs(np.random.default_rng(21), n)
+    H = K().Hierarchy([(n, 1.0, 1e-3)], "f64")
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    fd = dev(f)
+    it0, _, st0 = H.solve(u, fd, kappa=3, tol=1e-7, maxit=500)
+    ref = host(u)
+    res = autotune.tune(H, u, fd, 3, iters=4, force=True)
+    assert res["trials"] and res["exec"] in [t["exec"] for t in res["trials"]]
+    assert H.stats()["coarse_cutover"] == res["exec"]["coarse_cutover"]
+    u.zero_()
+    it1, _, st1 = H.solve(u, fd, kappa=3, tol=1e-7, maxit=500)
+    assert st1 == st0 == [0] and it1 == it0
+    assert np.array_equal(host(u), ref)
+
+
+def test_model_fit_paper_mode_counts():
+    """The run-time model fit in the paper-structured mode launches exactly the
+    paper's N_gpuCalls per cycle and finds positive alpha and beta."""
+    banner("model fit (paper mode, small n)")
+    from paper_2010_00626_amd import fit_model, model
+    rows = []
+    for kappa in (1, 2, K().KAPPA_W):
+        for nl in (5, 6, 7, 8):
+            ms, calls, stages, reps = fit_model.measure("paper", kappa, nl, nu=4, budget_ms=10.0)
+            assert calls == model.n_gpu_calls_paper(kappa, nl, 4)
+            rows.append(((kappa, nl), calls, model.n_ops_2d(kappa, nl), ms))
+    fit = model.fit(rows)
+    assert fit.alpha > 0 and fit.beta >= 0
