@@ -106,7 +106,9 @@ typedef struct {
     int32_t fuse_junctions; /* 1 = on levels run in 16 x 16 tiles, the post-smoothing of a call's first child and the
                                pre-smoothing of its second child (kappa >= 2) run as one kernel (default 1); results
                                do not depend on it */
-    int32_t reserved[2];
+    int32_t mid_tile_n;     /* fused grid kernels on levels whose largest n is above small_tile_n and <= this use
+                               32 x 32 tiles (0 = never; 0..4095; default 2047); results do not depend on it */
+    int32_t reserved;
 } kc_exec;
 
 typedef struct kc_hier kc_hier;

@@ -26,17 +26,42 @@ COARSE_CANDIDATES = tuple(
     for c in (15, 31, 63) for t in (256, 512) for w in (7, 15)
     if not (c == 63 and t == 256)       # 63 rows need at least 8 waves
 )
-TILE_CANDIDATES = tuple(dict(small_tile_n=s, stream_n=m) for s in (0, 127, 255, 511, 1023)
-                        for m in (0, 1023, 2047, 4095))
+TILE_CANDIDATES = tuple(dict(small_tile_n=s, mid_tile_n=t, stream_n=m) for s in (0, 127, 255, 511, 1023)
+                        for t in (0, 1023, 2047, 4095) for m in (0, 1023, 2047, 4095))
 DEFAULT_STAGES = (tuple(dict(coarse_cutover=31, coarse_threads=512, coarse_wave_n=15, **t) for t in TILE_CANDIDATES),
                   COARSE_CANDIDATES, TILE_CANDIDATES)
 
 
-def _relevant(cand: dict, nmax: int) -> bool:
-    """Skip shape options that cannot change the schedule of a hierarchy whose
-    largest level is nmax (streaming thresholds above it act like 'never')."""
-    m = cand.get("stream_n", 0)
-    return m == 0 or m <= nmax
+def _shapes(cand: dict, sizes) -> tuple:
+    """Kernel shape of every level above the coarse cutover of a hierarchy with
+    the given fine sizes (largest n per depth), as the library picks it: two
+    candidates with the same shapes give the same schedule."""
+    cut = cand.get("coarse_cutover", 31)
+    small, mid, stream = cand.get("small_tile_n", 511), cand.get("mid_tile_n", 2047), cand.get("stream_n", 2047)
+    out = []
+    n = max(sizes)
+    while n > cut:
+        if stream > 0 and n >= stream:
+            out.append("stream")
+        elif n <= small:
+            out.append("16")
+        elif n <= mid:
+            out.append("32")
+        else:
+            out.append("64x32")
+        n = (n - 1) // 2
+    return tuple(out)
+
+
+def _relevant(cand: dict, seen: set, sizes) -> bool:
+    """Skip a candidate whose per-level kernel shapes (and persistent-kernel
+    options) equal those of one already tried."""
+    key = (_shapes(cand, sizes), cand.get("coarse_cutover", 31), cand.get("coarse_threads", 512),
+           cand.get("coarse_wave_n", 15))
+    if key in seen:
+        return False
+    seen.add(key)
+    return True
 
 _memory: dict = {}
 
@@ -88,12 +113,13 @@ def tune(H: "kcycle.Hierarchy", u, f, kappa: int, nu1: int = 2, nu2: int = 2, om
     run = H.solve if driver == "solve" else H.pcg
     us = u if isinstance(u, (list, tuple)) else [u]
     trials = []
+    seen: set = set()
     best = None
     for stage in stages:
         base = dict(best["exec"]) if best else {}
         for part in stage:
             cand = dict(base, **part)
-            if not _relevant(cand, max(H.sizes)) or any(t["exec"] == cand for t in trials):
+            if not _relevant(cand, seen, H.sizes):
                 continue
             try:
                 H.set_exec(**dict(cand, poll_every=iters + 2))

@@ -592,7 +592,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
         }
     }
 
-    if constexpr (TX == 16) {
+    if constexpr (TX == TY && TX <= 32) {
         band_sweeps<T, NU, RW, RH>(sv, sf, s, w, zg, ry0, rx0, n);
     } else {
 #pragma unroll
@@ -623,7 +623,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
         if (j < n && i < n) B[(size_t)j * Lv.ldb + i] = vs[(H + y) * RW + (H + x)];
     }
     // residual on [x0, x0+TX] x [y0, y0+TY]
-    if constexpr (TX == 16) {
+    if constexpr (TX == TY && TX <= 32) {
         band_pass<T, RW, H, H + TX + 1, H, H + TY + 1, 2>(vs, rs, sf, s, w, ry0, rx0, n);
     } else {
         for (int p = threadIdx.x; p < (TX + 1) * (TY + 1); p += GRID_THREADS) {
@@ -723,7 +723,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_post(StageArgs a)
         sv[0][p] = sv[0][p] + e;
     }
     __syncthreads();
-    if constexpr (TX == 16) {
+    if constexpr (TX == TY && TX <= 32) {
         band_sweeps<T, NU, RW, RH>(sv, sf, s, w, false, ry0, rx0, n);
     } else {
 #pragma unroll
@@ -2181,7 +2181,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
 // launchers
 // ---------------------------------------------------------------------------
 // shape of a fused grid launch (flags): bit 1 = streaming strips with R = 16 << ((flags >> 2) & 3)
-// rows, else bit 0 = 16 x 16 tiles, else 64 x 32 tiles
+// rows, else bit 0 = 16 x 16 tiles, else bit 4 = 32 x 32 tiles, else 64 x 32 tiles
 template <typename T, int NU>
 static void pre_shape(const StageArgs& a, int nb, hipStream_t s)
 {
@@ -2193,6 +2193,8 @@ static void pre_shape(const StageArgs& a, int nb, hipStream_t s)
         }
     } else if (a.flags & 1) {
         k_pre<T, NU, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a);
+    } else if (a.flags & 16) {
+        k_pre<T, NU, 32, 32><<<nb, GRID_THREADS, 0, s>>>(a);
     } else {
         k_pre<T, NU, TX, TY><<<nb, GRID_THREADS, 0, s>>>(a);
     }
@@ -2209,6 +2211,8 @@ static void post_shape(const StageArgs& a, int nb, hipStream_t s)
         }
     } else if (a.flags & 1) {
         k_post<T, NU, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a);
+    } else if (a.flags & 16) {
+        k_post<T, NU, 32, 32><<<nb, GRID_THREADS, 0, s>>>(a);
     } else {
         k_post<T, NU, TX, TY><<<nb, GRID_THREADS, 0, s>>>(a);
     }

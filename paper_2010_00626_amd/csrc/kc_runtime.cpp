@@ -183,6 +183,7 @@ struct Layout {
 
 int tiles_of(int n) { return ((n + TX - 1) / TX) * ((n + TY - 1) / TY); }
 int tiles_small(int n) { return ((n + TS - 1) / TS) * ((n + TS - 1) / TS); }
+int tiles_mid(int n) { return ((n + TM - 1) / TM) * ((n + TM - 1) / TM); }
 // streaming blocks: STRIP_BLOCK_W columns x R rows, R = 16 << code
 int strip_rows_code(int n) { return n >= 4095 ? 2 : (n >= 2047 ? 1 : 0); }
 int tiles_stream(int n, int code) { return ((n + STRIP_BLOCK_W - 1) / STRIP_BLOCK_W) * ((n + (16 << code) - 1) / (16 << code)); }
@@ -546,8 +547,10 @@ kc_status build_tables(kc_hier* h, const std::vector<char>* active)
         h->tiles[tt_all0()][i + 1] = tiles_of(hi.il.n[0]);
         for (int d = 0; d < MAXL; ++d) {
             const int sh = h->shape[d];
-            const int tc = (sh & 2) ? tiles_stream(hi.il.n[d], (sh >> 2) & 3)
-                                    : ((sh & 1) ? tiles_small(hi.il.n[d]) : tiles_of(hi.il.n[d]));
+            const int tc = (sh & 2)    ? tiles_stream(hi.il.n[d], (sh >> 2) & 3)
+                           : (sh & 1)  ? tiles_small(hi.il.n[d])
+                           : (sh & 16) ? tiles_mid(hi.il.n[d])
+                                       : tiles_of(hi.il.n[d]);
             h->tiles[tt_cut(d)][i + 1] = (d < L && hi.cut > d) ? tc : 0;
             h->tiles[tt_lvl(d)][i + 1] = (d < L - 1) ? tiles_of(hi.il.n[d]) : 0;
             if (hi.cut == d && d < L) h->lists[lt_sub(d)].push_back(i);
@@ -632,6 +635,7 @@ kc_status plan_exec(kc_hier* h)
         int f = 0;
         if (maxn > 0 && h->ex.stream_n > 0 && maxn >= h->ex.stream_n) f = 2 | (strip_rows_code(maxn) << 2);
         else if (maxn > 0 && maxn <= h->ex.small_tile_n) f = 1;
+        else if (maxn > 0 && maxn <= h->ex.mid_tile_n) f = 16;
         h->shape[d] = f;
     }
     kc_status st = build_tables(h, nullptr);
@@ -990,6 +994,7 @@ std::string launch_name(const kc_hier* h, const Launch& L)
         const std::string nu = std::to_string(L.sa.nu);
         if (L.sa.flags & 2) return k + "_s<" + T + ", " + nu + ", " + std::to_string(16 << ((L.sa.flags >> 2) & 3)) + ">";
         if (L.sa.flags & 1) return k + "<" + T + ", " + nu + ", 16, 16>";
+        if (L.sa.flags & 16) return k + "<" + T + ", " + nu + ", 32, 32>";
         return k + "<" + T + ", " + nu + ", 64, 32>";
     }
     if (L.gk <= GK_NORM || L.gk == GK_ZERO_SELF) return std::string("k_unfused<") + T + ", " + std::to_string(L.gk) + ">";
@@ -1082,6 +1087,7 @@ void kc_exec_default(kc_exec* e)
     e->coarse_wave_n = 15;
     e->small_tile_n = 511;
     e->stream_n = 2047;
+    e->mid_tile_n = 2047;
     e->wave_regs = 1;
     e->fuse_junctions = 1;
 }
@@ -1142,6 +1148,7 @@ static kc_status validate_exec(const kc_exec* e)
     if (e->coarse_wave_n < 0 || e->coarse_wave_n > 15) return fail(KC_ERR_ARG, "coarse_wave_n must be in 0..15");
     if (e->small_tile_n < 0 || e->small_tile_n > 4095) return fail(KC_ERR_ARG, "small_tile_n must be in 0..4095");
     if (e->stream_n < 0) return fail(KC_ERR_ARG, "stream_n must be >= 0");
+    if (e->mid_tile_n < 0 || e->mid_tile_n > 4095) return fail(KC_ERR_ARG, "mid_tile_n must be in 0..4095");
     if (e->wave_regs != 0 && e->wave_regs != 1) return fail(KC_ERR_ARG, "wave_regs must be 0 or 1");
     if (e->fuse_junctions != 0 && e->fuse_junctions != 1) return fail(KC_ERR_ARG, "fuse_junctions must be 0 or 1");
     if (e->coarse_threads * 8 < 64 * e->coarse_cutover) return fail(KC_ERR_ARG, "coarse_threads too small for the cutover");
@@ -1702,6 +1709,7 @@ kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
     js += ", \"coarse_wave_n\": " + std::to_string(h->ex.coarse_wave_n);
     js += ", \"small_tile_n\": " + std::to_string(h->ex.small_tile_n);
     js += ", \"stream_n\": " + std::to_string(h->ex.stream_n);
+    js += ", \"mid_tile_n\": " + std::to_string(h->ex.mid_tile_n);
     js += ", \"wave_regs\": " + std::to_string(h->ex.wave_regs);
     js += ", \"fuse_junctions\": " + std::to_string(h->ex.fuse_junctions);
     js += ", \"subtree_lds_bytes\": " + std::to_string(h->sub_lds);

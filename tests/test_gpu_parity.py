@@ -119,6 +119,37 @@ def test_small_tile_option(n, kappa, small):
     assert np.array_equal(host(u), u_ref)
 
 
+@pytest.mark.parametrize("n,kappa,small,mid", [(255, 3, 0, 4095), (1023, 2, 127, 1023), (511, 2 ** 31 - 1, 0, 511)])
+def test_mid_tile_option(n, kappa, small, mid):
+    """32 x 32 tiles give the oracle's bits (one cycle, and a solve whose
+    stopping norm runs in them); FP32 cycles give the same bits in any shape."""
+    banner(f"mid tiles n={n} kappa={kappa} small_tile_n={small} mid_tile_n={mid}")
+    rng = np.random.default_rng(n + 11)
+    th, ep = 0.7, 2e-3
+    v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
+    ex = dict(small_tile_n=small, mid_tile_n=mid, stream_n=0)
+    H = K().Hierarchy([(n, th, ep)], exec=ex)
+    v = dev(v0)
+    H.cycle(v, dev(f), kappa=kappa, nu1=2, nu2=2)
+    Ho = O.Hierarchy(n, th, ep)
+    assert np.array_equal(host(v), Ho.cycle(v0, f, kappa=min(kappa, 64), nu1=2, nu2=2)[0])
+    u_ref, rc, it_ref, hist = Ho.solve(f, kappa=min(kappa, 64), tol=1e-6, maxit=500)
+    check_stop_margin(hist, 1e-6)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    iters, relres, status = H.solve(u, dev(f), kappa=kappa, tol=1e-6, maxit=500)
+    assert status == [0] and iters[0] == it_ref
+    assert np.array_equal(host(u), u_ref)
+    outs = []
+    for e in (ex, dict(small_tile_n=4095, stream_n=0)):
+        H32 = K().Hierarchy([(n, th, ep)], "f32", exec=e)
+        u.zero_()
+        it32, _, st32 = H32.solve(u, dev(f), kappa=kappa, tol=1e-8, maxit=500)
+        assert st32 == [0]
+        outs.append((it32[0], host(u)))
+        H32.close()
+    assert outs[0][0] == outs[1][0] and np.array_equal(outs[0][1], outs[1][1])
+
+
 STREAM_CASES = [
     # n, kappa, nu1, nu2, stream_n
     (255, 2, 2, 2, 63),
