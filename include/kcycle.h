@@ -103,12 +103,14 @@ typedef struct {
     int32_t wave_regs;      /* 1 = whole calls on the levels wave 0 runs alone (n <= coarse_wave_n) run in
                                registers (instances with n_coarsest = 1; default 1); 0 = phase by phase in LDS;
                                results do not depend on it */
-    int32_t fuse_junctions; /* 1 = on levels run in 16 x 16 tiles, the post-smoothing of a call's first child and the
+    int32_t fuse_junctions; /* 1 = on levels run in 8 x 8 or 16 x 16 tiles, the post-smoothing of a call's first child and the
                                pre-smoothing of its second child (kappa >= 2) run as one kernel (default 1); results
                                do not depend on it */
     int32_t mid_tile_n;     /* fused grid kernels on levels whose largest n is above small_tile_n and <= this use
                                32 x 32 tiles (0 = never; 0..4095; default 2047); results do not depend on it */
-    int32_t reserved;
+    int32_t tiny_tile_n;    /* fused grid kernels on levels whose largest n <= this use 8 x 8 tiles (one point per
+                               thread and phase; takes precedence over small_tile_n; 0 = never; 0..4095; default 255);
+                               results do not depend on it */
 } kc_exec;
 
 typedef struct kc_hier kc_hier;

@@ -6,10 +6,11 @@ measurement alone: for a hierarchy, a cycle (kappa, nu1, nu2) and a driver,
 each candidate runs a fixed number of iterations and the fastest is kept.  The
 search is coordinate descent over two groups of options, each searched with
 the best of the other fixed: the shapes of the fused grid kernels (the
-largest level size run in 16 x 16 tiles, the smallest level size streamed
-through registers), then the persistent-kernel options (coarse cutover,
+largest level sizes run in 8 x 8, 16 x 16 and 32 x 32 tiles, the smallest
+level size streamed through registers), then the persistent-kernel options (coarse cutover,
 threads, single-wave level size), then the grid shapes again (the best
-cutover depends on how cheap the grid launches below it are).  Results are
+cutover depends on how cheap the grid launches below it are).  The last group
+re-tries only the few fastest grid shapes of the first.  Results are
 cached per (device, instance sizes, precision, driver, kappa, nu1, nu2) in
 memory and, when KC_AUTOTUNE_CACHE names a file, in that JSON file.
 """
@@ -26,10 +27,12 @@ COARSE_CANDIDATES = tuple(
     for c in (15, 31, 63) for t in (256, 512) for w in (7, 15)
     if not (c == 63 and t == 256)       # 63 rows need at least 8 waves
 )
-TILE_CANDIDATES = tuple(dict(small_tile_n=s, mid_tile_n=t, stream_n=m) for s in (0, 127, 255, 511, 1023)
-                        for t in (0, 1023, 2047, 4095) for m in (0, 1023, 2047, 4095))
+TILE_CANDIDATES = tuple(dict(tiny_tile_n=y, small_tile_n=s, mid_tile_n=t, stream_n=m) for y in (0, 63, 127, 255)
+                        for s in (0, 127, 255, 511, 1023) for t in (0, 1023, 2047, 4095) for m in (0, 1023, 2047, 4095))
+# the third stage re-tries only the RETRY fastest tile shapes of the first under the chosen persistent-kernel options
+RETRY = 4
 DEFAULT_STAGES = (tuple(dict(coarse_cutover=31, coarse_threads=512, coarse_wave_n=15, **t) for t in TILE_CANDIDATES),
-                  COARSE_CANDIDATES, TILE_CANDIDATES)
+                  COARSE_CANDIDATES, "retry")
 
 
 def _shapes(cand: dict, sizes) -> tuple:
@@ -38,11 +41,14 @@ def _shapes(cand: dict, sizes) -> tuple:
     candidates with the same shapes give the same schedule."""
     cut = cand.get("coarse_cutover", 31)
     small, mid, stream = cand.get("small_tile_n", 511), cand.get("mid_tile_n", 2047), cand.get("stream_n", 2047)
+    tiny = cand.get("tiny_tile_n", 0)
     out = []
     n = max(sizes)
     while n > cut:
         if stream > 0 and n >= stream:
             out.append("stream")
+        elif n <= tiny:
+            out.append("8")
         elif n <= small:
             out.append("16")
         elif n <= mid:
@@ -115,8 +121,12 @@ def tune(H: "kcycle.Hierarchy", u, f, kappa: int, nu1: int = 2, nu2: int = 2, om
     trials = []
     seen: set = set()
     best = None
-    for stage in stages:
+    tile_keys = ("tiny_tile_n", "small_tile_n", "mid_tile_n", "stream_n")
+    for si, stage in enumerate(stages):
         base = dict(best["exec"]) if best else {}
+        if stage == "retry":   # the fastest tile shapes of the first stage, under the current options
+            first = sorted((t for t in trials if t.get("stage") == 0), key=lambda r: r["ms_per_iter"])[:RETRY]
+            stage = tuple({k: t["exec"][k] for k in tile_keys if k in t["exec"]} for t in first)
         for part in stage:
             cand = dict(base, **part)
             if not _relevant(cand, seen, H.sizes):
@@ -134,7 +144,7 @@ def tune(H: "kcycle.Hierarchy", u, f, kappa: int, nu1: int = 2, nu2: int = 2, om
             run(u, f, kappa=kappa, nu1=nu1, nu2=nu2, omega=omega, tol=0.0, maxit=iters)
             wall = time.perf_counter() - t0
             dev_ms = H.stats()["last_ms"]
-            trials.append({"exec": cand, "ms_per_iter": dev_ms / (iters + 1), "wall_ms": wall * 1e3})
+            trials.append({"exec": cand, "ms_per_iter": dev_ms / (iters + 1), "wall_ms": wall * 1e3, "stage": si})
         if not trials:
             raise RuntimeError("no execution candidate is valid for this hierarchy")
         best = min(trials, key=lambda r: r["ms_per_iter"])

@@ -12,6 +12,7 @@ constexpr int TX = 64;            // grid-kernel tile width  (one wave64 row)
 constexpr int TY = 32;            // grid-kernel tile height
 constexpr int TS = 16;            // small-level tile side of the fused kernels
 constexpr int TM = 32;            // mid-level tile side of the fused kernels
+constexpr int TT = 8;             // tiny tile side of the fused kernels (one point per thread and phase)
 constexpr int STRIP_BLOCK_W = 216; // columns of a streaming block (4 strips of 54)
 constexpr int GRID_THREADS = 256; // threads of the grid-wide kernels
 constexpr int HIST_CAP = 8192;    // relres history entries kept per instance
@@ -132,8 +133,8 @@ struct StageArgs {
     int32_t fin;              // Finalize kind of this launch's reduction
     int32_t nu;               // sweeps for fused pre/post kernels
     int32_t src, dst;         // buffer selectors for unfused kernels (0 = A, 1 = B)
-    int32_t flags;            // fused kernels' shape: bit 0 = 16 x 16 tiles; bit 4 = 32 x 32 tiles; bit 1 = streaming
-                              // strips, rows 16 << bits 2-3; none = 64 x 32 tiles
+    int32_t flags;            // fused kernels' shape: bit 0 = 16 x 16 tiles; bit 4 = 32 x 32 tiles; bit 5 = 8 x 8
+                              // tiles; bit 1 = streaming strips, rows 16 << bits 2-3; none = 64 x 32 tiles
 };
 
 // arguments of a persistent coarse-kernel launch
@@ -142,6 +143,7 @@ struct SubArgs {
     InstState* st;
     const int32_t* list;      // instance ids handled (one workgroup each)
     int32_t count;
+    int32_t first;            // list[0] (a launch for one instance reads no list)
     int32_t depth;            // depth of the calls
     int32_t kappa;            // counter of the first call
     int32_t pair;             // 1: call(kappa) then call(kappa-1) from zero; 0: one call from A

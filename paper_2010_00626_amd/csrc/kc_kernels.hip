@@ -1858,57 +1858,102 @@ struct Sub {
     }
 };
 
+// top level (N x N) of a persistent launch: F (scaled) and A (unless zero) are
+// loaded into registers, the tables staged (stage()), and after a barrier the
+// values go to the level's LDS arrays (F in the third, A in the first buffer);
+// false when the instance is finished (checked once the loads are in flight)
+template <typename T, int THREADS, int N, typename Stage>
+__device__ __forceinline__ bool top_level_in(gp<const T> Fg, gp<const T> Ag, int ldf, int lda, T fs, bool zero, bool done,
+                                             T* lev, Stage stage)
+{
+    constexpr int NN = N * N, NP = (NN + THREADS - 1) / THREADS, P = N + 2;
+    T fr[NP], ar[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int p = min((int)threadIdx.x + k * THREADS, NN - 1);
+        const int j = p / N, i = p - j * N;
+        fr[k] = Fg[(size_t)j * ldf + i];
+        ar[k] = zero ? T(0) : Ag[(size_t)j * lda + i];
+    }
+    stage();
+    if (done) return false;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int p = (int)threadIdx.x + k * THREADS;
+        if (p < NN) {
+            const int j = p / N, i = p - j * N;
+            lev[2 * P * P + (j + 1) * P + (i + 1)] = fs * fr[k];
+            if (!zero) lev[(j + 1) * P + (i + 1)] = ar[k];
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
 template <typename T, int THREADS>
 __global__ void __launch_bounds__(THREADS) k_subtree(SubArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ SubParams<T> pp;
-    const int inst = a.list[blockIdx.x];
-    if (a.st[inst].done) return;
+    // a launch for a single instance names it in its arguments (no list load first)
+    const int inst = (a.count == 1) ? a.first : a.list[blockIdx.x];
     const InstDev& I = a.inst[inst];
+    const bool done = a.st[inst].done != 0;   // checked once the loads below are in flight
     T* sm = reinterpret_cast<T*>(smem_raw);
     const int d0 = a.depth, L = I.L;
 
-    // stage parameters, op lists and a small coarsest factor in LDS
-    const int k1 = min(a.kappa, MAXL + 1), k2 = min(max(a.kappa - 1, 1), MAXL + 1);
-    const int n1 = I.ops_len[k1 - 1], n2 = (a.pair && a.kappa > 1) ? I.ops_len[k2 - 1] : 0;
-    for (int t = threadIdx.x; t < n1 + n2; t += blockDim.x)
-        pp.ops[t] = (t < n1) ? I.ops[I.ops_beg[k1 - 1] + t] : I.ops[I.ops_beg[k2 - 1] + (t - n1)];
-    for (int t = threadIdx.x; t < MAXL * 9; t += blockDim.x) {
-        const int d = t / 9;
-        pp.s[d][t % 9] = (d < L) ? P<T>::s(I, d)[t % 9] : T(0);
-    }
-    if (threadIdx.x < MAXL) {
-        const int d = threadIdx.x;
-        pp.w[d] = (d < L) ? P<T>::w(I, d) : T(0);
-        pp.n[d] = (d < L) ? I.lev[d].n : 0;
-        pp.off[d] = I.lds_off[d];
-    }
-    if (threadIdx.x == 0) {
-        pp.nops[0] = n1;
-        pp.nops[1] = n2;
-    }
-    if (I.nc2 * I.nc2 <= SubParams<T>::CH)
-        for (int t = threadIdx.x; t < I.nc2 * I.nc2; t += blockDim.x) pp.chol[t] = P<T>::chol(I)[t];
-    for (int p = threadIdx.x; p < I.sub_lds; p += blockDim.x) sm[p] = T(0);
-    __syncthreads();
-
-    Sub<T, THREADS> S{sm, &pp, &I, a.nu1, a.nu2, a.wave_n, 0u};
+    // the top level's F (and A) are loaded into registers first, so that they are in
+    // flight while the tables are staged; the load count is exact for the level size
     const LevelDev& Lv = I.lev[d0];
-    const int n = pp.n[d0], Pst = n + 2, off0 = pp.off[d0];
-    const int lg0 = 32 - __clz(n);   // n = 2^lg0 - 1
+    const int n = Lv.n;
     const T fs = (T)Lv.fscale;
     const gp<const T> Fg = glob<T>((const void*)Lv.F);
     const gp<T> Ag = glob<T>(Lv.A);
+    const bool zero = a.pair || a.zg;
+    const int k1 = min(a.kappa, MAXL + 1), k2 = min(max(a.kappa - 1, 1), MAXL + 1);
+    const int n1 = I.ops_len[k1 - 1], n2 = (a.pair && a.kappa > 1) ? I.ops_len[k2 - 1] : 0;
+    auto stage = [&]() {   // parameters, op lists and a small coarsest factor into LDS; LDS levels zeroed
+        for (int t = threadIdx.x; t < n1 + n2; t += blockDim.x)
+            pp.ops[t] = (t < n1) ? I.ops[I.ops_beg[k1 - 1] + t] : I.ops[I.ops_beg[k2 - 1] + (t - n1)];
+        for (int t = threadIdx.x; t < MAXL * 9; t += blockDim.x) {
+            const int d = t / 9;
+            pp.s[d][t % 9] = (d < L) ? P<T>::s(I, d)[t % 9] : T(0);
+        }
+        if (threadIdx.x < MAXL) {
+            const int d = threadIdx.x;
+            pp.w[d] = (d < L) ? P<T>::w(I, d) : T(0);
+            pp.n[d] = (d < L) ? I.lev[d].n : 0;
+            pp.off[d] = I.lds_off[d];
+        }
+        if (threadIdx.x == 0) {
+            pp.nops[0] = n1;
+            pp.nops[1] = n2;
+        }
+        if (I.nc2 * I.nc2 <= SubParams<T>::CH)
+            for (int t = threadIdx.x; t < I.nc2 * I.nc2; t += blockDim.x) pp.chol[t] = P<T>::chol(I)[t];
+        for (int p = threadIdx.x; p < I.sub_lds; p += blockDim.x) sm[p] = T(0);
+    };
+    // level sizes are 2^k - 1 <= cutover <= 63; the host accepts a 63 x 63 top level only with 512 threads
+    T* const lev = sm + I.lds_off[d0];
+    bool live = false;
+    switch (n) {
+    case 1: live = top_level_in<T, THREADS, 1>(Fg, Ag, Lv.ldf, Lv.lda, fs, zero, done, lev, stage); break;
+    case 3: live = top_level_in<T, THREADS, 3>(Fg, Ag, Lv.ldf, Lv.lda, fs, zero, done, lev, stage); break;
+    case 7: live = top_level_in<T, THREADS, 7>(Fg, Ag, Lv.ldf, Lv.lda, fs, zero, done, lev, stage); break;
+    case 15: live = top_level_in<T, THREADS, 15>(Fg, Ag, Lv.ldf, Lv.lda, fs, zero, done, lev, stage); break;
+    case 31: live = top_level_in<T, THREADS, 31>(Fg, Ag, Lv.ldf, Lv.lda, fs, zero, done, lev, stage); break;
+    default:
+        if constexpr (THREADS >= 512) live = top_level_in<T, THREADS, 63>(Fg, Ag, Lv.ldf, Lv.lda, fs, zero, done, lev, stage);
+        break;
+    }
+    if (!live) return;   // the whole workgroup leaves together
+
+    Sub<T, THREADS> S{sm, &pp, &I, a.nu1, a.nu2, a.wave_n, 0u};
+    const int Pst = n + 2, off0 = pp.off[d0];
+    const int lg0 = 32 - __clz(n);   // n = 2^lg0 - 1
     T* v0 = S.bufp(off0, lg0, 0);
     T* f0 = S.bufp(off0, lg0, 2);
-    const bool zero = a.pair || a.zg;
-    for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
-        const int j = p / n, i = p - j * n;
-        f0[(j + 1) * Pst + (i + 1)] = fs * Fg[(size_t)j * Lv.ldf + i];
-        if (!zero) v0[(j + 1) * Pst + (i + 1)] = Ag[(size_t)j * Lv.lda + i];
-    }
-    __syncthreads();
 
     if (a.fin == FIN_STOP) {
         __shared__ double red[16];
@@ -2181,7 +2226,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
 // launchers
 // ---------------------------------------------------------------------------
 // shape of a fused grid launch (flags): bit 1 = streaming strips with R = 16 << ((flags >> 2) & 3)
-// rows, else bit 0 = 16 x 16 tiles, else bit 4 = 32 x 32 tiles, else 64 x 32 tiles
+// rows, else bit 5 = 8 x 8 tiles, else bit 0 = 16 x 16 tiles, else bit 4 = 32 x 32 tiles, else 64 x 32 tiles
 template <typename T, int NU>
 static void pre_shape(const StageArgs& a, int nb, hipStream_t s)
 {
@@ -2191,6 +2236,8 @@ static void pre_shape(const StageArgs& a, int nb, hipStream_t s)
         case 1: k_pre_s<T, NU, 32><<<nb, 256, 0, s>>>(a); break;
         default: k_pre_s<T, NU, 64><<<nb, 256, 0, s>>>(a); break;
         }
+    } else if (a.flags & 32) {
+        k_pre<T, NU, 8, 8><<<nb, GRID_THREADS, 0, s>>>(a);
     } else if (a.flags & 1) {
         k_pre<T, NU, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a);
     } else if (a.flags & 16) {
@@ -2209,6 +2256,8 @@ static void post_shape(const StageArgs& a, int nb, hipStream_t s)
         case 1: k_post_s<T, NU, 32><<<nb, 256, 0, s>>>(a); break;
         default: k_post_s<T, NU, 64><<<nb, 256, 0, s>>>(a); break;
         }
+    } else if (a.flags & 32) {
+        k_post<T, NU, 8, 8><<<nb, GRID_THREADS, 0, s>>>(a);
     } else if (a.flags & 1) {
         k_post<T, NU, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a);
     } else if (a.flags & 16) {
@@ -2284,30 +2333,37 @@ static hipError_t launch_driver(GridKernel k, const StageArgs& a, int nb, hipStr
     return hipGetLastError();
 }
 
-template <typename T, int NU2>
+template <typename T, int NU2, int TSZ>
 static hipError_t launch_postpre_nu1(const StageArgs& a, int nb, hipStream_t s)
 {
     switch (a.nu) {   // a.nu = nu1 of the second call; a.src = nu2 of the first
-    case 0: k_postpre<T, NU2, 0, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a); break;
-    case 1: k_postpre<T, NU2, 1, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a); break;
-    case 2: k_postpre<T, NU2, 2, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a); break;
-    case 3: k_postpre<T, NU2, 3, 16, 16><<<nb, GRID_THREADS, 0, s>>>(a); break;
+    case 0: k_postpre<T, NU2, 0, TSZ, TSZ><<<nb, GRID_THREADS, 0, s>>>(a); break;
+    case 1: k_postpre<T, NU2, 1, TSZ, TSZ><<<nb, GRID_THREADS, 0, s>>>(a); break;
+    case 2: k_postpre<T, NU2, 2, TSZ, TSZ><<<nb, GRID_THREADS, 0, s>>>(a); break;
+    case 3: k_postpre<T, NU2, 3, TSZ, TSZ><<<nb, GRID_THREADS, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <typename T, int TSZ>
+static hipError_t launch_postpre_tile(const StageArgs& a, int nb, hipStream_t s)
+{
+    switch (a.src) {
+    case 0: return launch_postpre_nu1<T, 0, TSZ>(a, nb, s);
+    case 1: return launch_postpre_nu1<T, 1, TSZ>(a, nb, s);
+    case 2: return launch_postpre_nu1<T, 2, TSZ>(a, nb, s);
+    case 3: return launch_postpre_nu1<T, 3, TSZ>(a, nb, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 static hipError_t launch_postpre(const StageArgs& a, int nb, hipStream_t s)
 {
-    if ((a.flags & 3) != 1) return hipErrorInvalidValue;   // 16 x 16 tiles only
-    switch (a.src) {
-    case 0: return launch_postpre_nu1<T, 0>(a, nb, s);
-    case 1: return launch_postpre_nu1<T, 1>(a, nb, s);
-    case 2: return launch_postpre_nu1<T, 2>(a, nb, s);
-    case 3: return launch_postpre_nu1<T, 3>(a, nb, s);
-    default: return hipErrorInvalidValue;
-    }
+    if (a.flags == 1) return launch_postpre_tile<T, 16>(a, nb, s);
+    if (a.flags == 32) return launch_postpre_tile<T, 8>(a, nb, s);
+    return hipErrorInvalidValue;   // 16 x 16 and 8 x 8 tiles only
 }
 
 hipError_t launch_finalize(const StageArgs& a, hipStream_t s)

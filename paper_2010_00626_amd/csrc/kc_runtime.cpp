@@ -184,6 +184,7 @@ struct Layout {
 int tiles_of(int n) { return ((n + TX - 1) / TX) * ((n + TY - 1) / TY); }
 int tiles_small(int n) { return ((n + TS - 1) / TS) * ((n + TS - 1) / TS); }
 int tiles_mid(int n) { return ((n + TM - 1) / TM) * ((n + TM - 1) / TM); }
+int tiles_tiny(int n) { return ((n + TT - 1) / TT) * ((n + TT - 1) / TT); }
 // streaming blocks: STRIP_BLOCK_W columns x R rows, R = 16 << code
 int strip_rows_code(int n) { return n >= 4095 ? 2 : (n >= 2047 ? 1 : 0); }
 int tiles_stream(int n, int code) { return ((n + STRIP_BLOCK_W - 1) / STRIP_BLOCK_W) * ((n + (16 << code) - 1) / (16 << code)); }
@@ -210,7 +211,8 @@ kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Lay
         int L;
         kc_status st = check_problem(probs[i], L);
         if (st != KC_OK) return st;
-        tiles0 += std::max(std::max(tiles_of(probs[i].n), tiles_small(probs[i].n)), tiles_stream(probs[i].n, 0));   // any shape at depth 0
+        tiles0 += std::max(std::max(std::max(tiles_of(probs[i].n), tiles_small(probs[i].n)), tiles_stream(probs[i].n, 0)),
+                           tiles_tiny(probs[i].n));   // any shape at depth 0
     }
     lay.total_tiles0 = tiles0;
     lay.partial = take(sizeof(double) * 2 * (size_t)tiles0);
@@ -389,6 +391,7 @@ Launch sub(kc_hier* h, bool f32, int depth, int kappa, bool pair, int nu1, int n
     L.ba.st = h->d_st;
     L.ba.list = dev_list(h, lt_sub(depth));
     L.ba.count = nlist(h, lt_sub(depth));
+    L.ba.first = L.ba.count > 0 ? h->lists[lt_sub(depth)][0] : 0;
     L.ba.depth = depth;
     L.ba.kappa = kappa;
     L.ba.pair = pair ? 1 : 0;
@@ -433,7 +436,8 @@ void fuse_junctions(std::vector<Launch>& ls, size_t from)
         if (k + 1 < ls.size()) {
             const Launch& M = ls[k + 1];
             if (L.type == L_GRID && M.type == L_GRID && L.gk == GK_POST && M.gk == GK_PRE && L.f32 == M.f32 &&
-                L.sa.depth == M.sa.depth && L.sa.tile_off == M.sa.tile_off && L.sa.flags == 1 && M.sa.flags == 1 &&
+                L.sa.depth == M.sa.depth && L.sa.tile_off == M.sa.tile_off && (L.sa.flags == 1 || L.sa.flags == 32) &&
+                M.sa.flags == L.sa.flags &&
                 M.sa.zg == 0 && M.sa.fin == FIN_NONE && L.sa.fin == FIN_NONE) {
                 Launch F = M;
                 F.gk = GK_POSTPRE;
@@ -467,6 +471,7 @@ void gen_paper(kc_hier* h, int d, int k, const kc_cycle_params& c, bool f32, int
         L.ba.st = h->d_st;
         L.ba.list = dev_list(h, lt_coarse(d));
         L.ba.count = nlist(h, lt_coarse(d));
+        L.ba.first = L.ba.count > 0 ? h->lists[lt_coarse(d)][0] : 0;
         L.ba.depth = d;
         out.push_back(L);
         cur[d] = 0;
@@ -548,6 +553,7 @@ kc_status build_tables(kc_hier* h, const std::vector<char>* active)
         for (int d = 0; d < MAXL; ++d) {
             const int sh = h->shape[d];
             const int tc = (sh & 2)    ? tiles_stream(hi.il.n[d], (sh >> 2) & 3)
+                           : (sh & 32) ? tiles_tiny(hi.il.n[d])
                            : (sh & 1)  ? tiles_small(hi.il.n[d])
                            : (sh & 16) ? tiles_mid(hi.il.n[d])
                                        : tiles_of(hi.il.n[d]);
@@ -634,6 +640,7 @@ kc_status plan_exec(kc_hier* h)
             if (d < h->hi[i].il.L && h->hi[i].cut > d) maxn = std::max(maxn, h->hi[i].il.n[d]);
         int f = 0;
         if (maxn > 0 && h->ex.stream_n > 0 && maxn >= h->ex.stream_n) f = 2 | (strip_rows_code(maxn) << 2);
+        else if (maxn > 0 && maxn <= h->ex.tiny_tile_n) f = 32;
         else if (maxn > 0 && maxn <= h->ex.small_tile_n) f = 1;
         else if (maxn > 0 && maxn <= h->ex.mid_tile_n) f = 16;
         h->shape[d] = f;
@@ -988,13 +995,15 @@ std::string launch_name(const kc_hier* h, const Launch& L)
     if (L.type == L_SUB) return std::string("k_subtree<") + T + ", " + std::to_string(L.threads) + ">";
     if (L.type == L_COARSEST) return std::string("k_coarsest<") + T + ">";
     if (L.gk == GK_POSTPRE)
-        return std::string("k_postpre<") + T + ", " + std::to_string(L.sa.src) + ", " + std::to_string(L.sa.nu) + ", 16, 16>";
+        return std::string("k_postpre<") + T + ", " + std::to_string(L.sa.src) + ", " + std::to_string(L.sa.nu) +
+               (L.sa.flags == 32 ? ", 8, 8>" : ", 16, 16>");
     if (L.gk == GK_PRE || L.gk == GK_POST) {
         const std::string k = L.gk == GK_PRE ? "k_pre" : "k_post";
         const std::string nu = std::to_string(L.sa.nu);
         if (L.sa.flags & 2) return k + "_s<" + T + ", " + nu + ", " + std::to_string(16 << ((L.sa.flags >> 2) & 3)) + ">";
         if (L.sa.flags & 1) return k + "<" + T + ", " + nu + ", 16, 16>";
         if (L.sa.flags & 16) return k + "<" + T + ", " + nu + ", 32, 32>";
+        if (L.sa.flags & 32) return k + "<" + T + ", " + nu + ", 8, 8>";
         return k + "<" + T + ", " + nu + ", 64, 32>";
     }
     if (L.gk <= GK_NORM || L.gk == GK_ZERO_SELF) return std::string("k_unfused<") + T + ", " + std::to_string(L.gk) + ">";
@@ -1088,6 +1097,7 @@ void kc_exec_default(kc_exec* e)
     e->small_tile_n = 511;
     e->stream_n = 2047;
     e->mid_tile_n = 2047;
+    e->tiny_tile_n = 255;
     e->wave_regs = 1;
     e->fuse_junctions = 1;
 }
@@ -1149,6 +1159,7 @@ static kc_status validate_exec(const kc_exec* e)
     if (e->small_tile_n < 0 || e->small_tile_n > 4095) return fail(KC_ERR_ARG, "small_tile_n must be in 0..4095");
     if (e->stream_n < 0) return fail(KC_ERR_ARG, "stream_n must be >= 0");
     if (e->mid_tile_n < 0 || e->mid_tile_n > 4095) return fail(KC_ERR_ARG, "mid_tile_n must be in 0..4095");
+    if (e->tiny_tile_n < 0 || e->tiny_tile_n > 4095) return fail(KC_ERR_ARG, "tiny_tile_n must be in 0..4095");
     if (e->wave_regs != 0 && e->wave_regs != 1) return fail(KC_ERR_ARG, "wave_regs must be 0 or 1");
     if (e->fuse_junctions != 0 && e->fuse_junctions != 1) return fail(KC_ERR_ARG, "fuse_junctions must be 0 or 1");
     if (e->coarse_threads * 8 < 64 * e->coarse_cutover) return fail(KC_ERR_ARG, "coarse_threads too small for the cutover");
@@ -1710,6 +1721,7 @@ kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
     js += ", \"small_tile_n\": " + std::to_string(h->ex.small_tile_n);
     js += ", \"stream_n\": " + std::to_string(h->ex.stream_n);
     js += ", \"mid_tile_n\": " + std::to_string(h->ex.mid_tile_n);
+    js += ", \"tiny_tile_n\": " + std::to_string(h->ex.tiny_tile_n);
     js += ", \"wave_regs\": " + std::to_string(h->ex.wave_regs);
     js += ", \"fuse_junctions\": " + std::to_string(h->ex.fuse_junctions);
     js += ", \"subtree_lds_bytes\": " + std::to_string(h->sub_lds);

@@ -106,7 +106,7 @@ def test_small_tile_option(n, kappa, small):
     rng = np.random.default_rng(n + 7)
     th, ep = 2.1, 3e-4
     v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
-    H = K().Hierarchy([(n, th, ep)], exec=dict(small_tile_n=small))
+    H = K().Hierarchy([(n, th, ep)], exec=dict(small_tile_n=small, tiny_tile_n=0))
     v = dev(v0)
     H.cycle(v, dev(f), kappa=kappa, nu1=2, nu2=2)
     Ho = O.Hierarchy(n, th, ep)
@@ -119,15 +119,25 @@ def test_small_tile_option(n, kappa, small):
     assert np.array_equal(host(u), u_ref)
 
 
-@pytest.mark.parametrize("n,kappa,small,mid", [(255, 3, 0, 4095), (1023, 2, 127, 1023), (511, 2 ** 31 - 1, 0, 511)])
-def test_mid_tile_option(n, kappa, small, mid):
-    """32 x 32 tiles give the oracle's bits (one cycle, and a solve whose
-    stopping norm runs in them); FP32 cycles give the same bits in any shape."""
-    banner(f"mid tiles n={n} kappa={kappa} small_tile_n={small} mid_tile_n={mid}")
+TILE_SHAPE_CASES = [
+    (255, 3, dict(tiny_tile_n=0, small_tile_n=0, mid_tile_n=4095)),      # 32 x 32 everywhere
+    (1023, 2, dict(tiny_tile_n=0, small_tile_n=127, mid_tile_n=1023)),
+    (511, 2 ** 31 - 1, dict(tiny_tile_n=0, small_tile_n=0, mid_tile_n=511)),
+    (255, 2, dict(tiny_tile_n=255)),                                     # 8 x 8 everywhere
+    (1023, 3, dict(tiny_tile_n=127, small_tile_n=255, mid_tile_n=1023)),  # 8, 16, 32 and 32 x 32 tiles
+    (127, 2 ** 31 - 1, dict(tiny_tile_n=127)),
+]
+
+
+@pytest.mark.parametrize("n,kappa,shape", TILE_SHAPE_CASES)
+def test_tile_shape_options(n, kappa, shape):
+    """8 x 8 and 32 x 32 tiles give the oracle's bits (one cycle, and a solve
+    whose stopping norm runs in them); FP32 cycles give the same bits in any shape."""
+    banner(f"tile shapes n={n} kappa={kappa} {shape}")
     rng = np.random.default_rng(n + 11)
     th, ep = 0.7, 2e-3
     v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
-    ex = dict(small_tile_n=small, mid_tile_n=mid, stream_n=0)
+    ex = dict(shape, stream_n=0)
     H = K().Hierarchy([(n, th, ep)], exec=ex)
     v = dev(v0)
     H.cycle(v, dev(f), kappa=kappa, nu1=2, nu2=2)
@@ -140,7 +150,7 @@ def test_mid_tile_option(n, kappa, small, mid):
     assert status == [0] and iters[0] == it_ref
     assert np.array_equal(host(u), u_ref)
     outs = []
-    for e in (ex, dict(small_tile_n=4095, stream_n=0)):
+    for e in (ex, dict(tiny_tile_n=0, small_tile_n=4095, stream_n=0)):
         H32 = K().Hierarchy([(n, th, ep)], "f32", exec=e)
         u.zero_()
         it32, _, st32 = H32.solve(u, dev(f), kappa=kappa, tol=1e-8, maxit=500)
@@ -455,18 +465,21 @@ def test_register_calls_match_lds_phases(n, kappa, nu1, nu2, cut, wave_n, prec):
         assert np.array_equal(res[0][1], u_ref)
 
 
-@pytest.mark.parametrize("n,kappa,nu1,nu2,prec", [(255, 2, 2, 2, "f64"), (511, 3, 1, 2, "f64"),
-                                                  (255, 2 ** 31 - 1, 3, 0, "f64"), (255, 4, 0, 3, "f64"),
-                                                  (511, 2, 2, 2, "f32")])
-def test_junction_fusion_bitwise(n, kappa, nu1, nu2, prec):
-    """Fused sibling junctions give the bits of separate post / pre launches (and of the oracle in FP64)."""
-    banner(f"junction fusion n={n} kappa={kappa} nu={nu1}+{nu2} {prec}")
+@pytest.mark.parametrize("n,kappa,nu1,nu2,prec,tile", [(255, 2, 2, 2, "f64", 16), (511, 3, 1, 2, "f64", 16),
+                                                       (255, 2 ** 31 - 1, 3, 0, "f64", 16), (255, 4, 0, 3, "f64", 16),
+                                                       (511, 2, 2, 2, "f32", 16), (255, 2, 2, 2, "f64", 8),
+                                                       (511, 3, 3, 3, "f64", 8), (511, 2, 2, 2, "f32", 8)])
+def test_junction_fusion_bitwise(n, kappa, nu1, nu2, prec, tile):
+    """Fused sibling junctions (16 x 16 or 8 x 8 tiles) give the bits of separate
+    post / pre launches (and of the oracle in FP64)."""
+    banner(f"junction fusion n={n} kappa={kappa} nu={nu1}+{nu2} {prec} tile {tile}")
     rng = np.random.default_rng(n + 31 * kappa + nu1)
     th, ep = 0.6, 4e-3
     f = rng.uniform(-1, 1, (n, n))
     res = []
+    shape = dict(tiny_tile_n=0, small_tile_n=4095) if tile == 16 else dict(tiny_tile_n=4095)
     for fuse in (1, 0):
-        H = K().Hierarchy([(n, th, ep)], prec, exec=dict(small_tile_n=4095, coarse_cutover=15, fuse_junctions=fuse))
+        H = K().Hierarchy([(n, th, ep)], prec, exec=dict(shape, coarse_cutover=15, fuse_junctions=fuse))
         u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
         it, rr, st = H.solve(u, dev(f), kappa=kappa, nu1=nu1, nu2=nu2, tol=1e-6, maxit=400)
         assert st == [0]

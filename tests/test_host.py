@@ -113,10 +113,12 @@ def _grid_sequence(sizes, cut, kappa):
     return seq
 
 
-@pytest.mark.parametrize("L,cutover,small", [(10, 31, 511), (10, 15, 255), (9, 31, 0), (8, 15, 4095)])
-def test_junction_fusion_launch_count(L, cutover, small):
+@pytest.mark.parametrize("L,cutover,small,tiny", [(10, 31, 511, 0), (10, 15, 255, 0), (9, 31, 0, 0), (8, 15, 4095, 0),
+                                                 (10, 31, 0, 255), (9, 15, 127, 63), (10, 31, 511, 255)])
+def test_junction_fusion_launch_count(L, cutover, small, tiny):
     """With junction fusion, every post-smoothing launch followed by the next
-    sibling's (non-zero-guess) pre-smoothing on a 16 x 16-tile level is one launch."""
+    sibling's (non-zero-guess) pre-smoothing on a level run in 16 x 16 or 8 x 8
+    tiles is one launch."""
     n = 2 ** L - 1
     sizes = [2 ** (L - d) - 1 for d in range(L)]
     cut = next(d for d, s in enumerate(sizes) if s <= cutover)
@@ -124,11 +126,12 @@ def test_junction_fusion_launch_count(L, cutover, small):
         seq = _grid_sequence(sizes, cut, min(kappa, L + 1))
         fused = 0
         for a, b in zip(seq, seq[1:]):
-            if a[0] == "post" and b[0] == "pre" and a[1] == b[1] and not b[2] and sizes[a[1]] <= small:
+            if a[0] == "post" and b[0] == "pre" and a[1] == b[1] and not b[2] and sizes[a[1]] <= max(small, tiny):
                 fused += 1
-        c0 = K.schedule_counts([(n, 0.4, 1e-3)], kappa, coarse_cutover=cutover, small_tile_n=small, fuse_junctions=0)
-        c1 = K.schedule_counts([(n, 0.4, 1e-3)], kappa, coarse_cutover=cutover, small_tile_n=small, fuse_junctions=1)
+        opts = dict(coarse_cutover=cutover, small_tile_n=small, tiny_tile_n=tiny)
+        c0 = K.schedule_counts([(n, 0.4, 1e-3)], kappa, fuse_junctions=0, **opts)
+        c1 = K.schedule_counts([(n, 0.4, 1e-3)], kappa, fuse_junctions=1, **opts)
         assert c0["grid_launches"] == len(seq)
         assert c1["grid_launches"] == len(seq) - fused
-        if kappa > 1 and any(sizes[e] <= small for e in range(1, cut)):
+        if kappa > 1 and any(sizes[e] <= max(small, tiny) for e in range(1, cut)):
             assert fused > 0
