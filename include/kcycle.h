@@ -92,7 +92,7 @@ typedef struct {
                                1 = one kernel per operation of Algorithm 4 ("paper-structured") */
     int32_t use_graph;      /* 1 = capture one cycle as a hipGraph and replay it (default) */
     int32_t coarse_cutover; /* levels with n <= cutover run in the persistent kernel (7..63; default 31) */
-    int32_t coarse_threads; /* threads of the persistent kernel (256 or 512; default 512) */
+    int32_t coarse_threads; /* threads of the persistent kernel (256, 512, or 1024 with FP32 cycles; default 512) */
     int32_t poll_every;     /* cycles launched between host polls of the stop flags (default 0 = adaptive) */
     int32_t coarse_wave_n;  /* persistent-kernel levels with n <= this run on one wave (0..15; default 15) */
     int32_t small_tile_n;   /* fused grid kernels on levels whose largest n <= this use 16 x 16 tiles instead of

@@ -24,10 +24,10 @@ from . import kcycle
 
 COARSE_CANDIDATES = tuple(
     dict(coarse_cutover=c, coarse_threads=t, coarse_wave_n=w)
-    for c in (15, 31, 63) for t in (256, 512) for w in (7, 15)
+    for c in (15, 31, 63) for t in (256, 512, 1024) for w in (7, 15)
     if not (c == 63 and t == 256)       # 63 rows need at least 8 waves
-)
-TILE_CANDIDATES = tuple(dict(tiny_tile_n=y, small_tile_n=s, mid_tile_n=t, stream_n=m) for y in (0, 63, 127, 255)
+)   # 1024 threads: FP32 cycles only (set_exec rejects it otherwise and the candidate is skipped)
+TILE_CANDIDATES = tuple(dict(tiny_tile_n=y, small_tile_n=s, mid_tile_n=t, stream_n=m) for y in (0, 63, 127, 255, 511)
                         for s in (0, 127, 255, 511, 1023) for t in (0, 1023, 2047, 4095) for m in (0, 1023, 2047, 4095))
 # the third stage re-tries only the RETRY fastest tile shapes of the first under the chosen persistent-kernel options
 RETRY = 4

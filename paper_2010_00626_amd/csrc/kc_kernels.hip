@@ -2402,6 +2402,8 @@ hipError_t launch_subtree(bool f32, const SubArgs& a, int32_t threads, int32_t l
     } else if (threads == 512) {
         if (f32) k_subtree<float, 512><<<a.count, 512, lds_bytes, s>>>(a);
         else k_subtree<double, 512><<<a.count, 512, lds_bytes, s>>>(a);
+    } else if (threads == 1024 && f32) {   // FP32 only: the FP64 kernel does not fit 128 registers
+        k_subtree<float, 1024><<<a.count, 1024, lds_bytes, s>>>(a);
     } else {
         return hipErrorInvalidValue;
     }
@@ -2423,6 +2425,8 @@ hipError_t prepare_subtree(bool f32, int32_t lds_bytes)
         e = hipFuncSetAttribute((const void*)k_subtree<float, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_subtree<float, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_subtree<float, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     } else {
         e = hipFuncSetAttribute((const void*)k_subtree<double, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e == hipSuccess)

@@ -1148,12 +1148,15 @@ kc_status kc_level_stencils(const kc_problem* p, int32_t max_levels, int32_t* nl
     return KC_OK;
 }
 
-static kc_status validate_exec(const kc_exec* e)
+// prec: the hierarchy's precision, or -1 for host-only planning
+static kc_status validate_exec(const kc_exec* e, int prec)
 {
     if (e->mode != 0 && e->mode != 1) return fail(KC_ERR_ARG, "exec.mode must be 0 or 1");
     if (e->coarse_cutover < 7 || e->coarse_cutover > 63) return fail(KC_ERR_ARG, "coarse_cutover must be in 7..63");
-    if (e->coarse_threads != 256 && e->coarse_threads != 512)
-        return fail(KC_ERR_ARG, "coarse_threads must be 256 or 512");
+    if (e->coarse_threads != 256 && e->coarse_threads != 512 && e->coarse_threads != 1024)
+        return fail(KC_ERR_ARG, "coarse_threads must be 256, 512 or 1024");
+    if (e->coarse_threads == 1024 && prec == (int)KC_F64)
+        return fail(KC_ERR_ARG, "coarse_threads 1024 needs FP32 cycles (the FP64 persistent kernel needs more registers)");
     if (e->poll_every < 0) return fail(KC_ERR_ARG, "poll_every must be >= 0");
     if (e->coarse_wave_n < 0 || e->coarse_wave_n > 15) return fail(KC_ERR_ARG, "coarse_wave_n must be in 0..15");
     if (e->small_tile_n < 0 || e->small_tile_n > 4095) return fail(KC_ERR_ARG, "small_tile_n must be in 0..4095");
@@ -1187,7 +1190,7 @@ kc_status kc_schedule_counts(const kc_problem* probs, int32_t count, const kc_ex
     h.count = count;
     kc_exec_default(&h.ex);
     if (exec) h.ex = *exec;
-    if ((s = validate_exec(&h.ex)) != KC_OK) return s;
+    if ((s = validate_exec(&h.ex, -1)) != KC_OK) return s;
     if ((s = make_layout(probs, count, KC_F64, h.lay)) != KC_OK) return s;
     build_host(&h, probs);
     // host-only planning: no device tables are written and the LDS limit is not checked
@@ -1228,7 +1231,7 @@ kc_status kc_create(const kc_problem* probs, int32_t count, kc_precision prec, c
     h->prec = prec;
     kc_exec_default(&h->ex);
     if (exec) h->ex = *exec;
-    kc_status s = validate_exec(&h->ex);
+    kc_status s = validate_exec(&h->ex, (int)prec);
     if (s != KC_OK) { delete h; return s; }
     s = make_layout(probs, count, prec, h->lay);
     if (s != KC_OK) { delete h; return s; }
@@ -1307,7 +1310,7 @@ kc_status kc_destroy(kc_hier* h)
 kc_status kc_set_exec(kc_hier* h, const kc_exec* exec)
 {
     if (!h || !exec) return fail(KC_ERR_ARG, "null argument");
-    kc_status s = validate_exec(exec);
+    kc_status s = validate_exec(exec, (int)h->prec);
     if (s != KC_OK) return s;
     HIPCHK(hipStreamSynchronize(h->stream));
     drop_graphs(h);

@@ -494,6 +494,29 @@ def test_junction_fusion_bitwise(n, kappa, nu1, nu2, prec, tile):
         assert res[0][0] == it_ref and np.array_equal(res[0][1], u_ref)
 
 
+@pytest.mark.parametrize("n,kappa,cutover,wave_n", [(255, 2, 31, 15), (511, 3, 63, 15), (255, 2 ** 31 - 1, 63, 7),
+                                                   (127, 2, 15, 0)])
+def test_persistent_kernel_1024_threads(n, kappa, cutover, wave_n):
+    """FP32 cycles with a 1024-thread persistent kernel give the bits of the
+    512-thread one (same iterations and solution); FP64 rejects the option."""
+    banner(f"persistent kernel 1024 threads n={n} kappa={kappa} cutover={cutover} wave_n={wave_n}")
+    rng = np.random.default_rng(n + kappa % 97)
+    th, ep = 1.1, 5e-3
+    f = rng.uniform(-1, 1, (n, n))
+    outs = []
+    for threads in (1024, 512):
+        H = K().Hierarchy([(n, th, ep)], "f32", exec=dict(coarse_cutover=cutover, coarse_threads=threads,
+                                                          coarse_wave_n=wave_n))
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        it, rr, st = H.solve(u, dev(f), kappa=kappa, tol=1e-8, maxit=3000)
+        assert st == [0]
+        outs.append((it[0], host(u)))
+        H.close()
+    assert outs[0][0] == outs[1][0] and np.array_equal(outs[0][1], outs[1][1])
+    with pytest.raises(K().KCycleError):
+        K().Hierarchy([(n, th, ep)], "f64", exec=dict(coarse_cutover=cutover, coarse_threads=1024))
+
+
 def test_autotuner_keeps_results():
     """The autotuner picks valid execution options; results under them are the default options' bits."""
     banner("autotuner")
