@@ -325,10 +325,25 @@ __global__ void __launch_bounds__(GRID_THREADS) k_finalize(StageArgs a)
     const int inst = blockIdx.x;
     const int b0 = a.tile_off[inst], nb = a.tile_off[inst + 1] - b0;
     if (nb == 0 || a.st[inst].done) return;
+    // thread t adds partials t, t + 256, ... in that order; loads go in groups of
+    // eight (clamped indices, masked at use) so that they are in flight together
+    constexpr int G = 8;
     double t0 = 0.0, t1 = 0.0;
-    for (int k = threadIdx.x; k < nb; k += GRID_THREADS) {
-        t0 += a.partial[2 * (b0 + k)];
-        t1 += a.partial[2 * (b0 + k) + 1];
+    for (int k0 = threadIdx.x; k0 < nb; k0 += G * GRID_THREADS) {
+        double p0[G], p1[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int k = min(k0 + g * GRID_THREADS, nb - 1);
+            p0[g] = a.partial[2 * (b0 + k)];
+            p1[g] = a.partial[2 * (b0 + k) + 1];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (k0 + g * GRID_THREADS < nb) {
+                t0 += p0[g];
+                t1 += p1[g];
+            }
+        }
     }
     const double S0 = block_sum<GRID_THREADS>(t0, red[0]);
     const double S1 = block_sum<GRID_THREADS>(t1, red[1]);

@@ -550,3 +550,31 @@ def test_model_fit_paper_mode_counts():
             rows.append(((kappa, nl), calls, model.n_ops_2d(kappa, nl), ms))
     fit = model.fit(rows)
     assert fit.alpha > 0 and fit.beta >= 0
+
+
+@pytest.mark.parametrize("kappa", [1, 2])
+def test_paper_protocol_counts(kappa):
+    """The f = 0 error-reduction protocol counts the same cycles as the oracle's
+    cycles from the same random start; its MGCG count is the first iteration
+    count whose error is below the target."""
+    banner(f"paper protocol kappa={kappa}")
+    from paper_2010_00626_amd import protocol
+    n, th, ep = 63, math.pi / 4, 1e-2
+    v0 = inputs.uniform_rhs(np.random.default_rng(3), n)
+    H = K().Hierarchy([(n, th, ep)], "f64")
+    r = protocol.standalone(H, dev(v0), kappa, chunk=8, maxc=2000)
+    Ho = O.Hierarchy(n, th, ep)
+    v, f0, e0, k = v0.copy(), np.zeros((n, n)), np.linalg.norm(v0), 0
+    while np.linalg.norm(v) / e0 >= protocol.TARGET:
+        v = Ho.cycle(v, f0, kappa=kappa, nu1=2, nu2=2)[0]
+        k += 1
+    assert r["cycles"] == k
+    m = protocol.mgcg(H, dev(v0), kappa, kmax=500)
+    it = m["iterations"]
+    assert it is not None and m["final_error"] < protocol.TARGET
+    b = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    H.apply_A(b, dev(v0))
+    u = torch.zeros_like(b)
+    H.pcg(u, b, kappa=kappa, nu1=2, nu2=2, tol=0.0, maxit=it - 1)
+    assert np.linalg.norm(host(u) - v0) / e0 >= protocol.TARGET
+    H.close()
