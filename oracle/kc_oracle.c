@@ -14,7 +14,8 @@
  *   - coarse operators: Galerkin A_{l+1} = R A_l P with full weighting R and
  *     bilinear prolongation P (Section 4, the Galerkin solvers; R is the
  *     adjoint of P as stated in the symmetry discussion of Section 4);
- *   - relaxation: damped Jacobi, simultaneous update (Section 4);
+ *   - relaxation: damped Jacobi, simultaneous update (Section 4), or the
+ *     alternating zebra line Gauss-Seidel of the third and fourth solvers;
  *   - cycles: Algorithm 1 (gamma-cycle), Algorithm 2 (F-cycle) and
  *     Algorithm 3 (kappa-cycle), recursion exactly as printed, including the
  *     redundant second call at the level above the coarsest (Section 1);
@@ -142,6 +143,10 @@ void or_hier_free(or_hier* h)
         }
         free(h->d.t[k]);
         free(h->s.t[k]);
+        for (int dir = 0; dir < 2; ++dir) {
+            free(h->d.zp[k][dir]); free(h->d.zu[k][dir]);
+            free(h->s.zp[k][dir]); free(h->s.zu[k][dir]);
+        }
     }
     free(h->fine_v); free(h->fine_f); free(h->fine_v32); free(h->fine_f32);
     free(h->d.chol);
@@ -189,6 +194,11 @@ int or_hier_new(int n, double theta, double eps, int n_coarsest, double omega, o
         or_hier_free(h);
         return OR_BREAKDOWN;
     }
+    for (int k = 0; k < L; ++k)
+        if (zebra_factor_d(&h->d, k) != OR_OK || zebra_factor_s(&h->s, k) != OR_OK) {
+            or_hier_free(h);
+            return OR_ERR_ARG;
+        }
     size_t m0 = (size_t)n * n;
     h->fine_v = (double*)calloc(m0, sizeof(double));
     h->fine_f = (double*)calloc(m0, sizeof(double));
@@ -212,6 +222,22 @@ int or_hier_info(const or_hier* h, int* nlevels, int* sizes, double* stencils)
 void or_hier_apply(const or_hier* h, const double* x, double* y)
 {
     apply_d(h->d.n[0], h->d.s[0], h->d.h2inv[0], x, y);
+}
+
+int or_set_smoother(or_hier* h, int smoother)
+{
+    if (smoother != 0 && smoother != 1) return OR_ERR_ARG;
+    h->d.smoother = h->s.smoother = smoother;
+    return OR_OK;
+}
+
+void or_zebra_relax(or_hier* h, int dir, double* v, const double* f)
+{
+    h->d.v[0] = v;
+    h->d.f[0] = (double*)f;
+    zebra_d(&h->d, 0, dir);
+    h->d.v[0] = NULL;
+    h->d.f[0] = NULL;
 }
 
 /* ------------------------------------------------------------------ */

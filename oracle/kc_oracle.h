@@ -66,6 +66,15 @@ int or_hier_info(const or_hier* h, int* nlevels, int* sizes, double* stencils);
 /* y = A_1 x on the fine level */
 void or_hier_apply(const or_hier* h, const double* x, double* y);
 
+/* relaxation of every cycle, solve and CG run on h: 0 = damped Jacobi (the
+ * default), 1 = alternating zebra line Gauss-Seidel (relaxation r of a
+ * smoothing step along x-lines when r is even, y-lines when odd; lines of
+ * even index first) */
+int or_set_smoother(or_hier* h, int smoother);
+
+/* one zebra relaxation on the fine level in place (dir 0: x-lines, 1: y-lines) */
+void or_zebra_relax(or_hier* h, int dir, double* v, const double* f);
+
 /*
  * One cycle on the fine level (Algorithm 3 for kind 0, Algorithm 1 for kind 1
  * with cycle index = param, Algorithm 2 for kind 2).  v is updated in place;

@@ -66,6 +66,9 @@ def lib():
         L.or_hier_free.argtypes = [hp]
         L.or_hier_info.argtypes = [hp, ip, ip, dp]
         L.or_hier_apply.argtypes = [hp, dp, dp]
+        L.or_set_smoother.argtypes = [hp, C.c_int]
+        L.or_set_smoother.restype = C.c_int
+        L.or_zebra_relax.argtypes = [hp, C.c_int, dp, dp]
         L.or_cycle.argtypes = [hp, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, i32p, C.c_int64]
         L.or_cycle.restype = C.c_int64
         L.or_kcycle_f32.argtypes = [hp, C.c_int, C.c_int, C.c_int, fp, fp]
@@ -150,13 +153,18 @@ def decode_trace(tr: np.ndarray):
 class Hierarchy:
     """Levels of the rotated anisotropic diffusion problem, Galerkin coarsened."""
 
-    def __init__(self, n: int, theta: float, eps: float, n_coarsest: int = 1, omega: float = 0.8):
+    def __init__(self, n: int, theta: float, eps: float, n_coarsest: int = 1, omega: float = 0.8,
+                 smoother: str = "jacobi"):
+        """smoother: "jacobi" (damped, omega) or "zebra" (alternating line Gauss-Seidel)."""
         self.n, self.theta, self.eps, self.omega = n, theta, eps, omega
         h = C.c_void_p()
         rc = lib().or_hier_new(n, theta, eps, n_coarsest, omega, C.byref(h))
         if rc != OK:
             raise ValueError(f"or_hier_new failed ({rc}) for n={n}, n_coarsest={n_coarsest}")
         self._h = h
+        self.smoother = smoother
+        if lib().or_set_smoother(h, {"jacobi": 0, "zebra": 1}[smoother]) != OK:
+            raise ValueError(f"unknown smoother {smoother}")
         nl = C.c_int()
         sizes = (C.c_int * 16)()
         st = np.zeros(16 * 9)
@@ -177,6 +185,13 @@ class Hierarchy:
         y = np.empty_like(x)
         lib().or_hier_apply(self._h, _dp(x), _dp(y))
         return y
+
+    def zebra_relax(self, v, f, direction: int):
+        """One zebra line relaxation of the fine level (0: x-lines, 1: y-lines); returns the new v."""
+        v = np.array(v, dtype=np.float64, order="C", copy=True)
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        lib().or_zebra_relax(self._h, int(direction), _dp(v), _dp(f))
+        return v
 
     # ---- cycles ----
     def cycle(self, v, f, kappa=1, nu1=2, nu2=2, kind=KIND_KAPPA, trace_cap=0):
