@@ -82,7 +82,10 @@ typedef struct {
     int32_t kappa;
     int32_t nu1;
     int32_t nu2;
-    int32_t reserved;
+    int32_t smoother;   /* 0 = damped Jacobi with omega (default); 1 = alternating zebra line Gauss-Seidel (Section 4,
+                           third and fourth solvers): relaxation r of a smoothing step solves every x-line (r even)
+                           or y-line (r odd) exactly, lines of even index first, then odd; runs in the
+                           paper-structured execution mode only (exec.mode = 1, else KC_ERR_ARG) */
     double omega;
 } kc_cycle_params;
 

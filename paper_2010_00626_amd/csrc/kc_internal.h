@@ -41,6 +41,8 @@ struct InstDev {
     LevelDev lev[MAXL];  // cycle levels (level 0 may alias user arrays)
     const double* chol64;  // lower Cholesky factor of the coarsest matrix, nc2 x nc2 row-major (scaled system)
     const float* chol32;
+    const double* zt64[MAXL];  // zebra line-solve tables of level d: pivots, multipliers (x-lines), then (y-lines), n each
+    const float* zt32[MAXL];
     int32_t lds_off[MAXL]; // persistent kernel: element offset of level d's three (n+2)^2 arrays
     int32_t ops_beg[MAXL + 1]; // persistent kernel op list of a call with counter k = 1..MAXL+1
     int32_t ops_len[MAXL + 1];
@@ -179,6 +181,7 @@ enum GridKernel : int32_t {
     GK_GRAD = 20,      // -lam^T dS u / h^2 for theta and eps
     GK_ZERO_SELF = 22, // unfused: A[d] = 0 on the launch's own level
     GK_POSTPRE = 23,   // fused junction of sibling calls: post (nu2 = src) of the first + pre (nu) of the second
+    GK_ZEBRA = 24,     // zebra line relaxation in place on buffer src, lines of colour dst, direction nu (0 x, 1 y)
 };
 
 // launches kernel k (and, when a.fin is set and with_finalize, the finalize kernel after it)

@@ -462,6 +462,76 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// zebra line relaxation (paper-structured mode): one thread per line of the
+// launch's colour (lines 2 m + colour), solving that line's tridiagonal system
+// exactly with its neighbouring lines' current values, in place.  Forward
+// pass: d_q = F_q - (six off-line products: line j-1 then j+1, west to east,
+// for x-lines; column i-1 then i+1, south to north, for y-lines);
+// y_q = (d_q - lo y_{q-1}) / p_q, written over the line; backward pass
+// x_q = y_q - u_q x_{q+1}.  p, u: the level's pivots and upper multipliers.
+// ---------------------------------------------------------------------------
+template <typename T> struct ZT;
+template <> struct ZT<double> { static __device__ const double* t(const InstDev& I, int d) { return I.zt64[d]; } };
+template <> struct ZT<float> { static __device__ const float* t(const InstDev& I, int d) { return I.zt32[d]; } };
+
+template <typename T>
+__global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
+{
+    Tile t;
+    if (!get_tile(a, a.depth, false, t)) return;
+    const InstDev& I = a.inst[t.inst];
+    const int d = a.depth;
+    const LevelDev& Lv = I.lev[d];
+    const int n = Lv.n, dir = a.nu;
+    const int line = 2 * (t.blk * GRID_THREADS + (int)threadIdx.x) + a.dst;
+    if (line >= n) return;
+    T* V = buf<T>(Lv, a.src);
+    const int ldv = a.src ? Lv.ldb : Lv.lda;
+    const T* F = (const T*)Lv.F;
+    const T fs = (T)Lv.fscale;
+    Sten<T> s;
+    s.load(P<T>::s(I, d));
+    const T* tab = ZT<T>::t(I, d) + (size_t)dir * 2 * n;
+    const T* piv = tab;
+    const T* mul = tab + n;
+    const T lo = dir == 0 ? s.c[3] : s.c[1];
+    auto at = [&](int j, int i) -> T {
+        return ((unsigned)j < (unsigned)n && (unsigned)i < (unsigned)n) ? V[(size_t)j * ldv + i] : T(0);
+    };
+    T prev = T(0);
+    for (int q = 0; q < n; ++q) {
+        const int j = dir == 0 ? line : q, i = dir == 0 ? q : line;
+        T acc = T(0);
+        if (dir == 0) {
+            acc += s.c[0] * at(j - 1, i - 1);
+            acc += s.c[1] * at(j - 1, i);
+            acc += s.c[2] * at(j - 1, i + 1);
+            acc += s.c[6] * at(j + 1, i - 1);
+            acc += s.c[7] * at(j + 1, i);
+            acc += s.c[8] * at(j + 1, i + 1);
+        } else {
+            acc += s.c[0] * at(j - 1, i - 1);
+            acc += s.c[3] * at(j, i - 1);
+            acc += s.c[6] * at(j + 1, i - 1);
+            acc += s.c[2] * at(j - 1, i + 1);
+            acc += s.c[5] * at(j, i + 1);
+            acc += s.c[8] * at(j + 1, i + 1);
+        }
+        const T dq = fs * F[(size_t)j * Lv.ldf + i] - acc;
+        const T y = (q == 0) ? dq / piv[0] : (dq - lo * prev) / piv[q];
+        V[(size_t)j * ldv + i] = y;
+        prev = y;
+    }
+    T next = prev;   // x_{n-1} = y_{n-1}
+    for (int q = n - 2; q >= 0; --q) {
+        const int j = dir == 0 ? line : q, i = dir == 0 ? q : line;
+        const T x = V[(size_t)j * ldv + i] - mul[q] * next;
+        V[(size_t)j * ldv + i] = x;
+        next = x;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // band-mapped passes over an LDS region (small tiles): the block's threads
 // form bands of BW consecutive lanes, lane l of a band is column C0 + l and
 // band b owns the U consecutive rows from R0 + b U.  A thread loads the
@@ -2396,6 +2466,11 @@ hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nb, h
     case GK_PRE: e = f32 ? launch_pre<float>(a, nb, s) : launch_pre<double>(a, nb, s); break;
     case GK_POST: e = f32 ? launch_post<float>(a, nb, s) : launch_post<double>(a, nb, s); break;
     case GK_POSTPRE: e = f32 ? launch_postpre<float>(a, nb, s) : launch_postpre<double>(a, nb, s); break;
+    case GK_ZEBRA:
+        if (f32) k_zebra<float><<<nb, GRID_THREADS, 0, s>>>(a);
+        else k_zebra<double><<<nb, GRID_THREADS, 0, s>>>(a);
+        e = hipGetLastError();
+        break;
     case GK_SWEEP: case GK_RESID: case GK_RESTRICT: case GK_ZERO: case GK_PROLONG: case GK_ADD: case GK_COPY:
     case GK_NORM: case GK_ZERO_SELF:
         e = f32 ? launch_unfused<float>(k, a, nb, s) : launch_unfused<double>(k, a, nb, s);

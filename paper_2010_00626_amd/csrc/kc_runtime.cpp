@@ -171,6 +171,8 @@ struct InstLayout {
     size_t A[MAXL] = {}, B[MAXL] = {}, F[MAXL] = {};   // cycle arrays by level (A, F of level 0 unused in F64)
     size_t chol64 = 0, chol32 = 0, ops = 0;
     size_t r = 0, z = 0, p = 0, q = 0;
+    size_t zt64 = 0, zt32 = 0;   // zebra line-solve tables, per level [pivots x | multipliers x | pivots y | multipliers y]
+    size_t zoff[MAXL] = {};      // element offset of level d's tables
 };
 
 struct Layout {
@@ -234,6 +236,13 @@ kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Lay
         il.chol64 = take(sizeof(double) * m * m);
         il.chol32 = take(sizeof(float) * m * m);
         il.ops = take(sizeof(uint32_t) * OPS_CAP);
+        size_t zt = 0;
+        for (int d = 0; d < il.L; ++d) {
+            il.zoff[d] = zt;
+            zt += 4 * (size_t)il.n[d];
+        }
+        il.zt64 = take(sizeof(double) * zt);
+        il.zt32 = take(sizeof(float) * zt);
         const size_t v64 = (size_t)il.n[0] * il.ld[0] * 8;
         il.r = take(v64);
         il.z = take(v64);
@@ -327,7 +336,7 @@ struct kc_hier {
     bool compacted = false;                    // the tables cover only the instances still iterating
     int last_compactions = 0;                  // table compactions during the last driver call
     int sub_lds = 0;
-    std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> graphs;   // (driver, kappa, nu1, nu2, smoother)
     double omega_set = -1.0;
     // stats
     int64_t last_grid = 0, last_sub = 0, last_sub_stages = 0, last_cycles = 0, last_launched = 0;
@@ -483,7 +492,24 @@ void gen_paper(kc_hier* h, int d, int k, const kc_cycle_params& c, bool f32, int
         L.sa.dst = dst;
         out.push_back(L);
     };
-    for (int s = 0; s < c.nu1; ++s) { op(GK_SWEEP, cur[d], cur[d] ^ 1); cur[d] ^= 1; }
+    // relaxation r: a damped-Jacobi sweep into the other buffer, or a zebra
+    // relaxation in place (x-lines for even r, y-lines for odd r; two launches,
+    // lines of even index first): src = buffer, dst = colour, nu = direction
+    auto relax = [&](int r) {
+        if (c.smoother == 1) {
+            for (int color = 0; color < 2; ++color) {
+                Launch L = grid(h, GK_ZEBRA, f32, tt_lvl(d), d);
+                L.sa.src = cur[d];
+                L.sa.dst = color;
+                L.sa.nu = r & 1;
+                out.push_back(L);
+            }
+        } else {
+            op(GK_SWEEP, cur[d], cur[d] ^ 1);
+            cur[d] ^= 1;
+        }
+    };
+    for (int s = 0; s < c.nu1; ++s) relax(s);
     op(GK_RESID, cur[d], cur[d] ^ 1);
     op(GK_RESTRICT, cur[d] ^ 1, 0);
     op(GK_ZERO, 0, 0);
@@ -497,7 +523,7 @@ void gen_paper(kc_hier* h, int d, int k, const kc_cycle_params& c, bool f32, int
         out.push_back(L);
     }
     op(GK_ADD, cur[d], cur[d] ^ 1);
-    for (int s = 0; s < c.nu2; ++s) { op(GK_SWEEP, cur[d], cur[d] ^ 1); cur[d] ^= 1; }
+    for (int s = 0; s < c.nu2; ++s) relax(s);
 }
 
 void cycle_paper(kc_hier* h, const kc_cycle_params& c, int kappa, bool zg, bool f32, std::vector<Launch>& out)
@@ -660,6 +686,32 @@ kc_status plan_exec(kc_hier* h)
     return KC_OK;
 }
 
+// Zebra line relaxation (Section 4, third and fourth solvers): along a line
+// the matrix is tridiagonal with constant entries lo (previous point), the
+// diagonal and up (next point), in h^2-scaled units; elimination uses the
+// pivots p (p_0 = diag, p_q = diag - lo u_{q-1}) and upper multipliers
+// u_q = up / p_q.  Appends [p, u] for x-lines (west / centre / east entries)
+// and then for y-lines (south / centre / north) of one level, computed in T
+// from the stencil rounded to T.
+template <typename T>
+void line_tables(int n, const double s64[9], std::vector<T>& out)
+{
+    T s[9];
+    for (int q = 0; q < 9; ++q) s[q] = (T)s64[q];
+    for (int dir = 0; dir < 2; ++dir) {
+        const T lo = dir == 0 ? s[3] : s[1], dg = s[4], up = dir == 0 ? s[5] : s[7];
+        std::vector<T> p((size_t)n), u((size_t)n);
+        p[0] = dg;
+        u[0] = up / p[0];
+        for (int q = 1; q < n; ++q) {
+            p[q] = dg - lo * u[q - 1];
+            u[q] = up / p[q];
+        }
+        out.insert(out.end(), p.begin(), p.end());
+        out.insert(out.end(), u.begin(), u.end());
+    }
+}
+
 void fill_inst_static(kc_hier* h)
 {
     const bool f64 = h->prec == KC_F64;
@@ -692,6 +744,10 @@ void fill_inst_static(kc_hier* h)
         I.ops = (const uint32_t*)(h->ws + hi.il.ops);
         I.chol64 = (const double*)(h->ws + hi.il.chol64);
         I.chol32 = (const float*)(h->ws + hi.il.chol32);
+        for (int d = 0; d < hi.il.L; ++d) {
+            I.zt64[d] = (const double*)(h->ws + hi.il.zt64) + hi.il.zoff[d];
+            I.zt32[d] = (const float*)(h->ws + hi.il.zt32) + hi.il.zoff[d];
+        }
         I.r = (double*)(h->ws + hi.il.r);
         I.z = (double*)(h->ws + hi.il.z);
         I.p = (double*)(h->ws + hi.il.p);
@@ -746,6 +802,7 @@ kc_status check_cycle(const kc_cycle_params* c)
     if (c->kappa < 1) return fail(KC_ERR_ARG, "kappa must be >= 1");
     if (c->nu1 < 0 || c->nu2 < 0 || c->nu1 > 3 || c->nu2 > 3) return fail(KC_ERR_ARG, "nu1, nu2 must be in 0..3");
     if (!(c->omega > 0.0) || !std::isfinite(c->omega)) return fail(KC_ERR_ARG, "omega must be positive");
+    if (c->smoother != 0 && c->smoother != 1) return fail(KC_ERR_ARG, "smoother must be 0 (damped Jacobi) or 1 (zebra)");
     return KC_OK;
 }
 
@@ -808,7 +865,7 @@ kc_status launch_iteration(kc_hier* h, int drv, const kc_cycle_params& c, int ti
         for (int t = 0; t < times; ++t) HIPCHK(run(h, ls));
         return KC_OK;
     }
-    auto key = std::make_tuple(drv, clamp_kappa(h, c.kappa), c.nu1, c.nu2, 0.0);
+    auto key = std::make_tuple(drv, clamp_kappa(h, c.kappa), c.nu1, c.nu2, (double)c.smoother);
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         hipGraph_t g = nullptr;
@@ -943,6 +1000,8 @@ kc_status prepare_call(kc_hier* h, const kc_cycle_params* c)
 {
     kc_status s = check_cycle(c);
     if (s != KC_OK) return s;
+    if (c->smoother == 1 && h->ex.mode != 1)
+        return fail(KC_ERR_ARG, "the zebra smoother runs in the paper-structured execution mode (exec.mode = 1)");
     if (c->omega != h->omega_set) {
         set_omega(h, c->omega);
         h->omega_set = c->omega;
@@ -1006,6 +1065,7 @@ std::string launch_name(const kc_hier* h, const Launch& L)
         if (L.sa.flags & 32) return k + "<" + T + ", " + nu + ", 8, 8>";
         return k + "<" + T + ", " + nu + ", 64, 32>";
     }
+    if (L.gk == GK_ZEBRA) return std::string("k_zebra<") + T + ">";
     if (L.gk <= GK_NORM || L.gk == GK_ZERO_SELF) return std::string("k_unfused<") + T + ", " + std::to_string(L.gk) + ">";
     return std::string("k_driver<") + (L.f32 ? "true" : "false") + ", " + std::to_string(L.gk) + ">";
     (void)h;
@@ -1277,6 +1337,16 @@ kc_status kc_create(const kc_problem* probs, int32_t count, kc_precision prec, c
             hipMemcpyAsync(h->ws + hi.il.chol32, c32.data(), c32.size() * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
             hipStreamSynchronize(h->stream) != hipSuccess)
             return cleanup(fail(KC_ERR_HIP, "upload of the coarsest factor failed"));
+        std::vector<double> z64;
+        std::vector<float> z32;
+        for (int d = 0; d < hi.il.L; ++d) {
+            line_tables<double>(hi.il.n[d], hi.s[d], z64);
+            line_tables<float>(hi.il.n[d], hi.s[d], z32);
+        }
+        if (hipMemcpyAsync(h->ws + hi.il.zt64, z64.data(), z64.size() * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+            hipMemcpyAsync(h->ws + hi.il.zt32, z32.data(), z32.size() * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess)
+            return cleanup(fail(KC_ERR_HIP, "upload of the line-solve tables failed"));
     }
     if ((s = plan_exec(h)) != KC_OK) return cleanup(s);
     fill_inst_static(h);

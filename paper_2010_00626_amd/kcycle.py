@@ -38,8 +38,11 @@ class Problem(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_coarsest", C.c_int32), ("theta", C.c_double), ("eps", C.c_double)]
 
 
+SMOOTHERS = {"jacobi": 0, "zebra": 1}   # damped Jacobi; alternating zebra line Gauss-Seidel (paper mode only)
+
+
 class CycleParams(C.Structure):
-    _fields_ = [("kappa", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("kappa", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32), ("smoother", C.c_int32),
                 ("omega", C.c_double)]
 
 
@@ -220,21 +223,22 @@ class Hierarchy:
             lds[i] = t.stride(0)
         return ptrs, lds
 
-    def _params(self, kappa, nu1, nu2, omega):
-        return CycleParams(int(kappa), int(nu1), int(nu2), 0, float(omega))
+    def _params(self, kappa, nu1, nu2, omega, smoother="jacobi"):
+        sm = SMOOTHERS[smoother] if isinstance(smoother, str) else int(smoother)
+        return CycleParams(int(kappa), int(nu1), int(nu2), sm, float(omega))
 
     # ---- entry points ----
-    def cycle(self, v, f, kappa=1, nu1=2, nu2=2, omega=0.8):
+    def cycle(self, v, f, kappa=1, nu1=2, nu2=2, omega=0.8, smoother="jacobi"):
         """One kappa-cycle in place on v (FP64 hierarchies)."""
         pv, lv = self._arrays(v, "v")
         pf, lf = self._arrays(f, "f")
-        c = self._params(kappa, nu1, nu2, omega)
+        c = self._params(kappa, nu1, nu2, omega, smoother)
         _check(lib().kc_cycle(self._h, pv, lv, pf, lf, C.byref(c)))
 
-    def _solver(self, fn, u, f, kappa, nu1, nu2, omega, tol, maxit):
+    def _solver(self, fn, u, f, kappa, nu1, nu2, omega, tol, maxit, smoother="jacobi"):
         pu, lu = self._arrays(u, "u")
         pf, lf = self._arrays(f, "f")
-        c = self._params(kappa, nu1, nu2, omega)
+        c = self._params(kappa, nu1, nu2, omega, smoother)
         it = (C.c_int32 * self.count)()
         rr = (C.c_double * self.count)()
         st = (C.c_int32 * self.count)()
@@ -243,13 +247,13 @@ class Hierarchy:
             _check(rc)
         return list(it), list(rr), list(st)
 
-    def solve(self, u, f, kappa=1, nu1=2, nu2=2, omega=0.8, tol=1e-8, maxit=1000):
+    def solve(self, u, f, kappa=1, nu1=2, nu2=2, omega=0.8, tol=1e-8, maxit=1000, smoother="jacobi"):
         """Stand-alone kappa-cycles until ||f - A u|| / ||f|| < tol; returns (iters, relres, status)."""
-        return self._solver(lib().kc_solve, u, f, kappa, nu1, nu2, omega, tol, maxit)
+        return self._solver(lib().kc_solve, u, f, kappa, nu1, nu2, omega, tol, maxit, smoother)
 
-    def pcg(self, u, f, kappa=1, nu1=1, nu2=1, omega=0.8, tol=1e-8, maxit=500):
+    def pcg(self, u, f, kappa=1, nu1=1, nu2=1, omega=0.8, tol=1e-8, maxit=500, smoother="jacobi"):
         """CG preconditioned by one kappa-cycle per iteration; returns (iters, relres, status)."""
-        return self._solver(lib().kc_pcg, u, f, kappa, nu1, nu2, omega, tol, maxit)
+        return self._solver(lib().kc_pcg, u, f, kappa, nu1, nu2, omega, tol, maxit, smoother)
 
     def residual_history(self, instance: int = 0) -> list:
         """Relative residuals of the last solve / pcg of one instance, entry k
@@ -278,26 +282,27 @@ class Hierarchy:
         _check(lib().kc_set_exec(self._h, C.byref(e)))
         self._e = e
 
-    def time_stage(self, which: int, kappa=3, nu1=2, nu2=2, omega=0.8, reps=50):
+    def time_stage(self, which: int, kappa=3, nu1=2, nu2=2, omega=0.8, reps=50, smoother="jacobi"):
         """Average ms of one launch of a schedule stage and its algorithmic bytes."""
-        c = self._params(kappa, nu1, nu2, omega)
+        c = self._params(kappa, nu1, nu2, omega, smoother)
         ms, b = C.c_double(), C.c_double()
         _check(lib().kc_time_stage(self._h, int(which), C.byref(c), int(reps), C.byref(ms), C.byref(b)))
         return ms.value, b.value
 
-    def time_cycles(self, v, f, kappa=1, nu1=2, nu2=2, omega=0.8, reps=10):
+    def time_cycles(self, v, f, kappa=1, nu1=2, nu2=2, omega=0.8, reps=10, smoother="jacobi"):
         """Milliseconds per kappa-cycle over `reps` back-to-back cycles (FP64)."""
         pv, lv = self._arrays(v, "v")
         pf, lf = self._arrays(f, "f")
-        c = self._params(kappa, nu1, nu2, omega)
+        c = self._params(kappa, nu1, nu2, omega, smoother)
         ms = C.c_double()
         _check(lib().kc_time_cycles(self._h, pv, lv, pf, lf, C.byref(c), int(reps), C.byref(ms)))
         return ms.value
 
-    def profile_iteration(self, driver: str = "solve", kappa=1, nu1=2, nu2=2, omega=0.8, reps=5) -> dict:
+    def profile_iteration(self, driver: str = "solve", kappa=1, nu1=2, nu2=2, omega=0.8, reps=5,
+                          smoother="jacobi") -> dict:
         """Per-kernel times of one solver iteration ("solve" or "pcg"; that
         driver must have run last on this hierarchy, whose arrays keep iterating)."""
-        c = self._params(kappa, nu1, nu2, omega)
+        c = self._params(kappa, nu1, nu2, omega, smoother)
         buf = C.create_string_buffer(1 << 20)
         _check(lib().kc_profile_iteration(self._h, 1 if driver == "pcg" else 0, C.byref(c), int(reps), buf, len(buf)))
         return json.loads(buf.value.decode())

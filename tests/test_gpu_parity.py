@@ -578,3 +578,93 @@ def test_paper_protocol_counts(kappa):
     H.pcg(u, b, kappa=kappa, nu1=2, nu2=2, tol=0.0, maxit=it - 1)
     assert np.linalg.norm(host(u) - v0) / e0 >= protocol.TARGET
     H.close()
+
+
+ZEBRA_CASES = [(63, 1, 2, 2, 1), (63, 3, 2, 2, 3), (255, 2, 2, 2, 1), (127, 2 ** 31 - 1, 1, 1, 1), (255, 4, 0, 3, 1),
+               (127, 2, 3, 0, 7)]
+
+
+@pytest.mark.parametrize("n,kappa,nu1,nu2,nc", ZEBRA_CASES)
+def test_zebra_cycle_bitwise(n, kappa, nu1, nu2, nc):
+    """Alternating zebra line relaxation (paper-structured mode) gives the oracle's bits."""
+    banner(f"zebra cycle n={n} kappa={kappa} nu={nu1}+{nu2} n_coarsest={nc}")
+    rng = np.random.default_rng(n + 3 * nu1 + nc)
+    th, ep = 0.2, 1e-3
+    v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
+    H = K().Hierarchy([(n, th, ep, nc)], "f64", exec=dict(mode="paper"))
+    v = dev(v0)
+    H.cycle(v, dev(f), kappa=kappa, nu1=nu1, nu2=nu2, smoother="zebra")
+    Ho = O.Hierarchy(n, th, ep, nc, smoother="zebra")
+    ref = Ho.cycle(v0, f, kappa=min(kappa, 64), nu1=nu1, nu2=nu2)[0]
+    assert np.array_equal(host(v), ref)
+    H.cycle(v, dev(f), kappa=kappa, nu1=nu1, nu2=nu2, smoother="zebra")   # replay of the captured schedule
+    assert np.array_equal(host(v), Ho.cycle(ref, f, kappa=min(kappa, 64), nu1=nu1, nu2=nu2)[0])
+    H.close()
+
+
+@pytest.mark.parametrize("n,kappa,theta", [(255, 2, 0.0), (255, 3, math.pi / 4), (511, 4, 1.4)])
+def test_zebra_solve_bitwise(n, kappa, theta):
+    """Stand-alone zebra solve: the oracle's iterations and bits; and the
+    Jacobi hierarchy on the same handle is unaffected."""
+    banner(f"zebra solve n={n} kappa={kappa} theta={theta}")
+    f = inputs.uniform_rhs(np.random.default_rng(n + kappa), n)
+    ep = 1e-4
+    Ho = O.Hierarchy(n, theta, ep, smoother="zebra")
+    u_ref, rc, it_ref, hist = Ho.solve(f, kappa=kappa, tol=1e-8, maxit=500)
+    assert rc == O.OK
+    check_stop_margin(hist, 1e-8)
+    H = K().Hierarchy([(n, theta, ep)], "f64", exec=dict(mode="paper"))
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    iters, relres, status = H.solve(u, dev(f), kappa=kappa, tol=1e-8, maxit=500, smoother="zebra")
+    assert status == [0] and iters[0] == it_ref
+    assert np.array_equal(host(u), u_ref)
+    v0 = np.random.default_rng(1).uniform(-1, 1, (n, n))   # a Jacobi cycle on the same handle (separate graph)
+    v = dev(v0)
+    H.cycle(v, dev(f), kappa=kappa)
+    assert np.array_equal(host(v), O.Hierarchy(n, theta, ep).cycle(v0, f, kappa=kappa)[0])
+    H.close()
+
+
+@pytest.mark.parametrize("n,kappa,f32", [(255, 2, False), (255, 4, True), (511, 3, False)])
+def test_zebra_pcg(n, kappa, f32):
+    banner(f"zebra PCG n={n} kappa={kappa} f32={f32}")
+    f = inputs.gaussian_sum_rhs(5, n)
+    th, ep = 3 * math.pi / 8, 1e-5
+    Ho = O.Hierarchy(n, th, ep, smoother="zebra")
+    u_ref, rc, it_ref, hist = Ho.pcg(f, kappa=kappa, nu1=2, nu2=2, tol=1e-8, maxit=300, precond_f32=f32)
+    assert rc == O.OK
+    H = K().Hierarchy([(n, th, ep)], precision="f32" if f32 else "f64", exec=dict(mode="paper"))
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    iters, relres, status = H.pcg(u, dev(f), kappa=kappa, nu1=2, nu2=2, tol=1e-8, maxit=300, smoother="zebra")
+    assert status == [0]
+    assert abs(iters[0] - it_ref) <= (0 if not f32 else 1)
+    got = host(u)
+    assert relmax(got, u_ref) <= (1e-9 if not f32 else 1e-6)
+    assert np.linalg.norm(f - Ho.apply(got)) / np.linalg.norm(f) < 2e-8
+    H.close()
+
+
+@pytest.mark.parametrize("n,kappa", [(255, 2), (511, 3)])
+def test_zebra_ir_fp32(n, kappa):
+    banner(f"zebra FP32 cycles + FP64 refinement n={n} kappa={kappa}")
+    f = inputs.uniform_rhs(np.random.default_rng(2), n)
+    th, ep = 0.1, 1e-5
+    Ho = O.Hierarchy(n, th, ep, smoother="zebra")
+    u_ir, rc, it_ir, _ = Ho.ir_solve(f, kappa=kappa, tol=1e-8, maxit=500)
+    assert rc == O.OK
+    H = K().Hierarchy([(n, th, ep)], precision="f32", exec=dict(mode="paper"))
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    iters, relres, status = H.solve(u, dev(f), kappa=kappa, tol=1e-8, maxit=500, smoother="zebra")
+    assert status == [0] and abs(iters[0] - it_ir) <= 1
+    got = host(u)
+    assert np.linalg.norm(f - Ho.apply(got)) / np.linalg.norm(f) < 1e-8
+    assert relmax(got, u_ir) <= 1e-6
+    H.close()
+
+
+def test_zebra_needs_paper_mode():
+    H = K().Hierarchy([(63, 0.3, 1e-3)], "f64")
+    u = torch.zeros((63, 63), dtype=torch.float64, device="cuda")
+    with pytest.raises(K().KCycleError):
+        H.solve(u, dev(np.ones((63, 63))), kappa=2, smoother="zebra")
+    H.close()
