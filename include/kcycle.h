@@ -85,7 +85,8 @@ typedef struct {
     int32_t smoother;   /* 0 = damped Jacobi with omega (default); 1 = alternating zebra line Gauss-Seidel (Section 4,
                            third and fourth solvers): relaxation r of a smoothing step solves every x-line (r even)
                            or y-line (r odd) exactly, lines of even index first, then odd; runs in the
-                           paper-structured execution mode only (exec.mode = 1, else KC_ERR_ARG) */
+                           paper-structured execution mode only (exec.mode = 1) and for n <= 16383, else
+                           KC_ERR_ARG */
     double omega;
 } kc_cycle_params;
 

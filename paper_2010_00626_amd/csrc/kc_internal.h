@@ -41,7 +41,7 @@ struct InstDev {
     LevelDev lev[MAXL];  // cycle levels (level 0 may alias user arrays)
     const double* chol64;  // lower Cholesky factor of the coarsest matrix, nc2 x nc2 row-major (scaled system)
     const float* chol32;
-    const double* zt64[MAXL];  // zebra line-solve tables of level d: pivots, multipliers (x-lines), then (y-lines), n each
+    const double* zt64[MAXL];  // zebra line-solve tables of level d: reciprocal pivots, multipliers (x-lines), then (y-lines), n each
     const float* zt32[MAXL];
     int32_t lds_off[MAXL]; // persistent kernel: element offset of level d's three (n+2)^2 arrays
     int32_t ops_beg[MAXL + 1]; // persistent kernel op list of a call with counter k = 1..MAXL+1

@@ -463,71 +463,118 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a)
 
 // ---------------------------------------------------------------------------
 // zebra line relaxation (paper-structured mode): one thread per line of the
-// launch's colour (lines 2 m + colour), solving that line's tridiagonal system
+// launch's colour (lines 2 m + colour, 64 per workgroup), solving that line's tridiagonal system
 // exactly with its neighbouring lines' current values, in place.  Forward
 // pass: d_q = F_q - (six off-line products: line j-1 then j+1, west to east,
 // for x-lines; column i-1 then i+1, south to north, for y-lines);
-// y_q = (d_q - lo y_{q-1}) / p_q, written over the line; backward pass
-// x_q = y_q - u_q x_{q+1}.  p, u: the level's pivots and upper multipliers.
+// y_q = (d_q - lo y_{q-1}) r_q, written over the line; backward pass
+// x_q = y_q - u_q x_{q+1}.  r, u: the level's reciprocal pivots and upper
+// multipliers.
+//
+// Both passes go along the line in chunks of ZK points: every load of a chunk
+// (the two neighbouring lines one point ahead, F and r; or the line's own y
+// values and u) is issued before the chunk's stores, so a chunk costs one
+// memory round trip; the neighbouring lines' values at q - 1, q, q + 1 slide
+// through registers, and the chunk's d_q are formed before the recurrence,
+// whose serial step is one multiply-subtract-multiply.
 // ---------------------------------------------------------------------------
 template <typename T> struct ZT;
 template <> struct ZT<double> { static __device__ const double* t(const InstDev& I, int d) { return I.zt64[d]; } };
 template <> struct ZT<float> { static __device__ const float* t(const InstDev& I, int d) { return I.zt32[d]; } };
 
-template <typename T>
+template <typename T, int DIR>
 __global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
 {
+    constexpr int ZK = sizeof(T) == 8 ? 16 : 32;
+    constexpr int dir = DIR;
     Tile t;
     if (!get_tile(a, a.depth, false, t)) return;
     const InstDev& I = a.inst[t.inst];
     const int d = a.depth;
     const LevelDev& Lv = I.lev[d];
-    const int n = Lv.n, dir = a.nu;
-    const int line = 2 * (t.blk * GRID_THREADS + (int)threadIdx.x) + a.dst;
+    const int n = Lv.n;
+    // one wave per workgroup works (64 lines): the lines of a colour spread over
+    // as many compute units as there are waves, instead of sharing four per CU;
+    // the launch has ceil(n / 64) ceil(n / 32) >= ceil(n / 128) workgroups
+    if (threadIdx.x >= 64) return;
+    const int line = 2 * (t.blk * 64 + (int)threadIdx.x) + a.dst;
     if (line >= n) return;
-    T* V = buf<T>(Lv, a.src);
-    const int ldv = a.src ? Lv.ldb : Lv.lda;
-    const T* F = (const T*)Lv.F;
+    const gp<T> V = glob<T>(buf<T>(Lv, a.src));
+    const int ldv = a.src ? Lv.ldb : Lv.lda, ldf = Lv.ldf;   // element offsets fit 32 bits (n <= 2^14)
+    const gp<const T> F = glob<T>((const void*)Lv.F);
     const T fs = (T)Lv.fscale;
     Sten<T> s;
     s.load(P<T>::s(I, d));
-    const T* tab = ZT<T>::t(I, d) + (size_t)dir * 2 * n;
-    const T* piv = tab;
-    const T* mul = tab + n;
+    const gp<const T> rpv = glob<T>((const void*)(ZT<T>::t(I, d) + (size_t)dir * 2 * n));
+    const gp<const T> mul = rpv + n;
     const T lo = dir == 0 ? s.c[3] : s.c[1];
-    auto at = [&](int j, int i) -> T {
-        return ((unsigned)j < (unsigned)n && (unsigned)i < (unsigned)n) ? V[(size_t)j * ldv + i] : T(0);
-    };
+    // off-line coefficients at q - 1, q, q + 1 of the previous line (m) and the next line (p), in summation order
+    const T cm0 = s.c[0], cm1 = dir == 0 ? s.c[1] : s.c[3], cm2 = dir == 0 ? s.c[2] : s.c[6];
+    const T cp0 = dir == 0 ? s.c[6] : s.c[2], cp1 = dir == 0 ? s.c[7] : s.c[5], cp2 = s.c[8];
+    const bool hm = line > 0, hp = line + 1 < n;
+    const int Lm = hm ? line - 1 : line, Lp = hp ? line + 1 : line;   // clamped; values masked when absent
+    auto vi = [&](int L, int q) -> int { return dir == 0 ? L * ldv + q : q * ldv + L; };
+    auto fi = [&](int q) -> int { return dir == 0 ? line * ldf + q : q * ldf + line; };
+
+    T m0 = T(0), p0 = T(0);                              // previous / next line at q - 1
+    T m1 = hm ? V[vi(Lm, 0)] : T(0), p1 = hp ? V[vi(Lp, 0)] : T(0);   // at q
     T prev = T(0);
-    for (int q = 0; q < n; ++q) {
-        const int j = dir == 0 ? line : q, i = dir == 0 ? q : line;
-        T acc = T(0);
-        if (dir == 0) {
-            acc += s.c[0] * at(j - 1, i - 1);
-            acc += s.c[1] * at(j - 1, i);
-            acc += s.c[2] * at(j - 1, i + 1);
-            acc += s.c[6] * at(j + 1, i - 1);
-            acc += s.c[7] * at(j + 1, i);
-            acc += s.c[8] * at(j + 1, i + 1);
-        } else {
-            acc += s.c[0] * at(j - 1, i - 1);
-            acc += s.c[3] * at(j, i - 1);
-            acc += s.c[6] * at(j + 1, i - 1);
-            acc += s.c[2] * at(j - 1, i + 1);
-            acc += s.c[5] * at(j, i + 1);
-            acc += s.c[8] * at(j + 1, i + 1);
+    for (int q0 = 0; q0 < n; q0 += ZK) {
+        T mn[ZK], pn[ZK], fv[ZK], rv[ZK];
+#pragma unroll
+        for (int k = 0; k < ZK; ++k) {
+            const int qa = q0 + k + 1;                   // position entering the window
+            const int qc = min(qa, n - 1), qf = min(q0 + k, n - 1);
+            const T xm = V[vi(Lm, qc)], xp = V[vi(Lp, qc)], xf = F[fi(qf)];
+            mn[k] = (hm && qa < n) ? xm : T(0);
+            pn[k] = (hp && qa < n) ? xp : T(0);
+            fv[k] = xf;
+            rv[k] = rpv[qf];
         }
-        const T dq = fs * F[(size_t)j * Lv.ldf + i] - acc;
-        const T y = (q == 0) ? dq / piv[0] : (dq - lo * prev) / piv[q];
-        V[(size_t)j * ldv + i] = y;
-        prev = y;
+        T dq[ZK];
+#pragma unroll
+        for (int k = 0; k < ZK; ++k) {
+            T acc = T(0);
+            acc += cm0 * m0;
+            acc += cm1 * m1;
+            acc += cm2 * mn[k];
+            acc += cp0 * p0;
+            acc += cp1 * p1;
+            acc += cp2 * pn[k];
+            dq[k] = fs * fv[k] - acc;
+            m0 = m1;
+            m1 = mn[k];
+            p0 = p1;
+            p1 = pn[k];
+        }
+#pragma unroll
+        for (int k = 0; k < ZK; ++k) {
+            const int q = q0 + k;
+            if (q < n) {
+                const T y = (q == 0) ? dq[k] * rv[k] : (dq[k] - lo * prev) * rv[k];
+                V[vi(line, q)] = y;
+                prev = y;
+            }
+        }
     }
     T next = prev;   // x_{n-1} = y_{n-1}
-    for (int q = n - 2; q >= 0; --q) {
-        const int j = dir == 0 ? line : q, i = dir == 0 ? q : line;
-        const T x = V[(size_t)j * ldv + i] - mul[q] * next;
-        V[(size_t)j * ldv + i] = x;
-        next = x;
+    for (int q1 = n - 2; q1 >= 0; q1 -= ZK) {
+        T yv[ZK], mv[ZK];
+#pragma unroll
+        for (int k = 0; k < ZK; ++k) {
+            const int qc = max(q1 - k, 0);
+            yv[k] = V[vi(line, qc)];
+            mv[k] = mul[qc];
+        }
+#pragma unroll
+        for (int k = 0; k < ZK; ++k) {
+            const int q = q1 - k;
+            if (q >= 0) {
+                const T x = yv[k] - mv[k] * next;
+                V[vi(line, q)] = x;
+                next = x;
+            }
+        }
     }
 }
 
@@ -2466,9 +2513,14 @@ hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nb, h
     case GK_PRE: e = f32 ? launch_pre<float>(a, nb, s) : launch_pre<double>(a, nb, s); break;
     case GK_POST: e = f32 ? launch_post<float>(a, nb, s) : launch_post<double>(a, nb, s); break;
     case GK_POSTPRE: e = f32 ? launch_postpre<float>(a, nb, s) : launch_postpre<double>(a, nb, s); break;
-    case GK_ZEBRA:
-        if (f32) k_zebra<float><<<nb, GRID_THREADS, 0, s>>>(a);
-        else k_zebra<double><<<nb, GRID_THREADS, 0, s>>>(a);
+    case GK_ZEBRA:   // direction a.nu: 0 x-lines, 1 y-lines
+        if (f32) {
+            if (a.nu) k_zebra<float, 1><<<nb, GRID_THREADS, 0, s>>>(a);
+            else k_zebra<float, 0><<<nb, GRID_THREADS, 0, s>>>(a);
+        } else {
+            if (a.nu) k_zebra<double, 1><<<nb, GRID_THREADS, 0, s>>>(a);
+            else k_zebra<double, 0><<<nb, GRID_THREADS, 0, s>>>(a);
+        }
         e = hipGetLastError();
         break;
     case GK_SWEEP: case GK_RESID: case GK_RESTRICT: case GK_ZERO: case GK_PROLONG: case GK_ADD: case GK_COPY:

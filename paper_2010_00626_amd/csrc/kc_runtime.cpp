@@ -171,7 +171,7 @@ struct InstLayout {
     size_t A[MAXL] = {}, B[MAXL] = {}, F[MAXL] = {};   // cycle arrays by level (A, F of level 0 unused in F64)
     size_t chol64 = 0, chol32 = 0, ops = 0;
     size_t r = 0, z = 0, p = 0, q = 0;
-    size_t zt64 = 0, zt32 = 0;   // zebra line-solve tables, per level [pivots x | multipliers x | pivots y | multipliers y]
+    size_t zt64 = 0, zt32 = 0;   // zebra line-solve tables, per level [1/pivots x | multipliers x | 1/pivots y | multipliers y]
     size_t zoff[MAXL] = {};      // element offset of level d's tables
 };
 
@@ -689,10 +689,10 @@ kc_status plan_exec(kc_hier* h)
 // Zebra line relaxation (Section 4, third and fourth solvers): along a line
 // the matrix is tridiagonal with constant entries lo (previous point), the
 // diagonal and up (next point), in h^2-scaled units; elimination uses the
-// pivots p (p_0 = diag, p_q = diag - lo u_{q-1}) and upper multipliers
-// u_q = up / p_q.  Appends [p, u] for x-lines (west / centre / east entries)
-// and then for y-lines (south / centre / north) of one level, computed in T
-// from the stencil rounded to T.
+// pivots p_q (p_0 = diag, p_q = diag - lo u_{q-1}) through their reciprocals
+// r_q = 1 / p_q, and the upper multipliers u_q = up / p_q.  Appends [r, u] for
+// x-lines (west / centre / east entries) and then for y-lines (south /
+// centre / north) of one level, computed in T from the stencil rounded to T.
 template <typename T>
 void line_tables(int n, const double s64[9], std::vector<T>& out)
 {
@@ -700,14 +700,16 @@ void line_tables(int n, const double s64[9], std::vector<T>& out)
     for (int q = 0; q < 9; ++q) s[q] = (T)s64[q];
     for (int dir = 0; dir < 2; ++dir) {
         const T lo = dir == 0 ? s[3] : s[1], dg = s[4], up = dir == 0 ? s[5] : s[7];
-        std::vector<T> p((size_t)n), u((size_t)n);
-        p[0] = dg;
-        u[0] = up / p[0];
+        std::vector<T> r((size_t)n), u((size_t)n);
+        T piv = dg;
+        u[0] = up / piv;
+        r[0] = T(1) / piv;
         for (int q = 1; q < n; ++q) {
-            p[q] = dg - lo * u[q - 1];
-            u[q] = up / p[q];
+            piv = dg - lo * u[q - 1];
+            u[q] = up / piv;
+            r[q] = T(1) / piv;
         }
-        out.insert(out.end(), p.begin(), p.end());
+        out.insert(out.end(), r.begin(), r.end());
         out.insert(out.end(), u.begin(), u.end());
     }
 }
@@ -1002,6 +1004,9 @@ kc_status prepare_call(kc_hier* h, const kc_cycle_params* c)
     if (s != KC_OK) return s;
     if (c->smoother == 1 && h->ex.mode != 1)
         return fail(KC_ERR_ARG, "the zebra smoother runs in the paper-structured execution mode (exec.mode = 1)");
+    if (c->smoother == 1)
+        for (int i = 0; i < h->count; ++i)
+            if (h->hi[i].il.n[0] > 16383) return fail(KC_ERR_ARG, "the zebra smoother takes n <= 16383");
     if (c->omega != h->omega_set) {
         set_omega(h, c->omega);
         h->omega_set = c->omega;
@@ -1065,7 +1070,7 @@ std::string launch_name(const kc_hier* h, const Launch& L)
         if (L.sa.flags & 32) return k + "<" + T + ", " + nu + ", 8, 8>";
         return k + "<" + T + ", " + nu + ", 64, 32>";
     }
-    if (L.gk == GK_ZEBRA) return std::string("k_zebra<") + T + ">";
+    if (L.gk == GK_ZEBRA) return std::string("k_zebra<") + T + ", " + std::to_string(L.sa.nu) + ">";
     if (L.gk <= GK_NORM || L.gk == GK_ZERO_SELF) return std::string("k_unfused<") + T + ", " + std::to_string(L.gk) + ">";
     return std::string("k_driver<") + (L.f32 ? "true" : "false") + ", " + std::to_string(L.gk) + ">";
     (void)h;

@@ -5,6 +5,10 @@ until the L2 norm of the error has dropped by 1e8; FP64 throughout.
 * Tables 3 and 4: 12 levels (4095^2), 45 degrees, eps = 1e-4, damped Jacobi
   (omega 0.8), nu = 2 + 2, kappa in {1, 2, 3, 4, W}.
 * The solve-time figure: eps in {1e-5, ..., 1} at 9 and 13 levels, stand-alone.
+* Tables 5 and 6 (alternating zebra line relaxation, Galerkin coarsening,
+  one relaxation per direction before and after the coarse correction):
+  eps = 1e-5 and angles 10, 30, 45, 60, 80 degrees, stand-alone and MGCG, at a
+  chosen number of levels (the paper uses 14).
 
 Stand-alone: with f = 0 the exact solution is 0, so the error after k cycles
 is v_k itself.  Cycles run in chunks (one graph launch of `chunk` cycles, timed
@@ -21,7 +25,7 @@ Times: stand-alone total = cycles x (median device time per cycle of the
 chunks); MGCG total = wall time of one run of exactly k iterations (setup and
 host polling included, as the paper's totals include theirs).
 
-Usage: python -m paper_2010_00626_amd.protocol [--tables] [--sweep 9,13] [--maxc 40000]
+Usage: python -m paper_2010_00626_amd.protocol [--tables] [--sweep 9,13] [--zebra-levels 12] [--maxc 40000]
 Prints one JSON object per result line and a summary object at the end.
 """
 from __future__ import annotations
@@ -45,7 +49,8 @@ def _key(k: int) -> str:
     return "W" if k == kcycle.KAPPA_W else str(k)
 
 
-def standalone(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, chunk: int = 32, maxc: int = 40000) -> dict:
+def standalone(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, chunk: int = 32, maxc: int = 40000,
+               smoother: str = "jacobi") -> dict:
     import torch
     f = torch.zeros_like(v0)
     v = v0.clone()
@@ -53,12 +58,13 @@ def standalone(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, chunk: int = 
     done, per_cycle = 0, []
     while done < maxc:
         start = v.clone()
-        ms = H.time_cycles(v, f, kappa=kappa, nu1=nu, nu2=nu, omega=omega, reps=chunk - 1)   # chunk cycles in all
+        ms = H.time_cycles(v, f, kappa=kappa, nu1=nu, nu2=nu, omega=omega, reps=chunk - 1,
+                           smoother=smoother)   # chunk cycles in all
         per_cycle.append(ms)
         if float(torch.linalg.vector_norm(v)) / e0 < TARGET:
             v.copy_(start)
             for j in range(chunk):
-                H.cycle(v, f, kappa=kappa, nu1=nu, nu2=nu, omega=omega)
+                H.cycle(v, f, kappa=kappa, nu1=nu, nu2=nu, omega=omega, smoother=smoother)
                 if float(torch.linalg.vector_norm(v)) / e0 < TARGET:
                     cycles = done + j + 1
                     ms_c = statistics.median(per_cycle)
@@ -70,7 +76,7 @@ def standalone(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, chunk: int = 
             "final_error": float(torch.linalg.vector_norm(v)) / e0}
 
 
-def mgcg(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, kmax: int = 4000) -> dict:
+def mgcg(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, kmax: int = 4000, smoother: str = "jacobi") -> dict:
     import torch
     b = torch.empty_like(v0)
     H.apply_A(b, v0)
@@ -81,7 +87,7 @@ def mgcg(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, kmax: int = 4000) -
     def err(k: int) -> float:
         if k not in cache:
             u.zero_()
-            H.pcg(u, b, kappa=kappa, nu1=nu, nu2=nu, omega=omega, tol=0.0, maxit=k)
+            H.pcg(u, b, kappa=kappa, nu1=nu, nu2=nu, omega=omega, tol=0.0, maxit=k, smoother=smoother)
             cache[k] = float(torch.linalg.vector_norm(u - v0)) / e0
         return cache[k]
 
@@ -100,22 +106,26 @@ def mgcg(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, kmax: int = 4000) -
     u.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    it, rr, st = H.pcg(u, b, kappa=kappa, nu1=nu, nu2=nu, omega=omega, tol=0.0, maxit=hi)
+    it, rr, st = H.pcg(u, b, kappa=kappa, nu1=nu, nu2=nu, omega=omega, tol=0.0, maxit=hi, smoother=smoother)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) * 1e3
     return {"iterations": hi, "total_ms": dt, "ms_per_iteration": dt / hi, "final_error": err(hi)}
 
 
-def run(levels: int, theta: float, eps: float, kappas, which: str, seed: int, maxc: int) -> list:
+def run(levels: int, theta: float, eps: float, kappas, which: str, seed: int, maxc: int,
+        smoother: str = "jacobi") -> list:
     import torch
     n = 2 ** levels - 1
     v0 = torch.from_numpy(inputs.uniform_rhs(np.random.default_rng(seed), n)).to("cuda")
-    H = kcycle.Hierarchy([(n, theta, eps)], "f64")
+    # the zebra smoother runs in the paper-structured execution mode
+    H = kcycle.Hierarchy([(n, theta, eps)], "f64", exec=dict(mode="paper") if smoother == "zebra" else None)
     out = []
     for k in kappas:
         t0 = time.perf_counter()
-        r = standalone(H, v0, k, maxc=maxc) if which == "standalone" else mgcg(H, v0, k)
-        r.update({"solver": which, "levels": levels, "n": n, "theta": theta, "eps": eps, "kappa": _key(k),
+        r = (standalone(H, v0, k, maxc=maxc, smoother=smoother) if which == "standalone"
+             else mgcg(H, v0, k, smoother=smoother))
+        r.update({"solver": which, "smoother": smoother, "levels": levels, "n": n, "theta": theta, "eps": eps,
+                  "kappa": _key(k),
                   "unknowns_per_s": (n * n / (r["total_ms"] * 1e-3)) if r.get("total_ms") else None,
                   "wall_s": round(time.perf_counter() - t0, 2)})
         print(json.dumps(r), flush=True)
@@ -131,14 +141,22 @@ def main(argv=None):
     ap.add_argument("--eps", default="1e-5,1e-4,1e-3,1e-2,1e-1,1")
     ap.add_argument("--maxc", type=int, default=40000, help="stand-alone cycle cap")
     ap.add_argument("--seed", type=int, default=8)
+    ap.add_argument("--zebra-levels", type=int, default=0, help="Tables 5 and 6 (zebra) at this many levels")
+    ap.add_argument("--angles", default="10,30,45,60,80", help="degrees, for the zebra tables")
+    ap.add_argument("--zebra-kappas", default="1,2,3,4,W")
     a = ap.parse_args(argv)
-    res = {"tables": [], "sweep": []}
+    res = {"tables": [], "sweep": [], "zebra": []}
     if a.tables:
         for which in ("standalone", "mgcg"):
             res["tables"] += run(12, math.pi / 4, 1e-4, KAPPAS, which, a.seed, a.maxc)
     for lv in [int(x) for x in a.sweep.split(",") if x]:
         for e in [float(x) for x in a.eps.split(",")]:
             res["sweep"] += run(lv, math.pi / 4, e, KAPPAS, "standalone", a.seed, a.maxc)
+    if a.zebra_levels:
+        zk = [kcycle.KAPPA_W if x == "W" else int(x) for x in a.zebra_kappas.split(",")]
+        for deg in [float(x) for x in a.angles.split(",")]:
+            for which in ("standalone", "mgcg"):
+                res["zebra"] += run(a.zebra_levels, math.radians(deg), 1e-5, zk, which, a.seed, a.maxc, "zebra")
     print(json.dumps({"summary": res}))
 
 
