@@ -78,8 +78,9 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the execution-option autotuner")
     ap.add_argument("--exec", default="", help="JSON execution options for the headline configuration "
                     "(instead of the autotuned ones)")
-    ap.add_argument("--extras", default="c4,c3,c5,hbm",
-                    help="extra measurements: c4 (batched uneven), c3 (PCG 4095^2), c5 (adjoint), hbm (8191^2 kernel)")
+    ap.add_argument("--extras", default="c4,c3,c5,hbm,zebra",
+                    help="extra measurements: c4 (batched uneven), c3 (PCG 4095^2), c5 (adjoint), hbm (8191^2 kernel), "
+                         "zebra (the 1023^2 problem with alternating zebra line relaxation)")
     return ap.parse_args()
 
 
@@ -240,6 +241,8 @@ def main():
         extras["c3_pcg"] = c3_pcg(inputs, kcycle, torch)
     if "c5" in ex:
         extras["c5_adjoint"] = c5_adjoint(inputs, torch)
+    if "zebra" in ex:
+        extras["zebra_c2"] = zebra_c2(inputs, kcycle, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -376,6 +379,34 @@ def c3_pcg(inputs, kcycle, torch):
     out["2"]["err_vs_f64"] = float((u32 - u).abs().max() / u.abs().max())
     Hc.close()
     H64.close()
+    return out
+
+
+def zebra_c2(inputs, kcycle, torch):
+    """The 1023^2 workload with alternating zebra line Gauss-Seidel (paper-structured
+    execution, FP64, nu = 2 + 2: one x- and one y-relaxation on each side), per kappa,
+    to the same 1e-8 relative residual."""
+    w = inputs.config2()
+    inst = w.instances[0]
+    n = inst.n
+    f = torch.from_numpy(inst.f).to("cuda")
+    u = torch.zeros_like(f)
+    H = kcycle.Hierarchy([(n, inst.theta, inst.eps, w.n_coarsest)], "f64", exec=dict(mode="paper"))
+    out = {}
+    for k in (1, 2, 3, 4, kcycle.KAPPA_W):
+        u.zero_()
+        H.solve(u, f, kappa=k, nu1=2, nu2=2, tol=w.tol, maxit=2000, smoother="zebra")   # warm-up + capture
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, rr, st = H.solve(u, f, kappa=k, nu1=2, nu2=2, tol=w.tol, maxit=2000, smoother="zebra")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        key = "W" if k == kcycle.KAPPA_W else str(k)
+        out[key] = {"cycles": it[0], "status": st[0], "ms": round(dt * 1e3, 2),
+                    "ms_per_cycle": round(dt * 1e3 / max(it[0], 1), 3), "unknowns_per_s": n * n / dt}
+        print(f"[bench] zebra kappa={key}: {it[0]} cycles, {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    H.close()
     return out
 
 
