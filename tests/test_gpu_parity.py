@@ -668,3 +668,74 @@ def test_zebra_needs_paper_mode():
     with pytest.raises(K().KCycleError):
         H.solve(u, dev(np.ones((63, 63))), kappa=2, smoother="zebra")
     H.close()
+
+
+@pytest.mark.parametrize("n,nc,mode", [(1, 1, "fused"), (1, 1, "paper"), (3, 1, "fused"), (3, 3, "paper"),
+                                       (7, 7, "fused"), (7, 1, "paper"), (15, 3, "fused")])
+def test_degenerate_sizes(n, nc, mode):
+    """Problems with one point, no coarsening or a single coarse level: the
+    solve gives the oracle's iterations and bits (FP64); FP32 refinement converges."""
+    banner(f"degenerate size n={n} nc={nc} mode={mode}")
+    th, ep = 0.7, 1e-2
+    f = np.random.default_rng(n + nc).uniform(-1, 1, (n, n))
+    Ho = O.Hierarchy(n, th, ep, n_coarsest=nc)
+    u_ref, rc, it_ref, hist = Ho.solve(f, kappa=2, tol=1e-10, maxit=200)
+    assert rc == O.OK
+    check_stop_margin(hist, 1e-10)
+    H = K().Hierarchy([(n, th, ep, nc)], "f64", exec=dict(mode=mode))
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    it, rr, st = H.solve(u, dev(f), kappa=2, tol=1e-10, maxit=200)
+    assert st == [0] and it[0] == it_ref and np.array_equal(host(u), u_ref)
+    H.close()
+    H32 = K().Hierarchy([(n, th, ep, nc)], "f32", exec=dict(mode=mode))
+    u.zero_()
+    it, rr, st = H32.solve(u, dev(f), kappa=2, tol=1e-10, maxit=200)
+    assert st == [0]
+    assert np.linalg.norm(f - Ho.apply(host(u))) <= 1e-10 * np.linalg.norm(f)
+    H32.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_zero_right_hand_side(prec):
+    """f = 0: the solvers stop before the first cycle with u = 0."""
+    banner(f"zero right-hand side {prec}")
+    n = 127
+    H = K().Hierarchy([(n, 0.3, 1e-3)], prec)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    f = torch.zeros_like(u)
+    it, rr, st = H.solve(u, f, kappa=2, tol=1e-8, maxit=50)
+    assert st == [0] and it == [0] and rr == [0.0] and not bool(u.any())
+    it, rr, st = H.pcg(u, f, kappa=2, tol=1e-8, maxit=50)
+    assert st == [0] and it == [0] and not bool(u.any())
+    H.close()
+
+
+def test_full_size_c3_pcg_properties():
+    """At the full 4095^2 size of the PCG workload: one FP64 cycle is the
+    oracle's bits, and the FP32-preconditioned CG reaches the tolerance on
+    the true residual (computed on the device in FP64) with an iteration
+    count close to the FP64-preconditioned one."""
+    banner("full-size 4095^2 PCG properties")
+    w = inputs.config3()
+    inst = w.instances[0]
+    n = inst.n
+    f = dev(inst.f)
+    v0 = np.random.default_rng(12).uniform(-1, 1, (n, n))
+    H64 = K().Hierarchy([(n, inst.theta, inst.eps)], "f64")
+    v = dev(v0)
+    H64.cycle(v, f, kappa=2, nu1=1, nu2=1)
+    ref = O.Hierarchy(n, inst.theta, inst.eps).cycle(v0, inst.f, kappa=2, nu1=1, nu2=1)[0]
+    assert np.array_equal(host(v), ref)
+    u64 = torch.zeros_like(f)
+    it64, _, st64 = H64.pcg(u64, f, kappa=2, nu1=1, nu2=1, tol=w.tol, maxit=1000)
+    H32 = K().Hierarchy([(n, inst.theta, inst.eps)], "f32")
+    u = torch.zeros_like(f)
+    it, rr, st = H32.pcg(u, f, kappa=2, nu1=1, nu2=1, tol=w.tol, maxit=1000)
+    assert st == [0] and st64 == [0] and abs(it[0] - it64[0]) <= 2
+    r = torch.empty_like(f)
+    H64.apply_A(r, u)
+    rel = float(torch.linalg.vector_norm(f - r) / torch.linalg.vector_norm(f))
+    assert rel < 2 * w.tol
+    assert float((u - u64).abs().max() / u64.abs().max()) < 1e-9
+    H32.close()
+    H64.close()
