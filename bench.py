@@ -383,30 +383,35 @@ def c3_pcg(inputs, kcycle, torch):
 
 
 def zebra_c2(inputs, kcycle, torch):
-    """The 1023^2 workload with alternating zebra line Gauss-Seidel (paper-structured
-    execution, FP64, nu = 2 + 2: one x- and one y-relaxation on each side), per kappa,
-    to the same 1e-8 relative residual."""
+    """The 1023^2 workload with alternating zebra line Gauss-Seidel (FP64, nu = 2 + 2:
+    one x- and one y-relaxation on each side), per kappa, to the same 1e-8 relative
+    residual: in the fused mode (levels above the cutover one kernel per operation,
+    every call at the cutover in one persistent launch) and in the paper-structured
+    mode (one kernel per operation on every level)."""
     w = inputs.config2()
     inst = w.instances[0]
     n = inst.n
     f = torch.from_numpy(inst.f).to("cuda")
     u = torch.zeros_like(f)
-    H = kcycle.Hierarchy([(n, inst.theta, inst.eps, w.n_coarsest)], "f64", exec=dict(mode="paper"))
     out = {}
-    for k in (1, 2, 3, 4, kcycle.KAPPA_W):
-        u.zero_()
-        H.solve(u, f, kappa=k, nu1=2, nu2=2, tol=w.tol, maxit=2000, smoother="zebra")   # warm-up + capture
-        u.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        it, rr, st = H.solve(u, f, kappa=k, nu1=2, nu2=2, tol=w.tol, maxit=2000, smoother="zebra")
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        key = "W" if k == kcycle.KAPPA_W else str(k)
-        out[key] = {"cycles": it[0], "status": st[0], "ms": round(dt * 1e3, 2),
-                    "ms_per_cycle": round(dt * 1e3 / max(it[0], 1), 3), "unknowns_per_s": n * n / dt}
-        print(f"[bench] zebra kappa={key}: {it[0]} cycles, {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
-    H.close()
+    for mode in ("fused", "paper"):
+        H = kcycle.Hierarchy([(n, inst.theta, inst.eps, w.n_coarsest)], "f64", exec=dict(mode=mode))
+        res = {}
+        for k in (1, 2, 3, 4, kcycle.KAPPA_W):
+            u.zero_()
+            H.solve(u, f, kappa=k, nu1=2, nu2=2, tol=w.tol, maxit=2000, smoother="zebra")   # warm-up + capture
+            u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it, rr, st = H.solve(u, f, kappa=k, nu1=2, nu2=2, tol=w.tol, maxit=2000, smoother="zebra")
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            key = "W" if k == kcycle.KAPPA_W else str(k)
+            res[key] = {"cycles": it[0], "status": st[0], "ms": round(dt * 1e3, 2),
+                        "ms_per_cycle": round(dt * 1e3 / max(it[0], 1), 3), "unknowns_per_s": n * n / dt}
+            print(f"[bench] zebra {mode} kappa={key}: {it[0]} cycles, {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
+        H.close()
+        out[mode] = res
     return out
 
 

@@ -84,9 +84,11 @@ typedef struct {
     int32_t nu2;
     int32_t smoother;   /* 0 = damped Jacobi with omega (default); 1 = alternating zebra line Gauss-Seidel (Section 4,
                            third and fourth solvers): relaxation r of a smoothing step solves every x-line (r even)
-                           or y-line (r odd) exactly, lines of even index first, then odd; runs in the
-                           paper-structured execution mode only (exec.mode = 1) and for n <= 16383, else
-                           KC_ERR_ARG */
+                           or y-line (r odd) exactly, lines of even index first, then odd.  In the fused mode
+                           the levels above the coarse cutover run one kernel per operation and every call at
+                           the cutover runs in the persistent kernel (line solves in LDS); in the
+                           paper-structured mode every level runs one kernel per operation.  Needs n <= 16383
+                           (else KC_ERR_ARG) */
     double omega;
 } kc_cycle_params;
 
@@ -115,6 +117,9 @@ typedef struct {
     int32_t tiny_tile_n;    /* fused grid kernels on levels whose largest n <= this use 8 x 8 tiles (one point per
                                thread and phase; takes precedence over small_tile_n; 0 = never; 0..4095; default 255);
                                results do not depend on it */
+    int32_t zebra_wave_n;   /* zebra line relaxation on levels with n >= this solves each line with one wave (64 points
+                               per step, many lines in flight); smaller levels use one thread per line (0 = never;
+                               0..16383; default 63); results do not depend on it */
 } kc_exec;
 
 typedef struct kc_hier kc_hier;

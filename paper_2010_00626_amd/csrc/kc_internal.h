@@ -8,6 +8,8 @@
 namespace kc {
 
 constexpr int MAXL = 16;          // levels per instance
+constexpr int NTABLES = 1 + 3 * MAXL;   // block tables: whole fine level, fused grid per depth, per level, zebra per level
+constexpr int ZLDS_TABLE = 480;   // persistent-kernel LDS elements for the zebra tables of levels 1 .. 63 (4 n each)
 constexpr int TX = 64;            // grid-kernel tile width  (one wave64 row)
 constexpr int TY = 32;            // grid-kernel tile height
 constexpr int TS = 16;            // small-level tile side of the fused kernels
@@ -46,6 +48,8 @@ struct InstDev {
     int32_t lds_off[MAXL]; // persistent kernel: element offset of level d's three (n+2)^2 arrays
     int32_t ops_beg[MAXL + 1]; // persistent kernel op list of a call with counter k = 1..MAXL+1
     int32_t ops_len[MAXL + 1];
+    int32_t zops_beg[MAXL + 1];  // the same for zebra relaxation (no register calls)
+    int32_t zops_len[MAXL + 1];
     const uint32_t* ops;       // op list storage
     // FP64 vectors of the drivers (refinement / PCG); fine level, ld = ldv
     double* u;           // user solution
@@ -153,6 +157,7 @@ struct SubArgs {
     int32_t zg;               // single call: estimate is zero on entry
     int32_t fin;              // single call: FIN_STOP computes the stop test first
     int32_t wave_n;           // levels with n <= wave_n are run by one wave
+    int32_t smoother;         // 0 damped Jacobi, 1 alternating zebra line relaxation
     double* hist;
 };
 

@@ -21,6 +21,8 @@
 // (stop test, CG scalars) to the instance's state.
 #include <math.h>
 
+#include <type_traits>
+
 #include "../../include/kcycle.h"
 #include "kc_internal.h"
 
@@ -162,6 +164,14 @@ __device__ __forceinline__ T prolong_at(int j, int i, Get V)
 // ---------------------------------------------------------------------------
 // block -> (instance, tile) and deterministic reductions
 // ---------------------------------------------------------------------------
+// orders one wave's LDS accesses around a point (no other wave takes part)
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 struct Tile {
     int inst, blk, nblk, x0, y0;
 };
@@ -462,62 +472,58 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// zebra line relaxation (paper-structured mode): one thread per line of the
-// launch's colour (lines 2 m + colour, 64 per workgroup), solving that line's tridiagonal system
-// exactly with its neighbouring lines' current values, in place.  Forward
-// pass: d_q = F_q - (six off-line products: line j-1 then j+1, west to east,
-// for x-lines; column i-1 then i+1, south to north, for y-lines);
+// zebra line relaxation (paper-structured mode): every line of the launch's
+// colour (lines 2 m + colour) solves its tridiagonal system exactly with its
+// neighbouring lines' current values, in place.  Forward pass:
+// d_q = F_q - (six off-line products: line j-1 then j+1, west to east, for
+// x-lines; column i-1 then i+1, south to north, for y-lines);
 // y_q = (d_q - lo y_{q-1}) r_q, written over the line; backward pass
 // x_q = y_q - u_q x_{q+1}.  r, u: the level's reciprocal pivots and upper
-// multipliers.
+// multipliers.  Two mappings with the same arithmetic, chosen per instance:
 //
-// Both passes go along the line in chunks of ZK points: every load of a chunk
-// (the two neighbouring lines one point ahead, F and r; or the line's own y
-// values and u) is issued before the chunk's stores, so a chunk costs one
-// memory round trip; the neighbouring lines' values at q - 1, q, q + 1 slide
-// through registers, and the chunk's d_q are formed before the recurrence,
-// whose serial step is one multiply-subtract-multiply.
+// * lanes (levels below the launch's threshold): one thread per line, 64
+//   lines per workgroup (one wave, so a colour's lines spread over as many
+//   CUs as waves).  Both passes go along the line in chunks of ZK points:
+//   every load of a chunk (the two neighbouring lines one point ahead, F and
+//   r; or the line's own y values and u) is issued before the chunk's stores,
+//   the neighbouring lines' values at q - 1, q, q + 1 slide through
+//   registers, and the chunk's d_q are formed before the recurrence.
+// * waves (levels at or above the threshold): one wave per line, four lines
+//   per workgroup.  Lane l holds point q0 + l of a chunk of 64: the lanes
+//   form the chunk's d_q (and load r) in parallel and put them in the wave's
+//   LDS slots; the recurrence runs over the chunk wave-uniformly (unrolled,
+//   one broadcast LDS read per step, so the vector ALU issues only the
+//   recurrence's own operations), lane 0 writes the results out and each
+//   lane stores its own point; the next chunk's loads are issued before the
+//   recurrence, so they are in flight while it runs.  A level's
+//   n / 2 lines give n / 2 waves, against n / 128 for the lane mapping,
+//   which is what large levels need to keep memory busy.  The backward pass
+//   reads each point's y back in the lane that wrote it.
 // ---------------------------------------------------------------------------
 template <typename T> struct ZT;
 template <> struct ZT<double> { static __device__ const double* t(const InstDev& I, int d) { return I.zt64[d]; } };
 template <> struct ZT<float> { static __device__ const float* t(const InstDev& I, int d) { return I.zt32[d]; } };
 
+// per-line constants of one launch (direction DIR: 0 x-lines, 1 y-lines)
 template <typename T, int DIR>
-__global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
-{
-    constexpr int ZK = sizeof(T) == 8 ? 16 : 32;
-    constexpr int dir = DIR;
-    Tile t;
-    if (!get_tile(a, a.depth, false, t)) return;
-    const InstDev& I = a.inst[t.inst];
-    const int d = a.depth;
-    const LevelDev& Lv = I.lev[d];
-    const int n = Lv.n;
-    // one wave per workgroup works (64 lines): the lines of a colour spread over
-    // as many compute units as there are waves, instead of sharing four per CU;
-    // the launch has ceil(n / 64) ceil(n / 32) >= ceil(n / 128) workgroups
-    if (threadIdx.x >= 64) return;
-    const int line = 2 * (t.blk * 64 + (int)threadIdx.x) + a.dst;
-    if (line >= n) return;
-    const gp<T> V = glob<T>(buf<T>(Lv, a.src));
-    const int ldv = a.src ? Lv.ldb : Lv.lda, ldf = Lv.ldf;   // element offsets fit 32 bits (n <= 2^14)
-    const gp<const T> F = glob<T>((const void*)Lv.F);
-    const T fs = (T)Lv.fscale;
-    Sten<T> s;
-    s.load(P<T>::s(I, d));
-    const gp<const T> rpv = glob<T>((const void*)(ZT<T>::t(I, d) + (size_t)dir * 2 * n));
-    const gp<const T> mul = rpv + n;
-    const T lo = dir == 0 ? s.c[3] : s.c[1];
-    // off-line coefficients at q - 1, q, q + 1 of the previous line (m) and the next line (p), in summation order
-    const T cm0 = s.c[0], cm1 = dir == 0 ? s.c[1] : s.c[3], cm2 = dir == 0 ? s.c[2] : s.c[6];
-    const T cp0 = dir == 0 ? s.c[6] : s.c[2], cp1 = dir == 0 ? s.c[7] : s.c[5], cp2 = s.c[8];
-    const bool hm = line > 0, hp = line + 1 < n;
-    const int Lm = hm ? line - 1 : line, Lp = hp ? line + 1 : line;   // clamped; values masked when absent
-    auto vi = [&](int L, int q) -> int { return dir == 0 ? L * ldv + q : q * ldv + L; };
-    auto fi = [&](int q) -> int { return dir == 0 ? line * ldf + q : q * ldf + line; };
+struct ZLine {
+    gp<T> V;
+    gp<const T> F, rpv, mul;
+    int n, ldv, ldf, line;
+    T fs, lo, cm0, cm1, cm2, cp0, cp1, cp2;
+    bool hm, hp;
+    int Lm, Lp;
+    __device__ __forceinline__ int vi(int L, int q) const { return DIR == 0 ? L * ldv + q : q * ldv + L; }
+    __device__ __forceinline__ int fi(int q) const { return DIR == 0 ? line * ldf + q : q * ldf + line; }
+};
 
-    T m0 = T(0), p0 = T(0);                              // previous / next line at q - 1
-    T m1 = hm ? V[vi(Lm, 0)] : T(0), p1 = hp ? V[vi(Lp, 0)] : T(0);   // at q
+template <typename T, int DIR>
+__device__ __forceinline__ void zebra_lanes(const ZLine<T, DIR>& z)
+{
+    constexpr int ZK = sizeof(T) == 8 ? 8 : 16;
+    const int n = z.n;
+    T m0 = T(0), p0 = T(0);                                          // previous / next line at q - 1
+    T m1 = z.hm ? z.V[z.vi(z.Lm, 0)] : T(0), p1 = z.hp ? z.V[z.vi(z.Lp, 0)] : T(0);   // at q
     T prev = T(0);
     for (int q0 = 0; q0 < n; q0 += ZK) {
         T mn[ZK], pn[ZK], fv[ZK], rv[ZK];
@@ -525,23 +531,23 @@ __global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
         for (int k = 0; k < ZK; ++k) {
             const int qa = q0 + k + 1;                   // position entering the window
             const int qc = min(qa, n - 1), qf = min(q0 + k, n - 1);
-            const T xm = V[vi(Lm, qc)], xp = V[vi(Lp, qc)], xf = F[fi(qf)];
-            mn[k] = (hm && qa < n) ? xm : T(0);
-            pn[k] = (hp && qa < n) ? xp : T(0);
+            const T xm = z.V[z.vi(z.Lm, qc)], xp = z.V[z.vi(z.Lp, qc)], xf = z.F[z.fi(qf)];
+            mn[k] = (z.hm && qa < n) ? xm : T(0);
+            pn[k] = (z.hp && qa < n) ? xp : T(0);
             fv[k] = xf;
-            rv[k] = rpv[qf];
+            rv[k] = z.rpv[qf];
         }
         T dq[ZK];
 #pragma unroll
         for (int k = 0; k < ZK; ++k) {
             T acc = T(0);
-            acc += cm0 * m0;
-            acc += cm1 * m1;
-            acc += cm2 * mn[k];
-            acc += cp0 * p0;
-            acc += cp1 * p1;
-            acc += cp2 * pn[k];
-            dq[k] = fs * fv[k] - acc;
+            acc += z.cm0 * m0;
+            acc += z.cm1 * m1;
+            acc += z.cm2 * mn[k];
+            acc += z.cp0 * p0;
+            acc += z.cp1 * p1;
+            acc += z.cp2 * pn[k];
+            dq[k] = z.fs * fv[k] - acc;
             m0 = m1;
             m1 = mn[k];
             p0 = p1;
@@ -551,8 +557,8 @@ __global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
         for (int k = 0; k < ZK; ++k) {
             const int q = q0 + k;
             if (q < n) {
-                const T y = (q == 0) ? dq[k] * rv[k] : (dq[k] - lo * prev) * rv[k];
-                V[vi(line, q)] = y;
+                const T y = (q == 0) ? dq[k] * rv[k] : (dq[k] - z.lo * prev) * rv[k];
+                z.V[z.vi(z.line, q)] = y;
                 prev = y;
             }
         }
@@ -563,18 +569,255 @@ __global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
 #pragma unroll
         for (int k = 0; k < ZK; ++k) {
             const int qc = max(q1 - k, 0);
-            yv[k] = V[vi(line, qc)];
-            mv[k] = mul[qc];
+            yv[k] = z.V[z.vi(z.line, qc)];
+            mv[k] = z.mul[qc];
         }
 #pragma unroll
         for (int k = 0; k < ZK; ++k) {
             const int q = q1 - k;
             if (q >= 0) {
                 const T x = yv[k] - mv[k] * next;
-                V[vi(line, q)] = x;
+                z.V[z.vi(z.line, q)] = x;
                 next = x;
             }
         }
+    }
+}
+
+// the loads of one lane for a forward chunk: point q = q0 + lane (clamped
+// addresses).  The values are masked where the point or a neighbour is absent
+// only when d_q is formed, so that prefetched loads are not waited for early.
+template <typename T>
+struct ZFwd {
+    T m0, m1, m2, p0, p1, p2, f, r;
+    bool km0, km1, km2, kp0, kp1, kp2;   // which neighbour values are present
+    template <int DIR>
+    __device__ __forceinline__ void load(const ZLine<T, DIR>& z, int q)
+    {
+        const int qc = min(q, z.n - 1), qm = max(qc - 1, 0), qp = min(q + 1, z.n - 1);
+        m0 = z.V[z.vi(z.Lm, qm)];
+        m1 = z.V[z.vi(z.Lm, qc)];
+        m2 = z.V[z.vi(z.Lm, qp)];
+        p0 = z.V[z.vi(z.Lp, qm)];
+        p1 = z.V[z.vi(z.Lp, qc)];
+        p2 = z.V[z.vi(z.Lp, qp)];
+        f = z.F[z.fi(qc)];
+        r = z.rpv[qc];
+        km0 = z.hm && q >= 1;
+        km1 = z.hm;
+        km2 = z.hm && q + 1 < z.n;
+        kp0 = z.hp && q >= 1;
+        kp1 = z.hp;
+        kp2 = z.hp && q + 1 < z.n;
+    }
+    template <int DIR>
+    __device__ __forceinline__ T dq(const ZLine<T, DIR>& z) const
+    {
+        T acc = T(0);
+        acc += z.cm0 * (km0 ? m0 : T(0));
+        acc += z.cm1 * (km1 ? m1 : T(0));
+        acc += z.cm2 * (km2 ? m2 : T(0));
+        acc += z.cp0 * (kp0 ? p0 : T(0));
+        acc += z.cp1 * (kp1 ? p1 : T(0));
+        acc += z.cp2 * (kp2 ? p2 : T(0));
+        return z.fs * f - acc;
+    }
+};
+
+// a wave's LDS slots for one chunk: the lanes' (d_q, r_q) or (y_q, u_q) pairs,
+// read back one per step at a wave-uniform address (a broadcast read, on the
+// LDS pipe rather than the vector ALU), and the chunk's results, written by lane 0
+template <typename T>
+struct ZSlots {
+    T pair[64][2];
+    T res[64];
+};
+
+template <typename T, int DIR>
+__device__ __forceinline__ void zebra_wave(const ZLine<T, DIR>& z, ZSlots<T>& sl)
+{
+    constexpr int SB = 8;   // steps per block: pairs read a block ahead, results written out by lane 0 per block
+    const int n = z.n, lane = threadIdx.x & 63;
+    ZFwd<T> cur;
+    cur.load(z, lane);
+    T prev = T(0);
+    for (int q0 = 0; q0 < n; q0 += 64) {
+        sl.pair[lane][0] = cur.dq(z);
+        sl.pair[lane][1] = cur.r;
+        wave_sync();
+        if (q0 + 64 < n) cur.load(z, q0 + 64 + lane);   // in flight during the recurrence
+        const int cnt = min(64, n - q0);
+        const bool first = q0 == 0;
+        // a full chunk keeps every step; in the last one, steps past the line's end
+        // (k >= cnt) compute values that are neither kept nor stored
+        auto steps = [&](auto partial) {
+            T dk[SB], rk[SB];   // the block's pairs, read one block ahead of the recurrence
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                dk[j] = sl.pair[j][0];
+                rk[j] = sl.pair[j][1];
+            }
+#pragma unroll
+            for (int kb = 0; kb < 64; kb += SB) {
+                T dn[SB], rn[SB];
+                if (kb + SB < 64) {
+#pragma unroll
+                    for (int j = 0; j < SB; ++j) {
+                        dn[j] = sl.pair[kb + SB + j][0];
+                        rn[j] = sl.pair[kb + SB + j][1];
+                    }
+                }
+                T yb[SB];
+#pragma unroll
+                for (int j = 0; j < SB; ++j) {
+                    const int k = kb + j;
+                    const T t = (k == 0 && first) ? dk[j] : dk[j] - z.lo * prev;   // y_0 = d_0 r_0
+                    const T y = t * rk[j];
+                    yb[j] = y;
+                    if constexpr (decltype(partial)::value) prev = (k < cnt) ? y : prev;
+                    else prev = y;
+                }
+                if (lane == 0) {
+#pragma unroll
+                    for (int j = 0; j < SB; ++j) sl.res[kb + j] = yb[j];
+                }
+                if (kb + SB < 64) {
+#pragma unroll
+                    for (int j = 0; j < SB; ++j) {
+                        dk[j] = dn[j];
+                        rk[j] = rn[j];
+                    }
+                }
+            }
+        };
+        if (cnt == 64) steps(std::false_type{});
+        else steps(std::true_type{});
+        wave_sync();
+        if (lane < cnt) z.V[z.vi(z.line, q0 + lane)] = sl.res[lane];
+        wave_sync();   // the slots are rewritten by the next chunk
+    }
+    // backward, chunks from the last one down; lane l owns the point it wrote above
+    const int c_last = (n - 1) >> 6;
+    T next = prev;   // x_{n-1} = y_{n-1}
+    T yv, uv;
+    {
+        const int q = min((c_last << 6) + lane, n - 1);
+        yv = z.V[z.vi(z.line, q)];
+        uv = z.mul[q];
+    }
+    for (int c = c_last; c >= 0; --c) {
+        const int q0 = c << 6;
+        sl.pair[lane][0] = yv;
+        sl.pair[lane][1] = uv;
+        wave_sync();
+        if (c > 0) {   // in flight during the recurrence
+            const int q = q0 - 64 + lane;
+            yv = z.V[z.vi(z.line, q)];
+            uv = z.mul[q];
+        }
+        const int top = min(63, n - 2 - q0);   // x_{n-1} = y_{n-1} is already in place
+        auto steps = [&](auto partial) {
+            T yk[SB], uk[SB];   // the block's pairs, read one block ahead of the recurrence
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                yk[j] = sl.pair[64 - SB + j][0];
+                uk[j] = sl.pair[64 - SB + j][1];
+            }
+#pragma unroll
+            for (int kb = 64 - SB; kb >= 0; kb -= SB) {
+                T yn[SB], un[SB];
+                if (kb > 0) {
+#pragma unroll
+                    for (int j = 0; j < SB; ++j) {
+                        yn[j] = sl.pair[kb - SB + j][0];
+                        un[j] = sl.pair[kb - SB + j][1];
+                    }
+                }
+                T xb[SB];
+#pragma unroll
+                for (int j = SB - 1; j >= 0; --j) {
+                    const int k = kb + j;
+                    const T x = yk[j] - uk[j] * next;
+                    xb[j] = x;
+                    if constexpr (decltype(partial)::value) next = (k <= top) ? x : next;
+                    else next = x;
+                }
+                if (lane == 0) {
+#pragma unroll
+                    for (int j = 0; j < SB; ++j) sl.res[kb + j] = xb[j];
+                }
+                if (kb > 0) {
+#pragma unroll
+                    for (int j = 0; j < SB; ++j) {
+                        yk[j] = yn[j];
+                        uk[j] = un[j];
+                    }
+                }
+            }
+        };
+        if (top == 63) steps(std::false_type{});
+        else steps(std::true_type{});
+        wave_sync();
+        if (lane <= top) z.V[z.vi(z.line, q0 + lane)] = sl.res[lane];
+        wave_sync();
+    }
+}
+
+template <typename T, int DIR>
+__global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
+{
+    __shared__ ZSlots<T> slots[GRID_THREADS / 64];
+    const int b = blockIdx.x;
+    const int inst = find_inst(a.tile_off, a.count, b);
+    if (a.st[inst].done) return;
+    const InstDev& I = a.inst[inst];
+    const int d = a.depth;
+    const LevelDev& Lv = I.lev[d];
+    const int n = Lv.n;
+    // the launch's threshold (flags) picks the mapping for this instance; the
+    // block table was sized the same way
+    const bool waves = a.flags > 0 && n >= a.flags;
+    int blk = b - a.tile_off[inst];
+    int line;
+    if (waves) {
+        // consecutive line groups on one XCD (workgroups go round-robin over the
+        // eight XCDs), so y-lines sharing cache lines share an L2
+        const int nb = a.tile_off[inst + 1] - a.tile_off[inst];
+        if ((a.tile_off[inst] & 7) == 0 && (nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+        line = 2 * (blk * (GRID_THREADS / 64) + (int)(threadIdx.x >> 6)) + a.dst;
+    } else {
+        if (threadIdx.x >= 64) return;
+        line = 2 * (blk * 64 + (int)threadIdx.x) + a.dst;
+    }
+    if (line >= n) return;   // whole waves in the wave mapping
+    ZLine<T, DIR> z;
+    z.V = glob<T>(buf<T>(Lv, a.src));
+    z.ldv = a.src ? Lv.ldb : Lv.lda;   // element offsets fit 32 bits (n <= 2^14)
+    z.ldf = Lv.ldf;
+    z.F = glob<T>((const void*)Lv.F);
+    z.fs = (T)Lv.fscale;
+    z.n = n;
+    z.line = line;
+    Sten<T> s;
+    s.load(P<T>::s(I, d));
+    z.rpv = glob<T>((const void*)(ZT<T>::t(I, d) + (size_t)DIR * 2 * n));
+    z.mul = z.rpv + n;
+    z.lo = DIR == 0 ? s.c[3] : s.c[1];
+    // off-line coefficients at q - 1, q, q + 1 of the previous line (m) and the next line (p), in summation order
+    z.cm0 = s.c[0];
+    z.cm1 = DIR == 0 ? s.c[1] : s.c[3];
+    z.cm2 = DIR == 0 ? s.c[2] : s.c[6];
+    z.cp0 = DIR == 0 ? s.c[6] : s.c[2];
+    z.cp1 = DIR == 0 ? s.c[7] : s.c[5];
+    z.cp2 = s.c[8];
+    z.hm = line > 0;
+    z.hp = line + 1 < n;
+    z.Lm = z.hm ? line - 1 : line;   // clamped; values masked when absent
+    z.Lp = z.hp ? line + 1 : line;
+    if (waves) {
+        zebra_wave<T, DIR>(z, slots[threadIdx.x >> 6]);
+    } else {
+        zebra_lanes<T, DIR>(z);
     }
 }
 
@@ -1347,13 +1590,6 @@ __global__ void __launch_bounds__(256) k_post_s(StageArgs a)
 // phases need only wave-level ordering, while the other waves wait at the next
 // workgroup barrier.
 // ---------------------------------------------------------------------------
-__device__ inline void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
-
 // per-launch copy of everything the persistent kernel reads between phases:
 // LDS keeps it out of global memory, whose latency would otherwise be paid
 // once per phase (the phase fences forbid caching it in scalar registers)
@@ -1599,6 +1835,99 @@ __device__ __forceinline__ void ph_sweep_zg1(clds<T> x, lds<T> y, clds<T> F, cld
     ph_sweep<T, N, NB>(x, y, F, sc, om, t, true);
 }
 
+// zebra relaxation of one colour on an N x N level in LDS (zero ring, stride
+// N + 2), in place: thread t solves line 2 t + colour with the lane mapping of
+// the grid kernel (same arithmetic, same order; the ring supplies the zeros
+// that kernel masks in).  tab: the level's reciprocal pivots then upper
+// multipliers for the direction, staged in LDS.  Each chunk of ZK points
+// loads its neighbour values, right-hand sides and pivots before its stores.
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void zebra_lds_line(lds<T> x, clds<T> F, clds<T> sc, clds<T> tab, int color, int t)
+{
+    constexpr int P = N + 2, ZK = 8;
+    const int line = 2 * t + color;
+    if (line >= N) return;
+    auto at = [&](int L, int q) -> int { return DIR == 0 ? (L + 1) * P + (q + 1) : (q + 1) * P + (L + 1); };
+    const T cm0 = sc[0], cm1 = DIR == 0 ? sc[1] : sc[3], cm2 = DIR == 0 ? sc[2] : sc[6];
+    const T cp0 = DIR == 0 ? sc[6] : sc[2], cp1 = DIR == 0 ? sc[7] : sc[5], cp2 = sc[8];
+    const T lo = DIR == 0 ? sc[3] : sc[1];
+    T m0 = T(0), p0 = T(0);
+    T m1 = x[at(line - 1, 0)], p1 = x[at(line + 1, 0)];
+    T prev = T(0);
+#pragma unroll
+    for (int q0 = 0; q0 < N; q0 += ZK) {
+        T mn[ZK], pn[ZK], fv[ZK], rv[ZK];
+#pragma unroll
+        for (int k = 0; k < ZK; ++k) {
+            const int q = q0 + k;
+            if (q < N) {
+                mn[k] = x[at(line - 1, q + 1)];   // q + 1 = N reads the ring
+                pn[k] = x[at(line + 1, q + 1)];
+                fv[k] = F[at(line, q)];
+                rv[k] = tab[q];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < ZK; ++k) {
+            const int q = q0 + k;
+            if (q < N) {
+                T acc = T(0);
+                acc += cm0 * m0;
+                acc += cm1 * m1;
+                acc += cm2 * mn[k];
+                acc += cp0 * p0;
+                acc += cp1 * p1;
+                acc += cp2 * pn[k];
+                const T dq = fv[k] - acc;
+                const T y = (q == 0) ? dq * rv[k] : (dq - lo * prev) * rv[k];
+                x[at(line, q)] = y;
+                prev = y;
+                m0 = m1;
+                m1 = mn[k];
+                p0 = p1;
+                p1 = pn[k];
+            }
+        }
+    }
+    T next = prev;   // x_{N-1} = y_{N-1}
+#pragma unroll
+    for (int q1 = N - 2; q1 >= 0; q1 -= ZK) {
+        T yv[ZK], uv[ZK];
+#pragma unroll
+        for (int k = 0; k < ZK; ++k) {
+            const int q = q1 - k;
+            if (q >= 0) {
+                yv[k] = x[at(line, q)];
+                uv[k] = tab[N + q];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < ZK; ++k) {
+            const int q = q1 - k;
+            if (q >= 0) {
+                const T v = yv[k] - uv[k] * next;
+                x[at(line, q)] = v;
+                next = v;
+            }
+        }
+    }
+}
+template <typename T, int N, int NB>
+__device__ __noinline__ void ph_zebra0(lds<T> x, clds<T> F, clds<T> sc, clds<T> tab, int color, int t)
+{
+    zebra_lds_line<T, N, 0>(x, F, sc, tab, color, t);
+}
+template <typename T, int N, int NB>
+__device__ __noinline__ void ph_zebra1(lds<T> x, clds<T> F, clds<T> sc, clds<T> tab, int color, int t)
+{
+    zebra_lds_line<T, N, 1>(x, F, sc, tab, color, t);
+}
+
+// LDS element offset of the zebra tables of a level of size 2^lg - 1 (lg >= 1)
+// in the persistent kernel's table block: levels in increasing size, 4 n each
+__host__ __device__ constexpr int zlds_off(int lg) { return 4 * ((1 << lg) - lg - 1); }
+static_assert(zlds_off(7) == ZLDS_TABLE, "zebra table block");
+
 // ---------------------------------------------------------------------------
 // register engine: a whole call on a level that wave 0 runs alone (n <= 15),
 // with every coarser level of that call, held in registers.  Level N uses
@@ -1842,13 +2171,16 @@ __device__ __noinline__ void wcall_level(lds<T> vbuf, clds<T> fbuf, clds<T> sd, 
     }
 }
 
-template <typename T, int THREADS>
+// ZEB: the levels relax by alternating zebra line relaxation (in place, no
+// buffer swaps; tables in the LDS block zt) instead of damped Jacobi
+template <typename T, int THREADS, bool ZEB>
 struct Sub {
     T* sm;
     const SubParams<T>* pp;
     const InstDev* I;
     int nu1, nu2, wave_n;
     uint32_t cur;           // bit d: current estimate of level d is in the second buffer
+    T* zt = nullptr;
     bool pending = false;   // wave 0 has written LDS since the last workgroup barrier
 
     // level d of size n = 2^lg - 1 starts at LDS element off: buffers 0 and 1 (sweeps), 2 (F)
@@ -1864,8 +2196,35 @@ struct Sub {
         else __syncthreads();
     }
 
+    // zebra: a zero-guess call starts from v = 0; relaxation r runs x-lines (r even)
+    // or y-lines (r odd), lines of even index first
+    __device__ __forceinline__ void zebra_sweeps(int d, int lg, int off, int nu, bool zg)
+    {
+        const bool single = single_lg(lg);
+        const int n = (1 << lg) - 1;
+        const lds<T> x = to_lds<T>(bufp(off, lg, (cur >> d) & 1));
+        if (zg) {
+            KC_LEVEL_SWITCH(lg, ph_zero, x)
+            sync_lg(lg);
+        }
+        const clds<T> F = to_lds<T>((const T*)bufp(off, lg, 2));
+        const clds<T> sc = to_lds<T>(&pp->s[d][0]);
+        for (int k = 0; k < nu; ++k) {
+            const clds<T> tab = to_lds<T>((const T*)(zt + zlds_off(lg) + (k & 1) * 2 * n));
+            for (int color = 0; color < 2; ++color) {
+                if (k & 1) { KC_LEVEL_SWITCH(lg, ph_zebra1, x, F, sc, tab, color) }
+                else { KC_LEVEL_SWITCH(lg, ph_zebra0, x, F, sc, tab, color) }
+                sync_lg(lg);
+            }
+        }
+    }
+
     __device__ __forceinline__ void sweeps(int d, int lg, int off, int nu, bool zg)
     {
+        if constexpr (ZEB) {
+            zebra_sweeps(d, lg, off, nu, zg);
+            return;
+        }
         const bool single = single_lg(lg);
         const clds<T> F = to_lds<T>((const T*)bufp(off, lg, 2));
         const clds<T> sc = to_lds<T>(&pp->s[d][0]);
@@ -1955,6 +2314,7 @@ struct Sub {
     // waves that skip a wave-0 operation still follow its buffer swaps
     __device__ __forceinline__ void skip(int kind, int d, bool zg)
     {
+        if constexpr (ZEB) return;   // zebra relaxes in place
         int k = 0;
         if (kind == SOP_PRE) k = (zg && nu1 == 0) ? 0 : nu1;
         else if (kind == SOP_POST) k = nu2;
@@ -2023,7 +2383,7 @@ __device__ __forceinline__ bool top_level_in(gp<const T> Fg, gp<const T> Ag, int
     return true;
 }
 
-template <typename T, int THREADS>
+template <typename T, int THREADS, bool ZEB>
 __global__ void __launch_bounds__(THREADS) k_subtree(SubArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -2044,10 +2404,13 @@ __global__ void __launch_bounds__(THREADS) k_subtree(SubArgs a)
     const gp<T> Ag = glob<T>(Lv.A);
     const bool zero = a.pair || a.zg;
     const int k1 = min(a.kappa, MAXL + 1), k2 = min(max(a.kappa - 1, 1), MAXL + 1);
-    const int n1 = I.ops_len[k1 - 1], n2 = (a.pair && a.kappa > 1) ? I.ops_len[k2 - 1] : 0;
+    // zebra calls use op lists without register calls
+    const int32_t* const obeg = ZEB ? I.zops_beg : I.ops_beg;
+    const int32_t* const olen = ZEB ? I.zops_len : I.ops_len;
+    const int n1 = olen[k1 - 1], n2 = (a.pair && a.kappa > 1) ? olen[k2 - 1] : 0;
     auto stage = [&]() {   // parameters, op lists and a small coarsest factor into LDS; LDS levels zeroed
         for (int t = threadIdx.x; t < n1 + n2; t += blockDim.x)
-            pp.ops[t] = (t < n1) ? I.ops[I.ops_beg[k1 - 1] + t] : I.ops[I.ops_beg[k2 - 1] + (t - n1)];
+            pp.ops[t] = (t < n1) ? I.ops[obeg[k1 - 1] + t] : I.ops[obeg[k2 - 1] + (t - n1)];
         for (int t = threadIdx.x; t < MAXL * 9; t += blockDim.x) {
             const int d = t / 9;
             pp.s[d][t % 9] = (d < L) ? P<T>::s(I, d)[t % 9] : T(0);
@@ -2065,6 +2428,14 @@ __global__ void __launch_bounds__(THREADS) k_subtree(SubArgs a)
         if (I.nc2 * I.nc2 <= SubParams<T>::CH)
             for (int t = threadIdx.x; t < I.nc2 * I.nc2; t += blockDim.x) pp.chol[t] = P<T>::chol(I)[t];
         for (int p = threadIdx.x; p < I.sub_lds; p += blockDim.x) sm[p] = T(0);
+        if constexpr (ZEB) {   // line-solve tables of the relaxed levels, after the level arrays
+            for (int dd = d0; dd < L - 1; ++dd) {
+                const int nn = I.lev[dd].n, lgd = 32 - __clz(nn);
+                const T* src = ZT<T>::t(I, dd);
+                T* dst = sm + I.sub_lds + zlds_off(lgd);
+                for (int p = threadIdx.x; p < 4 * nn; p += blockDim.x) dst[p] = src[p];
+            }
+        }
     };
     // level sizes are 2^k - 1 <= cutover <= 63; the host accepts a 63 x 63 top level only with 512 threads
     T* const lev = sm + I.lds_off[d0];
@@ -2081,7 +2452,8 @@ __global__ void __launch_bounds__(THREADS) k_subtree(SubArgs a)
     }
     if (!live) return;   // the whole workgroup leaves together
 
-    Sub<T, THREADS> S{sm, &pp, &I, a.nu1, a.nu2, a.wave_n, 0u};
+    Sub<T, THREADS, ZEB> S{sm, &pp, &I, a.nu1, a.nu2, a.wave_n, 0u};
+    if constexpr (ZEB) S.zt = sm + I.sub_lds;
     const int Pst = n + 2, off0 = pp.off[d0];
     const int lg0 = 32 - __clz(n);   // n = 2^lg0 - 1
     T* v0 = S.bufp(off0, lg0, 0);
@@ -2538,14 +2910,20 @@ hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nb, h
 hipError_t launch_subtree(bool f32, const SubArgs& a, int32_t threads, int32_t lds_bytes, hipStream_t s)
 {
     if (a.count <= 0) return hipSuccess;
+    const bool z = a.smoother == 1;
     if (threads == 256) {
-        if (f32) k_subtree<float, 256><<<a.count, 256, lds_bytes, s>>>(a);
-        else k_subtree<double, 256><<<a.count, 256, lds_bytes, s>>>(a);
+        if (f32) z ? k_subtree<float, 256, true><<<a.count, 256, lds_bytes, s>>>(a)
+                   : k_subtree<float, 256, false><<<a.count, 256, lds_bytes, s>>>(a);
+        else z ? k_subtree<double, 256, true><<<a.count, 256, lds_bytes, s>>>(a)
+               : k_subtree<double, 256, false><<<a.count, 256, lds_bytes, s>>>(a);
     } else if (threads == 512) {
-        if (f32) k_subtree<float, 512><<<a.count, 512, lds_bytes, s>>>(a);
-        else k_subtree<double, 512><<<a.count, 512, lds_bytes, s>>>(a);
+        if (f32) z ? k_subtree<float, 512, true><<<a.count, 512, lds_bytes, s>>>(a)
+                   : k_subtree<float, 512, false><<<a.count, 512, lds_bytes, s>>>(a);
+        else z ? k_subtree<double, 512, true><<<a.count, 512, lds_bytes, s>>>(a)
+               : k_subtree<double, 512, false><<<a.count, 512, lds_bytes, s>>>(a);
     } else if (threads == 1024 && f32) {   // FP32 only: the FP64 kernel does not fit 128 registers
-        k_subtree<float, 1024><<<a.count, 1024, lds_bytes, s>>>(a);
+        z ? k_subtree<float, 1024, true><<<a.count, 1024, lds_bytes, s>>>(a)
+          : k_subtree<float, 1024, false><<<a.count, 1024, lds_bytes, s>>>(a);
     } else {
         return hipErrorInvalidValue;
     }
@@ -2562,18 +2940,14 @@ hipError_t launch_coarsest(bool f32, const SubArgs& a, hipStream_t s)
 
 hipError_t prepare_subtree(bool f32, int32_t lds_bytes)
 {
-    hipError_t e;
-    if (f32) {
-        e = hipFuncSetAttribute((const void*)k_subtree<float, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_subtree<float, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_subtree<float, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    } else {
-        e = hipFuncSetAttribute((const void*)k_subtree<double, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_subtree<double, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    }
+    const void* ks[] = {(const void*)k_subtree<float, 256, false>,  (const void*)k_subtree<float, 512, false>,
+                        (const void*)k_subtree<float, 1024, false>, (const void*)k_subtree<float, 256, true>,
+                        (const void*)k_subtree<float, 512, true>,   (const void*)k_subtree<float, 1024, true>,
+                        (const void*)k_subtree<double, 256, false>, (const void*)k_subtree<double, 512, false>,
+                        (const void*)k_subtree<double, 256, true>,  (const void*)k_subtree<double, 512, true>};
+    hipError_t e = hipSuccess;
+    for (int k = f32 ? 0 : 6; k < (f32 ? 6 : 10) && e == hipSuccess; ++k)
+        e = hipFuncSetAttribute(ks[k], hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     return e;
 }
 

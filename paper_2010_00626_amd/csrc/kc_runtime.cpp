@@ -178,7 +178,7 @@ struct InstLayout {
 struct Layout {
     size_t inst = 0, state = 0, tiles = 0, lists = 0, partial = 0, hist = 0;
     size_t total = 0;
-    int ntables = 0;       // (1 + 2 MAXL) tile tables of (count + 1)
+    int ntables = 0;       // NTABLES tile tables of (count + 1)
     int total_tiles0 = 0;
     std::vector<InstLayout> il;
 };
@@ -187,6 +187,13 @@ int tiles_of(int n) { return ((n + TX - 1) / TX) * ((n + TY - 1) / TY); }
 int tiles_small(int n) { return ((n + TS - 1) / TS) * ((n + TS - 1) / TS); }
 int tiles_mid(int n) { return ((n + TM - 1) / TM) * ((n + TM - 1) / TM); }
 int tiles_tiny(int n) { return ((n + TT - 1) / TT) * ((n + TT - 1) / TT); }
+// zebra launches: the lines of one colour ((n + 1) / 2 at most), one wave each (four per
+// workgroup) on levels with n >= wave_n > 0, else one thread each (64 per workgroup)
+int zebra_blocks(int n, int wave_n)
+{
+    const int lines = (n + 1) / 2;
+    return (wave_n > 0 && n >= wave_n) ? (lines + GRID_THREADS / 64 - 1) / (GRID_THREADS / 64) : (lines + 63) / 64;
+}
 // streaming blocks: STRIP_BLOCK_W columns x R rows, R = 16 << code
 int strip_rows_code(int n) { return n >= 4095 ? 2 : (n >= 2047 ? 1 : 0); }
 int tiles_stream(int n, int code) { return ((n + STRIP_BLOCK_W - 1) / STRIP_BLOCK_W) * ((n + (16 << code) - 1) / (16 << code)); }
@@ -205,7 +212,7 @@ kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Lay
     lay.il.assign(count, InstLayout());
     lay.inst = take(sizeof(InstDev) * count);
     lay.state = take(sizeof(InstState) * count);
-    lay.ntables = 1 + 2 * MAXL;
+    lay.ntables = NTABLES;
     lay.tiles = take(sizeof(int32_t) * (size_t)lay.ntables * (count + 1));
     lay.lists = take(sizeof(int32_t) * (size_t)2 * MAXL * count);
     int tiles0 = 0;
@@ -276,6 +283,7 @@ struct HostInst {
     double s[MAXL][9];
     std::vector<uint32_t> ops;
     int ops_beg[KMAX] = {}, ops_len[KMAX] = {};
+    int zops_beg[KMAX] = {}, zops_len[KMAX] = {};   // zebra relaxation: lists without register calls
     int lds_off[MAXL] = {}, lds_elems = 0;
 };
 
@@ -285,6 +293,10 @@ int lg_of(int n)
     while ((1 << lg) - 1 < n) ++lg;
     return lg;
 }
+
+// op list lengths / starts for a smoother (0 damped Jacobi, 1 zebra)
+const int* olen(const HostInst& hi, int smoother) { return smoother == 1 ? hi.zops_len : hi.ops_len; }
+const int* obeg(const HostInst& hi, int smoother) { return smoother == 1 ? hi.zops_beg : hi.ops_beg; }
 
 // op list of one call at depth d with counter k (Algorithm 3), levels in LDS;
 // a call on a level of at most reg_n points per side becomes one register call
@@ -336,6 +348,7 @@ struct kc_hier {
     bool compacted = false;                    // the tables cover only the instances still iterating
     int last_compactions = 0;                  // table compactions during the last driver call
     int sub_lds = 0;
+    int sub_lds_z = 0;                         // with the zebra line-solve tables after the levels
     std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> graphs;   // (driver, kappa, nu1, nu2, smoother)
     double omega_set = -1.0;
     // stats
@@ -350,7 +363,8 @@ namespace {
 // tile table indices
 int tt_all0() { return 0; }
 int tt_cut(int d) { return 1 + d; }          // instances with cut > d
-int tt_lvl(int d) { return 1 + MAXL + d; }   // instances with L - 1 > d
+int tt_lvl(int d) { return 1 + MAXL + d; }   // instances with L - 1 > d and cut > d (one kernel per operation)
+int tt_zeb(int d) { return 1 + 2 * MAXL + d; }   // zebra line groups of those instances
 int lt_sub(int d) { return d; }              // instances with cut == d
 int lt_coarse(int d) { return MAXL + d; }    // instances with L - 1 == d
 
@@ -391,7 +405,7 @@ Launch fused_grid(kc_hier* h, GridKernel gk, bool f32, int d)
     return L;
 }
 
-Launch sub(kc_hier* h, bool f32, int depth, int kappa, bool pair, int nu1, int nu2, bool zg, int fin)
+Launch sub(kc_hier* h, bool f32, int depth, int kappa, bool pair, int nu1, int nu2, bool zg, int fin, int smoother = 0)
 {
     Launch L{};
     L.type = L_SUB;
@@ -409,9 +423,10 @@ Launch sub(kc_hier* h, bool f32, int depth, int kappa, bool pair, int nu1, int n
     L.ba.zg = zg ? 1 : 0;
     L.ba.fin = fin;
     L.ba.wave_n = h->ex.coarse_wave_n;
+    L.ba.smoother = smoother;
     L.ba.hist = h->d_hist;
     L.threads = h->ex.coarse_threads;
-    L.lds = h->sub_lds;
+    L.lds = smoother == 1 ? h->sub_lds_z : h->sub_lds;
     return L;
 }
 
@@ -469,10 +484,15 @@ void cycle_fused(kc_hier* h, const kc_cycle_params& c, int kappa, bool zg, int f
     if (h->ex.fuse_junctions) fuse_junctions(out, from);
 }
 
-// Algorithm 4: one launch per operation; cur[d] tracks which buffer holds v_d
+// Algorithm 4: one launch per operation; cur[d] tracks which buffer holds v_d.
+// With zebra relaxation in the fused execution mode the same schedule runs the
+// levels above each instance's cut, and one persistent launch per parent call
+// runs the pair of child calls at the cut (every coarser level, the coarsest
+// solve included, stays inside it)
 void gen_paper(kc_hier* h, int d, int k, const kc_cycle_params& c, bool f32, int cur[], std::vector<Launch>& out)
 {
-    if (nlist(h, lt_coarse(d)) > 0) {
+    const bool hybrid = h->ex.mode == 0;
+    if (!hybrid && nlist(h, lt_coarse(d)) > 0) {
         Launch L{};
         L.type = L_COARSEST;
         L.f32 = f32;
@@ -498,10 +518,11 @@ void gen_paper(kc_hier* h, int d, int k, const kc_cycle_params& c, bool f32, int
     auto relax = [&](int r) {
         if (c.smoother == 1) {
             for (int color = 0; color < 2; ++color) {
-                Launch L = grid(h, GK_ZEBRA, f32, tt_lvl(d), d);
+                Launch L = grid(h, GK_ZEBRA, f32, tt_zeb(d), d);
                 L.sa.src = cur[d];
                 L.sa.dst = color;
                 L.sa.nu = r & 1;
+                L.sa.flags = h->ex.zebra_wave_n;   // per instance: one wave per line at n >= this
                 out.push_back(L);
             }
         } else {
@@ -514,6 +535,8 @@ void gen_paper(kc_hier* h, int d, int k, const kc_cycle_params& c, bool f32, int
     op(GK_RESTRICT, cur[d] ^ 1, 0);
     op(GK_ZERO, 0, 0);
     cur[d + 1] = 0;
+    if (hybrid && nlist(h, lt_sub(d + 1)) > 0)   // result in the level's first buffer
+        out.push_back(sub(h, f32, d + 1, k, true, c.nu1, c.nu2, false, FIN_NONE, c.smoother));
     gen_paper(h, d + 1, k, c, f32, cur, out);
     if (k > 1) gen_paper(h, d + 1, k - 1, c, f32, cur, out);
     {
@@ -530,6 +553,8 @@ void cycle_paper(kc_hier* h, const kc_cycle_params& c, int kappa, bool zg, bool 
 {
     int cur[MAXL + 1] = {};
     if (zg) out.push_back(grid(h, GK_ZERO_SELF, f32, tt_all0(), 0));   // v_1 <- 0 for a zero-guess call
+    if (h->ex.mode == 0 && nlist(h, lt_sub(0)) > 0)   // instances below the cutover altogether
+        out.push_back(sub(h, f32, 0, kappa, false, c.nu1, c.nu2, false, FIN_NONE, c.smoother));
     gen_paper(h, 0, kappa, c, f32, cur, out);
     if (cur[0] != 0) {
         Launch L = grid(h, GK_COPY, f32, tt_lvl(0), 0);
@@ -569,7 +594,7 @@ void count_launches(const std::vector<Launch>& ls, int64_t& grid_n, int64_t& sub
 kc_status build_tables(kc_hier* h, const std::vector<char>* active)
 {
     const int cnt = h->count;
-    h->tiles.assign(1 + 2 * MAXL, std::vector<int32_t>(cnt + 1, 0));
+    h->tiles.assign(NTABLES, std::vector<int32_t>(cnt + 1, 0));
     h->lists.assign(2 * MAXL, std::vector<int32_t>());
     for (int i = 0; i < cnt; ++i) {
         if (active && !(*active)[i]) continue;
@@ -584,14 +609,18 @@ kc_status build_tables(kc_hier* h, const std::vector<char>* active)
                            : (sh & 16) ? tiles_mid(hi.il.n[d])
                                        : tiles_of(hi.il.n[d]);
             h->tiles[tt_cut(d)][i + 1] = (d < L && hi.cut > d) ? tc : 0;
-            h->tiles[tt_lvl(d)][i + 1] = (d < L - 1) ? tiles_of(hi.il.n[d]) : 0;
+            // one-kernel-per-operation stages: levels above the instance's cut (all of them in
+            // the paper-structured mode, where the cut is L)
+            const bool lvl = d < L - 1 && hi.cut > d;
+            h->tiles[tt_lvl(d)][i + 1] = lvl ? tiles_of(hi.il.n[d]) : 0;
+            h->tiles[tt_zeb(d)][i + 1] = lvl ? zebra_blocks(hi.il.n[d], h->ex.zebra_wave_n) : 0;
             if (hi.cut == d && d < L) h->lists[lt_sub(d)].push_back(i);
             if (L - 1 == d) h->lists[lt_coarse(d)].push_back(i);
         }
     }
     for (auto& t : h->tiles)
         for (int i = 0; i < cnt; ++i) t[i + 1] += t[i];
-    std::vector<int32_t> flat((size_t)(1 + 2 * MAXL) * (cnt + 1));
+    std::vector<int32_t> flat((size_t)NTABLES * (cnt + 1));
     for (size_t t = 0; t < h->tiles.size(); ++t) std::copy(h->tiles[t].begin(), h->tiles[t].end(), flat.begin() + t * (cnt + 1));
     std::vector<int32_t> lflat((size_t)2 * MAXL * cnt, 0);
     for (size_t t = 0; t < h->lists.size(); ++t) std::copy(h->lists[t].begin(), h->lists[t].end(), lflat.begin() + t * cnt);
@@ -614,6 +643,7 @@ kc_status plan_exec(kc_hier* h)
     h->max_cut = 0;
     h->max_L = 0;
     h->sub_lds = 0;
+    h->sub_lds_z = 0;
     for (int i = 0; i < h->count; ++i) {
         HostInst& hi = h->hi[i];
         const int L = hi.il.L;
@@ -649,9 +679,28 @@ kc_status plan_exec(kc_hier* h)
             }
             hi.ops_len[k - 1] = (int)hi.ops.size() - hi.ops_beg[k - 1];
         }
+        // zebra relaxation has no register engine: its lists run every level phase by phase
+        for (int k = 1; k <= KMAX; ++k) {
+            hi.zops_beg[k - 1] = hi.ops_beg[k - 1];
+            hi.zops_len[k - 1] = hi.ops_len[k - 1];
+        }
+        if (reg_n > 0 && cut < L) {
+            const int below = L - cut;
+            for (int k = 1; k <= KMAX; ++k) {
+                if (k <= below + 1 || k == 1) {
+                    hi.zops_beg[k - 1] = (int)hi.ops.size();
+                    gen_sub_call(hi, cut, k, false, 0, hi.ops);
+                    hi.zops_len[k - 1] = (int)hi.ops.size() - hi.zops_beg[k - 1];
+                } else {
+                    hi.zops_beg[k - 1] = hi.zops_beg[below];
+                    hi.zops_len[k - 1] = hi.zops_len[below];
+                }
+            }
+        }
         if ((int)hi.ops.size() > OPS_CAP) return fail(KC_ERR_ARG, "coarse cutover too large for the op buffer");
         hi.lds_elems = off;
         h->sub_lds = std::max(h->sub_lds, (int)(off * T));
+        if (cut < L) h->sub_lds_z = std::max(h->sub_lds_z, (int)((off + ZLDS_TABLE) * T));
     }
     if (h->sub_lds > 0 && h->d_tiles) {
         const int maxl = max_lds_bytes() - 8192;   // the kernel's static parameter block stays below 8 KB
@@ -679,8 +728,8 @@ kc_status plan_exec(kc_hier* h)
             HIPCHK(hipMemcpyAsync(h->ws + hi.il.ops, hi.ops.data(), hi.ops.size() * 4, hipMemcpyHostToDevice, h->stream));
         }
         HIPCHK(hipStreamSynchronize(h->stream));
-        if (h->sub_lds > 65536) {
-            HIPCHK(prepare_subtree(h->prec == KC_F32_CYCLE, h->sub_lds));
+        if (std::max(h->sub_lds, h->sub_lds_z) > 65536) {
+            HIPCHK(prepare_subtree(h->prec == KC_F32_CYCLE, std::max(h->sub_lds, h->sub_lds_z)));
         }
     }
     return KC_OK;
@@ -742,6 +791,8 @@ void fill_inst_static(kc_hier* h)
         for (int k = 0; k < KMAX; ++k) {
             I.ops_beg[k] = hi.ops_beg[k];
             I.ops_len[k] = hi.ops_len[k];
+            I.zops_beg[k] = hi.zops_beg[k];
+            I.zops_len[k] = hi.zops_len[k];
         }
         I.ops = (const uint32_t*)(h->ws + hi.il.ops);
         I.chol64 = (const double*)(h->ws + hi.il.chol64);
@@ -815,7 +866,9 @@ void iteration(kc_hier* h, int drv, const kc_cycle_params& c, std::vector<Launch
 {
     const bool f32 = h->prec == KC_F32_CYCLE;
     const int kappa = clamp_kappa(h, c.kappa);
-    const bool paper = h->ex.mode == 1;
+    // zebra relaxation always takes the one-kernel-per-operation schedule above the
+    // persistent kernel (the fused grid kernels are damped Jacobi)
+    const bool paper = h->ex.mode == 1 || c.smoother == 1;
     switch (drv) {
     case DRV_CYCLE:
         if (paper) cycle_paper(h, c, kappa, false, false, out);
@@ -1002,11 +1055,13 @@ kc_status prepare_call(kc_hier* h, const kc_cycle_params* c)
 {
     kc_status s = check_cycle(c);
     if (s != KC_OK) return s;
-    if (c->smoother == 1 && h->ex.mode != 1)
-        return fail(KC_ERR_ARG, "the zebra smoother runs in the paper-structured execution mode (exec.mode = 1)");
-    if (c->smoother == 1)
+    if (c->smoother == 1) {
         for (int i = 0; i < h->count; ++i)
             if (h->hi[i].il.n[0] > 16383) return fail(KC_ERR_ARG, "the zebra smoother takes n <= 16383");
+        if (h->ex.mode == 0 && h->sub_lds_z > max_lds_bytes() - 8192)
+            return fail(KC_ERR_ARG, "coarse cutover with zebra tables needs " + std::to_string(h->sub_lds_z) +
+                                        " B of LDS, device allows " + std::to_string(max_lds_bytes() - 8192));
+    }
     if (c->omega != h->omega_set) {
         set_omega(h, c->omega);
         h->omega_set = c->omega;
@@ -1036,8 +1091,9 @@ void record_counts(kc_hier* h, int drv, const kc_cycle_params& c)
             for (int idx : h->lists[lt_sub(L.ba.depth)]) {
                 const HostInst& hi = h->hi[idx];
                 const int kk = std::min(L.ba.kappa, KMAX);
-                st += hi.ops_len[kk - 1];
-                if (L.ba.pair && L.ba.kappa > 1) st += hi.ops_len[std::min(L.ba.kappa - 1, KMAX) - 1];
+                const int* ln = olen(hi, L.ba.smoother);
+                st += ln[kk - 1];
+                if (L.ba.pair && L.ba.kappa > 1) st += ln[std::min(L.ba.kappa - 1, KMAX) - 1];
                 break;
             }
     h->last_sub_stages = st;
@@ -1056,7 +1112,8 @@ constexpr double FL_PROLONG = 3.0;    // average over injected, edge and centre 
 std::string launch_name(const kc_hier* h, const Launch& L)
 {
     const char* T = L.f32 ? "float" : "double";
-    if (L.type == L_SUB) return std::string("k_subtree<") + T + ", " + std::to_string(L.threads) + ">";
+    if (L.type == L_SUB)
+        return std::string("k_subtree<") + T + ", " + std::to_string(L.threads) + (L.ba.smoother == 1 ? ", true>" : ", false>");
     if (L.type == L_COARSEST) return std::string("k_coarsest<") + T + ">";
     if (L.gk == GK_POSTPRE)
         return std::string("k_postpre<") + T + ", " + std::to_string(L.sa.src) + ", " + std::to_string(L.sa.nu) +
@@ -1088,8 +1145,8 @@ void launch_work(const kc_hier* h, const Launch& L, double& bytes, double& flops
             bytes += 2.0 * nt * nt * T;
             auto add_list = [&](int k) {
                 const int kk = std::min(k, KMAX);
-                for (int o = 0; o < hi.ops_len[kk - 1]; ++o) {
-                    const uint32_t op = hi.ops[hi.ops_beg[kk - 1] + o];
+                for (int o = 0; o < olen(hi, L.ba.smoother)[kk - 1]; ++o) {
+                    const uint32_t op = hi.ops[obeg(hi, L.ba.smoother)[kk - 1] + o];
                     const double n = hi.il.n[sop_depth(op)], n2 = n * n;
                     if (sop_kind(op) == SOP_PRE) {
                         const double nc = (n - 1) / 2;
@@ -1163,6 +1220,7 @@ void kc_exec_default(kc_exec* e)
     e->stream_n = 2047;
     e->mid_tile_n = 2047;
     e->tiny_tile_n = 255;
+    e->zebra_wave_n = 63;
     e->wave_regs = 1;
     e->fuse_junctions = 1;
 }
@@ -1228,6 +1286,7 @@ static kc_status validate_exec(const kc_exec* e, int prec)
     if (e->stream_n < 0) return fail(KC_ERR_ARG, "stream_n must be >= 0");
     if (e->mid_tile_n < 0 || e->mid_tile_n > 4095) return fail(KC_ERR_ARG, "mid_tile_n must be in 0..4095");
     if (e->tiny_tile_n < 0 || e->tiny_tile_n > 4095) return fail(KC_ERR_ARG, "tiny_tile_n must be in 0..4095");
+    if (e->zebra_wave_n < 0 || e->zebra_wave_n > 16383) return fail(KC_ERR_ARG, "zebra_wave_n must be in 0..16383");
     if (e->wave_regs != 0 && e->wave_regs != 1) return fail(KC_ERR_ARG, "wave_regs must be 0 or 1");
     if (e->fuse_junctions != 0 && e->fuse_junctions != 1) return fail(KC_ERR_ARG, "fuse_junctions must be 0 or 1");
     if (e->coarse_threads * 8 < 64 * e->coarse_cutover) return fail(KC_ERR_ARG, "coarse_threads too small for the cutover");
@@ -1262,9 +1321,9 @@ kc_status kc_schedule_counts(const kc_problem* probs, int32_t count, const kc_ex
     h.d_tiles = nullptr;
     s = plan_exec(&h);
     if (s != KC_OK) return s;
-    std::vector<int32_t> zeros((size_t)(1 + 2 * MAXL) * (count + 1) + 2 * MAXL * count, 0);
+    std::vector<int32_t> zeros((size_t)NTABLES * (count + 1) + 2 * MAXL * count, 0);
     h.d_tiles = zeros.data();
-    h.d_lists = zeros.data() + (size_t)(1 + 2 * MAXL) * (count + 1);
+    h.d_lists = zeros.data() + (size_t)NTABLES * (count + 1);
     std::vector<Launch> ls;
     iteration(&h, DRV_CYCLE, *c, ls);
     int64_t g = 0, sb = 0;
@@ -1274,8 +1333,8 @@ kc_status kc_schedule_counts(const kc_problem* probs, int32_t count, const kc_ex
         if (L.type == L_SUB)
             for (int idx : h.lists[lt_sub(L.ba.depth)]) {
                 const HostInst& hi = h.hi[idx];
-                st += hi.ops_len[std::min(L.ba.kappa, KMAX) - 1];
-                if (L.ba.pair && L.ba.kappa > 1) st += hi.ops_len[std::min(L.ba.kappa - 1, KMAX) - 1];
+                st += olen(hi, L.ba.smoother)[std::min(L.ba.kappa, KMAX) - 1];
+                if (L.ba.pair && L.ba.kappa > 1) st += olen(hi, L.ba.smoother)[std::min(L.ba.kappa - 1, KMAX) - 1];
                 break;
             }
     if (grid_launches) *grid_launches = g;
@@ -1800,6 +1859,7 @@ kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
     js += ", \"stream_n\": " + std::to_string(h->ex.stream_n);
     js += ", \"mid_tile_n\": " + std::to_string(h->ex.mid_tile_n);
     js += ", \"tiny_tile_n\": " + std::to_string(h->ex.tiny_tile_n);
+    js += ", \"zebra_wave_n\": " + std::to_string(h->ex.zebra_wave_n);
     js += ", \"wave_regs\": " + std::to_string(h->ex.wave_regs);
     js += ", \"fuse_junctions\": " + std::to_string(h->ex.fuse_junctions);
     js += ", \"subtree_lds_bytes\": " + std::to_string(h->sub_lds);

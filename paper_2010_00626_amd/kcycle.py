@@ -51,7 +51,8 @@ class Exec(C.Structure):
                 ("coarse_threads", C.c_int32), ("poll_every", C.c_int32), ("coarse_wave_n", C.c_int32),
                 ("small_tile_n", C.c_int32), ("stream_n", C.c_int32),
                 ("wave_regs", C.c_int32), ("fuse_junctions", C.c_int32), ("mid_tile_n", C.c_int32),
-                ("tiny_tile_n", C.c_int32)]
+                ("tiny_tile_n", C.c_int32),
+                ("zebra_wave_n", C.c_int32)]
 
 
 _lib = None
@@ -107,7 +108,8 @@ def _check(status: int, allow_positive: bool = False) -> int:
 def exec_options(mode: int | str = 0, use_graph: bool = True, coarse_cutover: int = 31,
                  coarse_threads: int = 512, poll_every: int = 0, coarse_wave_n: int = 15,
                  small_tile_n: int = 511, stream_n: int = 2047, wave_regs: int = 1,
-                 fuse_junctions: int = 1, mid_tile_n: int = 2047, tiny_tile_n: int = 255) -> Exec:
+                 fuse_junctions: int = 1, mid_tile_n: int = 2047, tiny_tile_n: int = 255,
+                 zebra_wave_n: int = 63) -> Exec:
     e = Exec()
     lib().kc_exec_default(C.byref(e))
     e.mode = {"fused": 0, "paper": 1}.get(mode, mode) if isinstance(mode, str) else int(mode)
@@ -122,6 +124,7 @@ def exec_options(mode: int | str = 0, use_graph: bool = True, coarse_cutover: in
     e.fuse_junctions = int(fuse_junctions)
     e.mid_tile_n = int(mid_tile_n)
     e.tiny_tile_n = int(tiny_tile_n)
+    e.zebra_wave_n = int(zebra_wave_n)
     return e
 
 

@@ -25,7 +25,8 @@ Times: stand-alone total = cycles x (median device time per cycle of the
 chunks); MGCG total = wall time of one run of exactly k iterations (setup and
 host polling included, as the paper's totals include theirs).
 
-Usage: python -m paper_2010_00626_amd.protocol [--tables] [--sweep 9,13] [--zebra-levels 12] [--maxc 40000]
+Usage: python -m paper_2010_00626_amd.protocol [--tables] [--sweep 9,13] [--zebra-levels 12] [--zebra-exec JSON]
+       [--maxc 40000]
 Prints one JSON object per result line and a summary object at the end.
 """
 from __future__ import annotations
@@ -113,18 +114,18 @@ def mgcg(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, kmax: int = 4000, s
 
 
 def run(levels: int, theta: float, eps: float, kappas, which: str, seed: int, maxc: int,
-        smoother: str = "jacobi") -> list:
+        smoother: str = "jacobi", exec_opts: dict | None = None) -> list:
     import torch
     n = 2 ** levels - 1
     v0 = torch.from_numpy(inputs.uniform_rhs(np.random.default_rng(seed), n)).to("cuda")
-    # the zebra smoother runs in the paper-structured execution mode
-    H = kcycle.Hierarchy([(n, theta, eps)], "f64", exec=dict(mode="paper") if smoother == "zebra" else None)
+    H = kcycle.Hierarchy([(n, theta, eps)], "f64", exec=exec_opts)
     out = []
     for k in kappas:
         t0 = time.perf_counter()
         r = (standalone(H, v0, k, maxc=maxc, smoother=smoother) if which == "standalone"
              else mgcg(H, v0, k, smoother=smoother))
-        r.update({"solver": which, "smoother": smoother, "levels": levels, "n": n, "theta": theta, "eps": eps,
+        r.update({"solver": which, "smoother": smoother, "exec": exec_opts or {}, "levels": levels, "n": n,
+                  "theta": theta, "eps": eps,
                   "kappa": _key(k),
                   "unknowns_per_s": (n * n / (r["total_ms"] * 1e-3)) if r.get("total_ms") else None,
                   "wall_s": round(time.perf_counter() - t0, 2)})
@@ -144,6 +145,8 @@ def main(argv=None):
     ap.add_argument("--zebra-levels", type=int, default=0, help="Tables 5 and 6 (zebra) at this many levels")
     ap.add_argument("--angles", default="10,30,45,60,80", help="degrees, for the zebra tables")
     ap.add_argument("--zebra-kappas", default="1,2,3,4,W")
+    ap.add_argument("--zebra-exec", default="{}",
+                    help='execution options of the zebra runs as JSON, e.g. \'{"mode": "paper"}\' (default: fused)')
     a = ap.parse_args(argv)
     res = {"tables": [], "sweep": [], "zebra": []}
     if a.tables:
@@ -156,7 +159,8 @@ def main(argv=None):
         zk = [kcycle.KAPPA_W if x == "W" else int(x) for x in a.zebra_kappas.split(",")]
         for deg in [float(x) for x in a.angles.split(",")]:
             for which in ("standalone", "mgcg"):
-                res["zebra"] += run(a.zebra_levels, math.radians(deg), 1e-5, zk, which, a.seed, a.maxc, "zebra")
+                res["zebra"] += run(a.zebra_levels, math.radians(deg), 1e-5, zk, which, a.seed, a.maxc, "zebra",
+                                    json.loads(a.zebra_exec))
     print(json.dumps({"summary": res}))
 
 

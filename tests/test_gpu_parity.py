@@ -662,11 +662,127 @@ def test_zebra_ir_fp32(n, kappa):
     H.close()
 
 
-def test_zebra_needs_paper_mode():
-    H = K().Hierarchy([(63, 0.3, 1e-3)], "f64")
-    u = torch.zeros((63, 63), dtype=torch.float64, device="cuda")
-    with pytest.raises(K().KCycleError):
-        H.solve(u, dev(np.ones((63, 63))), kappa=2, smoother="zebra")
+ZEBRA_WAVE_CASES = [(63, 2, 1, 1), (127, 2 ** 31 - 1, 1, 1), (255, 3, 3, 127), (511, 2, 1, 511), (255, 1, 1, 0)]
+
+
+@pytest.mark.parametrize("n,kappa,nc,wave_n", ZEBRA_WAVE_CASES)
+def test_zebra_line_mappings_bitwise(n, kappa, nc, wave_n):
+    """Both line mappings of the zebra kernel (one wave per line on levels
+    with n >= zebra_wave_n, one thread per line below; 0 = threads only),
+    with chunk tails of every kind, give the oracle's bits."""
+    banner(f"zebra mappings n={n} kappa={kappa} n_coarsest={nc} zebra_wave_n={wave_n}")
+    rng = np.random.default_rng(7 * n + wave_n)
+    th, ep = 2.3, 1e-4
+    v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
+    H = K().Hierarchy([(n, th, ep, nc)], "f64", exec=dict(mode="paper", zebra_wave_n=wave_n))
+    v = dev(v0)
+    H.cycle(v, dev(f), kappa=kappa, nu1=2, nu2=2, smoother="zebra")
+    Ho = O.Hierarchy(n, th, ep, nc, smoother="zebra")
+    assert np.array_equal(host(v), Ho.cycle(v0, f, kappa=min(kappa, 64), nu1=2, nu2=2)[0])
+    H.close()
+
+
+def test_zebra_batched_ragged_mappings():
+    """A ragged batch whose instances take different line mappings in the
+    same launches: each instance gets the oracle's iterations and bits."""
+    banner("zebra batched ragged")
+    specs = [(255, 0.4, 1e-3), (63, 1.3, 1e-2), (127, 2.6, 1e-4), (511, 0.05, 1e-5)]
+    rng = np.random.default_rng(12)
+    fs = [inputs.uniform_rhs(rng, s[0]) for s in specs]
+    H = K().Hierarchy(specs, "f64", exec=dict(mode="paper", zebra_wave_n=127))
+    us = [torch.zeros((s[0], s[0]), dtype=torch.float64, device="cuda") for s in specs]
+    iters, relres, status = H.solve(us, [dev(f) for f in fs], kappa=2, tol=1e-8, maxit=400, smoother="zebra")
+    assert status == [0] * len(specs)
+    for k, (s, f) in enumerate(zip(specs, fs)):
+        u_ref, rc, it_ref, hist = O.Hierarchy(*s, smoother="zebra").solve(f, kappa=2, tol=1e-8, maxit=400)
+        assert rc == O.OK and iters[k] == it_ref, k
+        assert np.array_equal(host(us[k]), u_ref), k
+    H.close()
+
+
+ZEBRA_FUSED_CASES = [
+    (63, 2, 1, dict(coarse_cutover=31)),                                   # top level in grid kernels, cut at 31
+    (63, 2 ** 31 - 1, 1, dict(coarse_cutover=63)),                         # the whole instance in the persistent kernel
+    (255, 3, 1, dict(coarse_cutover=63, coarse_threads=512)),
+    (127, 4, 3, dict(coarse_cutover=15, coarse_threads=256)),              # 3 x 3 coarsest (Cholesky in LDS)
+    (255, 1, 1, dict(coarse_cutover=31, coarse_threads=256, coarse_wave_n=0)),
+    (511, 2, 1, dict(coarse_cutover=31, coarse_wave_n=7, wave_regs=0)),
+]
+
+
+@pytest.mark.parametrize("n,kappa,nc,ex", ZEBRA_FUSED_CASES)
+def test_zebra_fused_cycle_bitwise(n, kappa, nc, ex):
+    """Zebra relaxation in the fused mode (levels above the cutover one kernel
+    per operation, every call at the cutover in one persistent launch with
+    line solves in LDS): the oracle's bits, and the same bits as the
+    paper-structured mode."""
+    banner(f"zebra fused cycle n={n} kappa={kappa} n_coarsest={nc} exec={ex}")
+    rng = np.random.default_rng(3 * n + nc)
+    th, ep = 0.6, 1e-4
+    v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
+    Ho = O.Hierarchy(n, th, ep, nc, smoother="zebra")
+    ref = Ho.cycle(v0, f, kappa=min(kappa, 64), nu1=2, nu2=2)[0]
+    for mode_ex in (dict(ex), dict(mode="paper")):
+        H = K().Hierarchy([(n, th, ep, nc)], "f64", exec=mode_ex)
+        v = dev(v0)
+        H.cycle(v, dev(f), kappa=kappa, nu1=2, nu2=2, smoother="zebra")
+        assert np.array_equal(host(v), ref), mode_ex
+        H.cycle(v, dev(f), kappa=kappa, nu1=2, nu2=2, smoother="zebra")   # replay of the captured schedule
+        assert np.array_equal(host(v), Ho.cycle(ref, f, kappa=min(kappa, 64), nu1=2, nu2=2)[0]), mode_ex
+        H.close()
+
+
+@pytest.mark.parametrize("n,kappa,theta", [(255, 3, 0.3), (511, 4, 1.2)])
+def test_zebra_fused_solve_and_pcg(n, kappa, theta):
+    """Fused-mode zebra: stand-alone solve with the oracle's iterations and
+    bits (device stop test), PCG with FP64 and FP32 preconditioner cycles."""
+    banner(f"zebra fused solve/pcg n={n} kappa={kappa}")
+    ep = 1e-5
+    f = inputs.uniform_rhs(np.random.default_rng(n + kappa), n)
+    Ho = O.Hierarchy(n, theta, ep, smoother="zebra")
+    u_ref, rc, it_ref, hist = Ho.solve(f, kappa=kappa, tol=1e-8, maxit=500)
+    assert rc == O.OK
+    check_stop_margin(hist, 1e-8)
+    H = K().Hierarchy([(n, theta, ep)], "f64", exec=dict(coarse_cutover=63))
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    it, rr, st = H.solve(u, dev(f), kappa=kappa, tol=1e-8, maxit=500, smoother="zebra")
+    assert st == [0] and it[0] == it_ref
+    assert np.array_equal(host(u), u_ref)
+    up_ref, rc, itp_ref, _ = Ho.pcg(f, kappa=kappa, nu1=2, nu2=2, tol=1e-8, maxit=300)
+    assert rc == O.OK
+    u.zero_()
+    it, rr, st = H.pcg(u, dev(f), kappa=kappa, nu1=2, nu2=2, tol=1e-8, maxit=300, smoother="zebra")
+    assert st == [0] and it[0] == itp_ref
+    assert relmax(host(u), up_ref) <= 1e-9
+    H.close()
+    H32 = K().Hierarchy([(n, theta, ep)], "f32", exec=dict(coarse_cutover=31))
+    u.zero_()
+    it, rr, st = H32.pcg(u, dev(f), kappa=kappa, nu1=2, nu2=2, tol=1e-8, maxit=300, smoother="zebra")
+    assert st == [0] and abs(it[0] - itp_ref) <= 1
+    assert np.linalg.norm(f - Ho.apply(host(u))) / np.linalg.norm(f) < 2e-8
+    u.zero_()
+    it, rr, st = H32.solve(u, dev(f), kappa=kappa, tol=1e-8, maxit=500, smoother="zebra")
+    assert st == [0]
+    assert np.linalg.norm(f - Ho.apply(host(u))) / np.linalg.norm(f) < 1e-8
+    H32.close()
+
+
+def test_zebra_fused_batched_ragged():
+    """A ragged batch in the fused mode whose instances reach the cutover at
+    different depths (one lies below it altogether): each instance gets the
+    oracle's iterations and bits."""
+    banner("zebra fused batched ragged")
+    specs = [(255, 0.4, 1e-3), (31, 1.3, 1e-2), (127, 2.6, 1e-4), (511, 0.05, 1e-5), (63, 2.2, 3e-3)]
+    rng = np.random.default_rng(21)
+    fs = [inputs.uniform_rhs(rng, s[0]) for s in specs]
+    H = K().Hierarchy(specs, "f64", exec=dict(coarse_cutover=31))
+    us = [torch.zeros((s[0], s[0]), dtype=torch.float64, device="cuda") for s in specs]
+    iters, relres, status = H.solve(us, [dev(f) for f in fs], kappa=3, tol=1e-8, maxit=400, smoother="zebra")
+    assert status == [0] * len(specs)
+    for k, (s, f) in enumerate(zip(specs, fs)):
+        u_ref, rc, it_ref, hist = O.Hierarchy(*s, smoother="zebra").solve(f, kappa=3, tol=1e-8, maxit=400)
+        assert rc == O.OK and iters[k] == it_ref, k
+        assert np.array_equal(host(us[k]), u_ref), k
     H.close()
 
 
