@@ -70,7 +70,7 @@ struct InstDev {
     double ds_ep[9];     // d stencil / d eps
 };
 
-// per-instance solver state, written by the finalising block of reductions
+// per-instance solver state, written by the finalize kernel of reductions
 struct InstState {
     double ssf;        // ||F||^2 (scaled units)
     double relres;     // last relative residual
@@ -86,11 +86,9 @@ struct InstState {
     int32_t status;    // kc_status of this instance once done
     int32_t done;      // nonzero: every kernel skips this instance
     int32_t maxit;
-    int32_t counter;   // blocks arrived at the current reduction (last one finalises)
-    int32_t pad;
 };
 
-// reduction kinds finalised by the last block of a kernel
+// reduction kinds, applied per instance by the finalize kernel after a reduction
 enum Finalize : int32_t {
     FIN_NONE = 0,
     FIN_SSF = 1,        // ssf = sum; relres0 bookkeeping reset

@@ -14,11 +14,13 @@
 // bilinear prolongation gathers the one, two or four coarse neighbours south
 // to north, west to east, and scales the sum by 1/2 or 1/4.
 //
-// Grid-wide kernels work on 64 x 32 tiles of one level of every instance in a
-// batch (blockIdx -> instance by a prefix table).  Reductions are
-// deterministic: one partial per block, summed in a fixed order by the last
-// block of the instance to arrive, which also applies the solver's decision
-// (stop test, CG scalars) to the instance's state.
+// Grid-wide kernels work on tiles (8 x 8 to 64 x 32) or row strips of one
+// level of every instance in a batch (blockIdx -> instance by a prefix table).
+// Reductions are deterministic: one partial per block, summed in a fixed order
+// by a finalize kernel (one workgroup per instance), which also applies the
+// solver's decision (stop test, CG scalars) to the instance's state.  Calls
+// below a cutover level run in a persistent kernel, one workgroup per instance
+// with the levels in LDS.
 #include <math.h>
 
 #include <type_traits>
@@ -472,7 +474,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// zebra line relaxation (paper-structured mode): every line of the launch's
+// zebra line relaxation on the levels run one kernel per operation: every line of the launch's
 // colour (lines 2 m + colour) solves its tridiagonal system exactly with its
 // neighbouring lines' current values, in place.  Forward pass:
 // d_q = F_q - (six off-line products: line j-1 then j+1, west to east, for

@@ -38,7 +38,7 @@ class Problem(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_coarsest", C.c_int32), ("theta", C.c_double), ("eps", C.c_double)]
 
 
-SMOOTHERS = {"jacobi": 0, "zebra": 1}   # damped Jacobi; alternating zebra line Gauss-Seidel (paper mode only)
+SMOOTHERS = {"jacobi": 0, "zebra": 1}   # damped Jacobi; alternating zebra line Gauss-Seidel
 
 
 class CycleParams(C.Structure):
@@ -164,11 +164,13 @@ def level_stencils(n: int, theta: float, eps: float, n_coarsest: int = 1) -> np.
     return buf[: 9 * nl.value].reshape(nl.value, 3, 3).copy()
 
 
-def schedule_counts(problems, kappa: int, nu1: int = 2, nu2: int = 2, omega: float = 0.8, **exec_kw) -> dict:
+def schedule_counts(problems, kappa: int, nu1: int = 2, nu2: int = 2, omega: float = 0.8, smoother: str = "jacobi",
+                    **exec_kw) -> dict:
     """Launches per cycle of the flattened schedule (host computation, no GPU)."""
     arr, n = _problems(problems)
     e = exec_options(**exec_kw)
-    c = CycleParams(int(kappa), int(nu1), int(nu2), 0, float(omega))
+    sm = SMOOTHERS[smoother] if isinstance(smoother, str) else int(smoother)
+    c = CycleParams(int(kappa), int(nu1), int(nu2), sm, float(omega))
     g, s, st = C.c_int64(), C.c_int64(), C.c_int64()
     _check(lib().kc_schedule_counts(arr, n, C.byref(e), C.byref(c), C.byref(g), C.byref(s), C.byref(st)))
     return {"grid_launches": g.value, "subtree_launches": s.value, "subtree_stages": st.value}

@@ -96,6 +96,37 @@ def test_fused_mode_launch_count(L, cutover):
         assert c["subtree_launches"] == subs
 
 
+@pytest.mark.parametrize("L,nu", [(6, (2, 2)), (9, (1, 1)), (12, (2, 0))])
+def test_zebra_paper_mode_launch_count(L, nu):
+    """Zebra relaxation, one launch per operation: a relaxation is two launches
+    (one per colour) and relaxes in place, so a non-coarsest call costs
+    5 + 2 (nu1 + nu2) launches and no final copy is needed."""
+    n = 2 ** L - 1
+    for kappa in (1, 2, 3, 4, K.KAPPA_W):
+        c = K.schedule_counts([(n, 0.4, 1e-3)], kappa, nu[0], nu[1], smoother="zebra", mode="paper")
+        assert c["grid_launches"] == M.n_gpu_calls_paper(kappa, L, 2 * (nu[0] + nu[1]))
+        assert c["subtree_launches"] == 0
+
+
+@pytest.mark.parametrize("L,cutover", [(10, 63), (12, 31), (6, 63), (8, 15), (5, 31)])
+def test_zebra_fused_mode_launch_count(L, cutover):
+    """Zebra relaxation in the fused mode: one launch per operation for every
+    call above the cutover depth, one persistent launch per call at the depth
+    above it (or one for the whole cycle when the fine grid is below the
+    cutover), and the persistent op lists hold no register calls."""
+    n = 2 ** L - 1
+    sizes = [2 ** (L - d) - 1 for d in range(L)]
+    cut = next(d for d, s in enumerate(sizes) if s <= cutover)
+    for kappa in (1, 2, 3, 4, K.KAPPA_W):
+        kk = min(kappa, 10 ** 6)
+        c = K.schedule_counts([(n, 0.4, 1e-3)], kappa, 2, 2, smoother="zebra", coarse_cutover=cutover)
+        assert c["grid_launches"] == (5 + 2 * 4) * sum(M.level_calls(kk, d + 1) for d in range(cut))
+        assert c["subtree_launches"] == (M.level_calls(kk, cut) if cut > 0 else 1)
+        j = K.schedule_counts([(n, 0.4, 1e-3)], kappa, 2, 2, coarse_cutover=cutover)
+        assert j["subtree_launches"] == c["subtree_launches"]
+        assert c["subtree_stages"] >= j["subtree_stages"]
+
+
 def _grid_sequence(sizes, cut, kappa):
     """Grid-wide launches of one fused cycle, in order: ('pre' | 'post', depth, zero_guess),
     written from Algorithm 3's call structure (the persistent launches are left out)."""
