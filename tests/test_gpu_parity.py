@@ -811,6 +811,28 @@ def test_degenerate_sizes(n, nc, mode):
     H32.close()
 
 
+@pytest.mark.parametrize("n,nc,mode", [(1, 1, "fused"), (3, 1, "fused"), (3, 1, "paper"), (7, 7, "fused"),
+                                       (7, 3, "paper"), (15, 1, "fused"), (15, 3, "paper")])
+def test_zebra_degenerate_sizes(n, nc, mode):
+    """Zebra relaxation on one-point problems, single coarse levels and
+    problems below the cutover: the oracle's iterations and bits (FP64)."""
+    banner(f"zebra degenerate size n={n} nc={nc} mode={mode}")
+    th, ep = 1.1, 1e-3
+    f = np.random.default_rng(5 * n + nc).uniform(-1, 1, (n, n))
+    Ho = O.Hierarchy(n, th, ep, n_coarsest=nc, smoother="zebra")
+    u_ref, rc, it_ref, hist = Ho.solve(f, kappa=2, tol=1e-10, maxit=200)
+    assert rc == O.OK
+    check_stop_margin(hist, 1e-10)
+    H = K().Hierarchy([(n, th, ep, nc)], "f64", exec=dict(mode=mode))
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    it, rr, st = H.solve(u, dev(f), kappa=2, tol=1e-10, maxit=200, smoother="zebra")
+    assert st == [0] and it[0] == it_ref and np.array_equal(host(u), u_ref)
+    u.zero_()
+    it, rr, st = H.solve(u, dev(np.zeros((n, n))), kappa=2, tol=1e-10, maxit=200, smoother="zebra")
+    assert st == [0] and it[0] == 0 and not host(u).any()   # f = 0: stops before the first cycle
+    H.close()
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_zero_right_hand_side(prec):
     """f = 0: the solvers stop before the first cycle with u = 0."""
