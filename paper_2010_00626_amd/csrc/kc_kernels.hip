@@ -490,16 +490,17 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a)
 //   r; or the line's own y values and u) is issued before the chunk's stores,
 //   the neighbouring lines' values at q - 1, q, q + 1 slide through
 //   registers, and the chunk's d_q are formed before the recurrence.
-// * waves (levels at or above the threshold): one wave per line, four lines
-//   per workgroup.  Lane l holds point q0 + l of a chunk of 64: the lanes
-//   form the chunk's d_q (and load r) in parallel and put them in the wave's
-//   LDS slots; the recurrence runs over the chunk wave-uniformly (unrolled,
-//   one broadcast LDS read per step, so the vector ALU issues only the
-//   recurrence's own operations), lane 0 writes the results out and each
-//   lane stores its own point; the next chunk's loads are issued before the
-//   recurrence, so they are in flight while it runs.  A level's
-//   n / 2 lines give n / 2 waves, against n / 128 for the lane mapping,
-//   which is what large levels need to keep memory busy.  The backward pass
+// * waves (levels at or above the threshold): two lines per wave (lanes 0-31
+//   and 32-63), eight per workgroup.  Lane l holds point q0 + (l mod 32) of a
+//   chunk of 32 points of its line: the lanes form the chunk's d_q (and load
+//   r) in parallel and put them in the wave's LDS slots; lanes 0 and 32 alone
+//   run the two recurrences over the chunk (unrolled, one LDS read per step,
+//   so the vector ALU issues only the recurrences' own operations, each
+//   advancing both lines, and the LDS returns 2 x 16 bytes per step), write
+//   the results back to LDS, and each lane stores its own point; the next
+//   chunk's loads are issued before the recurrences, so they are in flight
+//   while they run.  A level's n / 2 lines give n / 4 waves, against n / 128
+//   for the lane mapping, which is what large levels need to keep memory busy.  The backward pass
 //   reads each point's y back in the lane that wrote it.
 // ---------------------------------------------------------------------------
 template <typename T> struct ZT;
@@ -626,29 +627,36 @@ struct ZFwd {
     }
 };
 
-// a wave's LDS slots for one chunk: the lanes' (d_q, r_q) or (y_q, u_q) pairs,
-// read back one per step at a wave-uniform address (a broadcast read, on the
-// LDS pipe rather than the vector ALU), and the chunk's results, written by lane 0
+// a wave's LDS slots for one chunk of each of its two lines: the lanes' (d_q, r_q)
+// or (y_q, u_q) pairs, read back one per step by the lane running that line's
+// recurrence, and the chunk's results, written by that lane and read by every
+// lane of the line
+constexpr int ZC = 32;   // points per chunk and line (two lines per wave)
 template <typename T>
 struct ZSlots {
-    T pair[64][2];
-    T res[64];
+    T pair[2][ZC][2];
+    T res[2][ZC];
 };
 
 template <typename T, int DIR>
 __device__ __forceinline__ void zebra_wave(const ZLine<T, DIR>& z, ZSlots<T>& sl)
 {
-    constexpr int SB = 8;   // steps per block: pairs read a block ahead, results written out by lane 0 per block
-    const int n = z.n, lane = threadIdx.x & 63;
+    constexpr int SB = 8;   // steps per block: the block's pairs are read one block ahead
+    const int n = z.n, lane = threadIdx.x & 63, h = lane >> 5, p = lane & (ZC - 1);
+    const bool runner = p == 0;   // lanes 0 and 32 run the recurrences of the two lines
     ZFwd<T> cur;
-    cur.load(z, lane);
+    cur.load(z, p);
     T prev = T(0);
-    for (int q0 = 0; q0 < n; q0 += 64) {
-        sl.pair[lane][0] = cur.dq(z);
-        sl.pair[lane][1] = cur.r;
+    // one chunk of the forward pass.  Every chunk issues the same memory operations (the next
+    // chunk's loads, clamped past the line's end, then one store), and the first chunk runs
+    // before the loop: the loop is then entered, like its back edge, with one store behind
+    // the loads, so the wait for them need not cover that store
+    auto fwd = [&](int q0) {
+        sl.pair[h][p][0] = cur.dq(z);
+        sl.pair[h][p][1] = cur.r;
         wave_sync();
-        if (q0 + 64 < n) cur.load(z, q0 + 64 + lane);   // in flight during the recurrence
-        const int cnt = min(64, n - q0);
+        cur.load(z, q0 + ZC + p);   // in flight during the recurrence
+        const int cnt = min(ZC, n - q0);
         const bool first = q0 == 0;
         // a full chunk keeps every step; in the last one, steps past the line's end
         // (k >= cnt) compute values that are neither kept nor stored
@@ -656,34 +664,29 @@ __device__ __forceinline__ void zebra_wave(const ZLine<T, DIR>& z, ZSlots<T>& sl
             T dk[SB], rk[SB];   // the block's pairs, read one block ahead of the recurrence
 #pragma unroll
             for (int j = 0; j < SB; ++j) {
-                dk[j] = sl.pair[j][0];
-                rk[j] = sl.pair[j][1];
+                dk[j] = sl.pair[h][j][0];
+                rk[j] = sl.pair[h][j][1];
             }
 #pragma unroll
-            for (int kb = 0; kb < 64; kb += SB) {
+            for (int kb = 0; kb < ZC; kb += SB) {
                 T dn[SB], rn[SB];
-                if (kb + SB < 64) {
+                if (kb + SB < ZC) {
 #pragma unroll
                     for (int j = 0; j < SB; ++j) {
-                        dn[j] = sl.pair[kb + SB + j][0];
-                        rn[j] = sl.pair[kb + SB + j][1];
+                        dn[j] = sl.pair[h][kb + SB + j][0];
+                        rn[j] = sl.pair[h][kb + SB + j][1];
                     }
                 }
-                T yb[SB];
 #pragma unroll
                 for (int j = 0; j < SB; ++j) {
                     const int k = kb + j;
                     const T t = (k == 0 && first) ? dk[j] : dk[j] - z.lo * prev;   // y_0 = d_0 r_0
                     const T y = t * rk[j];
-                    yb[j] = y;
+                    sl.res[h][k] = y;
                     if constexpr (decltype(partial)::value) prev = (k < cnt) ? y : prev;
                     else prev = y;
                 }
-                if (lane == 0) {
-#pragma unroll
-                    for (int j = 0; j < SB; ++j) sl.res[kb + j] = yb[j];
-                }
-                if (kb + SB < 64) {
+                if (kb + SB < ZC) {
 #pragma unroll
                     for (int j = 0; j < SB; ++j) {
                         dk[j] = dn[j];
@@ -692,61 +695,67 @@ __device__ __forceinline__ void zebra_wave(const ZLine<T, DIR>& z, ZSlots<T>& sl
                 }
             }
         };
-        if (cnt == 64) steps(std::false_type{});
-        else steps(std::true_type{});
+        // two lanes run the recurrences: each instruction advances both lines, and the LDS
+        // returns 2 x 16 bytes per step
+        if (runner) {
+            if (cnt == ZC) steps(std::false_type{});
+            else steps(std::true_type{});
+        }
         wave_sync();
-        if (lane < cnt) z.V[z.vi(z.line, q0 + lane)] = sl.res[lane];
+        {   // lanes past the line's end store the last point's value again (same value, same address)
+            const int k = min(p, cnt - 1);
+            z.V[z.vi(z.line, q0 + k)] = sl.res[h][k];
+        }
         wave_sync();   // the slots are rewritten by the next chunk
-    }
-    // backward, chunks from the last one down; lane l owns the point it wrote above
-    const int c_last = (n - 1) >> 6;
-    T next = prev;   // x_{n-1} = y_{n-1}
+    };
+    fwd(0);
+    for (int q0 = ZC; q0 < n; q0 += ZC) fwd(q0);
+
+    // backward, chunks from the last one down; a lane owns the points it wrote above
+    const int c_last = (n - 1) / ZC;
+    const T ylast = __shfl(prev, lane & ZC, 64);   // y_{n-1}, kept by the line's runner lane
+    T next = prev;   // x_{n-1} = y_{n-1} (runner lanes)
     T yv, uv;
     {
-        const int q = min((c_last << 6) + lane, n - 1);
+        const int q = min(c_last * ZC + p, n - 1);
         yv = z.V[z.vi(z.line, q)];
         uv = z.mul[q];
     }
-    for (int c = c_last; c >= 0; --c) {
-        const int q0 = c << 6;
-        sl.pair[lane][0] = yv;
-        sl.pair[lane][1] = uv;
+    auto bwd = [&](int c) {
+        const int q0 = c * ZC;
+        sl.pair[h][p][0] = yv;
+        sl.pair[h][p][1] = uv;
         wave_sync();
-        if (c > 0) {   // in flight during the recurrence
-            const int q = q0 - 64 + lane;
+        {   // in flight during the recurrence (every chunk issues it; clamped before the line's start)
+            const int q = max(q0 - ZC + p, 0);
             yv = z.V[z.vi(z.line, q)];
             uv = z.mul[q];
         }
-        const int top = min(63, n - 2 - q0);   // x_{n-1} = y_{n-1} is already in place
+        const int top = min(ZC - 1, n - 2 - q0);   // x_{n-1} = y_{n-1} is already in place
         auto steps = [&](auto partial) {
             T yk[SB], uk[SB];   // the block's pairs, read one block ahead of the recurrence
 #pragma unroll
             for (int j = 0; j < SB; ++j) {
-                yk[j] = sl.pair[64 - SB + j][0];
-                uk[j] = sl.pair[64 - SB + j][1];
+                yk[j] = sl.pair[h][ZC - SB + j][0];
+                uk[j] = sl.pair[h][ZC - SB + j][1];
             }
 #pragma unroll
-            for (int kb = 64 - SB; kb >= 0; kb -= SB) {
+            for (int kb = ZC - SB; kb >= 0; kb -= SB) {
                 T yn[SB], un[SB];
                 if (kb > 0) {
 #pragma unroll
                     for (int j = 0; j < SB; ++j) {
-                        yn[j] = sl.pair[kb - SB + j][0];
-                        un[j] = sl.pair[kb - SB + j][1];
+                        yn[j] = sl.pair[h][kb - SB + j][0];
+                        un[j] = sl.pair[h][kb - SB + j][1];
                     }
                 }
-                T xb[SB];
 #pragma unroll
                 for (int j = SB - 1; j >= 0; --j) {
                     const int k = kb + j;
                     const T x = yk[j] - uk[j] * next;
-                    xb[j] = x;
+                    sl.res[h][k] = x;
                     if constexpr (decltype(partial)::value) next = (k <= top) ? x : next;
                     else next = x;
-                }
-                if (lane == 0) {
-#pragma unroll
-                    for (int j = 0; j < SB; ++j) sl.res[kb + j] = xb[j];
                 }
                 if (kb > 0) {
 #pragma unroll
@@ -757,12 +766,21 @@ __device__ __forceinline__ void zebra_wave(const ZLine<T, DIR>& z, ZSlots<T>& sl
                 }
             }
         };
-        if (top == 63) steps(std::false_type{});
-        else steps(std::true_type{});
+        if (runner) {
+            if (top == ZC - 1) steps(std::false_type{});
+            else steps(std::true_type{});
+        }
         wave_sync();
-        if (lane <= top) z.V[z.vi(z.line, q0 + lane)] = sl.res[lane];
+        {   // lanes past top store the value at top again; with top = -1 (a chunk holding only
+            // the line's last point) every lane stores y_{n-1} back in place
+            const int k = min(p, max(top, 0));
+            const T xv = top >= 0 ? sl.res[h][k] : ylast;
+            z.V[z.vi(z.line, q0 + k)] = xv;
+        }
         wave_sync();
-    }
+    };
+    bwd(c_last);
+    for (int c = c_last - 1; c >= 0; --c) bwd(c);
 }
 
 template <typename T, int DIR>
@@ -786,12 +804,17 @@ __global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
         // eight XCDs), so y-lines sharing cache lines share an L2
         const int nb = a.tile_off[inst + 1] - a.tile_off[inst];
         if ((a.tile_off[inst] & 7) == 0 && (nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
-        line = 2 * (blk * (GRID_THREADS / 64) + (int)(threadIdx.x >> 6)) + a.dst;
+        // two lines per wave, lanes 0-31 and 32-63; a second line past the level's last one
+        // repeats the first (the same values go to the same addresses twice)
+        const int first = 2 * (blk * (GRID_THREADS / 32) + 2 * (int)(threadIdx.x >> 6)) + a.dst;
+        if (first >= n) return;   // the whole wave
+        line = first + 2 * (int)((threadIdx.x >> 5) & 1);
+        if (line >= n) line = first;
     } else {
         if (threadIdx.x >= 64) return;
         line = 2 * (blk * 64 + (int)threadIdx.x) + a.dst;
     }
-    if (line >= n) return;   // whole waves in the wave mapping
+    if (line >= n) return;
     ZLine<T, DIR> z;
     z.V = glob<T>(buf<T>(Lv, a.src));
     z.ldv = a.src ? Lv.ldb : Lv.lda;   // element offsets fit 32 bits (n <= 2^14)

@@ -187,12 +187,12 @@ int tiles_of(int n) { return ((n + TX - 1) / TX) * ((n + TY - 1) / TY); }
 int tiles_small(int n) { return ((n + TS - 1) / TS) * ((n + TS - 1) / TS); }
 int tiles_mid(int n) { return ((n + TM - 1) / TM) * ((n + TM - 1) / TM); }
 int tiles_tiny(int n) { return ((n + TT - 1) / TT) * ((n + TT - 1) / TT); }
-// zebra launches: the lines of one colour ((n + 1) / 2 at most), one wave each (four per
-// workgroup) on levels with n >= wave_n > 0, else one thread each (64 per workgroup)
+// zebra launches: the lines of one colour ((n + 1) / 2 at most), two per wave (eight per
+// workgroup) on levels with n >= wave_n > 0, else one per thread (64 per workgroup)
 int zebra_blocks(int n, int wave_n)
 {
     const int lines = (n + 1) / 2;
-    return (wave_n > 0 && n >= wave_n) ? (lines + GRID_THREADS / 64 - 1) / (GRID_THREADS / 64) : (lines + 63) / 64;
+    return (wave_n > 0 && n >= wave_n) ? (lines + GRID_THREADS / 32 - 1) / (GRID_THREADS / 32) : (lines + 63) / 64;
 }
 // streaming blocks: STRIP_BLOCK_W columns x R rows, R = 16 << code
 int strip_rows_code(int n) { return n >= 4095 ? 2 : (n >= 2047 ? 1 : 0); }
