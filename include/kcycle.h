@@ -117,9 +117,9 @@ typedef struct {
     int32_t tiny_tile_n;    /* fused grid kernels on levels whose largest n <= this use 8 x 8 tiles (one point per
                                thread and phase; takes precedence over small_tile_n; 0 = never; 0..4095; default 255);
                                results do not depend on it */
-    int32_t zebra_wave_n;   /* zebra line relaxation on levels with n >= this solves each line with one wave (64 points
-                               per step, many lines in flight); smaller levels use one thread per line (0 = never;
-                               0..16383; default 63); results do not depend on it */
+    int32_t zebra_wave_n;   /* zebra line relaxation on levels with n >= this solves each line with half a wave (two
+                               lines per wave, 32 points per chunk, many lines in flight); smaller levels use one
+                               thread per line (0 = never; 0..16383; default 63); results do not depend on it */
 } kc_exec;
 
 typedef struct kc_hier kc_hier;

@@ -522,7 +522,7 @@ void gen_paper(kc_hier* h, int d, int k, const kc_cycle_params& c, bool f32, int
                 L.sa.src = cur[d];
                 L.sa.dst = color;
                 L.sa.nu = r & 1;
-                L.sa.flags = h->ex.zebra_wave_n;   // per instance: one wave per line at n >= this
+                L.sa.flags = h->ex.zebra_wave_n;   // per instance: two lines per wave at n >= this
                 out.push_back(L);
             }
         } else {

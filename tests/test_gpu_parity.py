@@ -667,7 +667,7 @@ ZEBRA_WAVE_CASES = [(63, 2, 1, 1), (127, 2 ** 31 - 1, 1, 1), (255, 3, 3, 127), (
 
 @pytest.mark.parametrize("n,kappa,nc,wave_n", ZEBRA_WAVE_CASES)
 def test_zebra_line_mappings_bitwise(n, kappa, nc, wave_n):
-    """Both line mappings of the zebra kernel (one wave per line on levels
+    """Both line mappings of the zebra kernel (two lines per wave on levels
     with n >= zebra_wave_n, one thread per line below; 0 = threads only),
     with chunk tails of every kind, give the oracle's bits."""
     banner(f"zebra mappings n={n} kappa={kappa} n_coarsest={nc} zebra_wave_n={wave_n}")
