@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--exec", default="", help="JSON execution options for the headline configuration "
                     "(instead of the autotuned ones)")
     ap.add_argument("--extras", default="c4,c3,c5,hbm,zebra",
-                    help="extra measurements: c4 (batched uneven), c3 (PCG 4095^2), c5 (adjoint), hbm (8191^2 kernel), "
+                    help="extra measurements: c4 (batched uneven), c3 (PCG 4095^2), c5 (adjoint), hbm (8191^2 and 16383^2 kernels), "
                          "zebra (the 1023^2 problem with alternating zebra line relaxation)")
     return ap.parse_args()
 
@@ -234,7 +234,7 @@ def main():
     del H, u64
     torch.cuda.empty_cache()
     if "hbm" in ex:
-        extras["fine_kernel_8191"] = hbm_kernel(kcycle, torch)
+        extras["fine_kernels_hbm"] = hbm_kernel(kcycle, torch)
     if "c4" in ex:
         extras["c4_batched"] = c4_batched(inputs, kcycle, autotune, torch)
     if "c3" in ex:
@@ -266,21 +266,29 @@ def main():
 
 
 def hbm_kernel(kcycle, torch):
-    """Fine-level fused kernels on an 8191^2 FP64 grid (537 MB per array, far
-    beyond the 256 MB Infinity Cache): achieved HBM bandwidth of one launch."""
-    n = 8191
-    Hh = kcycle.Hierarchy([(n, math.pi / 4, 1e-4)], "f64")
-    fh = torch.zeros((n, n), dtype=torch.float64, device="cuda").uniform_(-1, 1)
-    uh = torch.zeros_like(fh)
-    Hh.solve(uh, fh, kappa=1, tol=0.0, maxit=1)      # binds the arrays
+    """Fine-level fused kernels on 8191^2 and 16383^2 FP64 grids (537 MB and 2.1 GB per
+    array, far beyond the 256 MB Infinity Cache): achieved HBM bandwidth of one launch,
+    for the benchmark's nu = 2 (pre, post) and per nu = 0, 1, 2 (by_nu: the pre-part is
+    residual + full weighting after nu sweeps, the post-part prolong-add before nu sweeps)."""
     res = {}
-    for name, which in (("pre", 0), ("post", 1)):
-        ms, b = Hh.time_stage(which, kappa=1, reps=20)
-        res[name] = {"ms": round(ms, 4), "bytes": b, "GB_s": round(b / (ms * 1e-3) / 1e9, 1),
-                     "frac_of_8TBs": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    Hh.close()
-    del Hh, fh, uh
-    torch.cuda.empty_cache()
+    for n in (8191, 16383):
+        Hh = kcycle.Hierarchy([(n, math.pi / 4, 1e-4)], "f64")
+        fh = torch.zeros((n, n), dtype=torch.float64, device="cuda").uniform_(-1, 1)
+        uh = torch.zeros_like(fh)
+        Hh.solve(uh, fh, kappa=1, tol=0.0, maxit=1)      # binds the arrays
+        by_nu = {}
+        for nu in (0, 1, 2):
+            for name, which in (("pre", 0), ("post", 1)):
+                ms, b = Hh.time_stage(which, kappa=1, nu1=nu, nu2=nu, reps=20)
+                gbs = b / (ms * 1e-3) / 1e9
+                entry = {"ms": round(ms, 4), "bytes": b, "GB_s": round(gbs, 1), "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4)}
+                by_nu[f"{name}_nu{nu}"] = entry
+                if n == 8191 and nu == 2:
+                    res[name] = entry
+        res[f"by_nu_{n}"] = by_nu
+        Hh.close()
+        del Hh, fh, uh
+        torch.cuda.empty_cache()
     return res
 
 
