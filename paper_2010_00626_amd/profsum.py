@@ -6,7 +6,11 @@ same name, so a per-name average mixes levels; this summary groups the
 dispatches by (kernel name, grid size) as well, which separates the levels
 (the grid of a fused grid kernel is tiles x 256 work-items).
 
-Usage: python -m paper_2010_00626_amd.profsum <rocprofv3 output dir> [--top 25] [--match SUBSTR]
+With --counters it summarises a rocprofv3 --pmc run instead (counter_collection.csv):
+the mean of every counter per (kernel name, grid size), over the dispatches whose
+name contains --match.
+
+Usage: python -m paper_2010_00626_amd.profsum <rocprofv3 output dir> [--top 25] [--match SUBSTR] [--counters]
 """
 from __future__ import annotations
 
@@ -60,13 +64,41 @@ def summarise(root: str, top: int = 25, match: str | None = None) -> str:
     return "\n".join(out) + "\n"
 
 
+def summarise_counters(root: str, match: str | None = None) -> str:
+    files = sorted(glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True))
+    if not files:
+        raise SystemExit(f"no *counter_collection.csv under {root}")
+    vals = defaultdict(lambda: defaultdict(list))
+    names = []
+    for path in files:
+        for r in _rows(path):
+            kern = r.get("Kernel_Name", "?")
+            if match and match not in kern:
+                continue
+            grid = int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0)
+            c = r["Counter_Name"]
+            if c not in names:
+                names.append(c)
+            vals[(kern, grid)][c].append(float(r["Counter_Value"]))
+    out = [f"{'kernel':44s} {'grid':>9s} {'dispatches':>10s} " + " ".join(f"{c:>16s}" for c in names)]
+    for (kern, grid), d in sorted(vals.items()):
+        n = max(len(v) for v in d.values())
+        cells = " ".join(f"{sum(d[c]) / len(d[c]):16.1f}" if d.get(c) else f"{'-':>16s}" for c in names)
+        out.append(f"{_short(kern, 44):44s} {grid:9d} {n:10d} {cells}")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("root")
     ap.add_argument("--top", type=int, default=25)
     ap.add_argument("--match", default=None)
+    ap.add_argument("--counters", action="store_true", help="summarise a --pmc run (mean per kernel and grid)")
     a = ap.parse_args(argv)
-    sys.stdout.write(summarise(a.root, a.top, a.match))
+    if a.counters:
+        sys.stdout.write(summarise_counters(a.root, a.match))
+    else:
+        sys.stdout.write(summarise(a.root, a.top, a.match))
 
 
 if __name__ == "__main__":

@@ -166,3 +166,30 @@ def test_junction_fusion_launch_count(L, cutover, small, tiny):
         assert c1["grid_launches"] == len(seq) - fused
         if kappa > 1 and any(sizes[e] <= max(small, tiny) for e in range(1, cut)):
             assert fused > 0
+
+
+def test_profsum_summaries(tmp_path):
+    """The profile summaries group dispatches by kernel and grid size: mean
+    durations from a kernel trace, mean counter values from a --pmc run."""
+    from paper_2010_00626_amd import profsum
+    (tmp_path / "t").mkdir()
+    with open(tmp_path / "t" / "x_kernel_trace.csv", "w") as fh:
+        fh.write("Kernel_Name,Start_Timestamp,End_Timestamp,Grid_Size_X,Grid_Size_Y,Grid_Size_Z\n")
+        fh.write("void kc::k_a<float>(kc::StageArgs),0,2000,256,1,1\n")
+        fh.write("void kc::k_a<float>(kc::StageArgs),5000,9000,256,1,1\n")
+        fh.write("void kc::k_a<float>(kc::StageArgs),0,1000,512,1,1\n")
+    out = profsum.summarise(str(tmp_path / "t"))
+    assert "# dispatches: 3, kernel time 0.007 ms" in out
+    line = [l for l in out.splitlines() if "k_a<float>" in l and " 256 " in l][0].split()
+    assert line[-6:] == ["256", "2", "0.006", "3.00", "2.00", "4.00"]
+    (tmp_path / "c").mkdir()
+    with open(tmp_path / "c" / "x_counter_collection.csv", "w") as fh:
+        fh.write("Kernel_Name,Grid_Size,Counter_Name,Counter_Value\n")
+        for v in (10.0, 30.0):
+            fh.write(f"void kc::k_b<double>(kc::StageArgs),1024,VALUBusy,{v}\n")
+        fh.write("void kc::k_b<double>(kc::StageArgs),1024,SQ_WAVES,16\n")
+        fh.write("void kc::k_c(kc::StageArgs),64,VALUBusy,99\n")
+    out = profsum.summarise_counters(str(tmp_path / "c"), match="k_b")
+    rows = out.splitlines()
+    assert rows[0].split()[-2:] == ["VALUBusy", "SQ_WAVES"] and len(rows) == 2
+    assert rows[1].split()[-4:] == ["1024", "2", "20.0", "16.0"]
