@@ -417,9 +417,9 @@ def c3_pcg(inputs, kcycle, torch):
 def zebra_c2(inputs, kcycle, torch):
     """The 1023^2 workload with alternating zebra line Gauss-Seidel (FP64, nu = 2 + 2:
     one x- and one y-relaxation on each side), per kappa, to the same 1e-8 relative
-    residual: in the fused mode (levels above the cutover one kernel per operation,
-    every call at the cutover in one persistent launch) and in the paper-structured
-    mode (one kernel per operation on every level)."""
+    residual: in the fused mode (levels above 63^2 one kernel per operation, every
+    call at 63^2 in one persistent launch) and in the paper-structured mode (one
+    kernel per operation on every level)."""
     w = inputs.config2()
     inst = w.instances[0]
     n = inst.n
@@ -427,7 +427,9 @@ def zebra_c2(inputs, kcycle, torch):
     u = torch.zeros_like(f)
     out = {}
     for mode in ("fused", "paper"):
-        H = kcycle.Hierarchy([(n, inst.theta, inst.eps, w.n_coarsest)], "f64", exec=dict(mode=mode))
+        # fused: calls at 63^2 and below in the persistent kernel (the line solves of 63^2 fit its LDS)
+        ex = dict(mode=mode, coarse_cutover=63) if mode == "fused" else dict(mode=mode)
+        H = kcycle.Hierarchy([(n, inst.theta, inst.eps, w.n_coarsest)], "f64", exec=ex)
         res = {}
         for k in (1, 2, 3, 4, kcycle.KAPPA_W):
             u.zero_()
