@@ -193,3 +193,17 @@ def test_profsum_summaries(tmp_path):
     rows = out.splitlines()
     assert rows[0].split()[-2:] == ["VALUBusy", "SQ_WAVES"] and len(rows) == 2
     assert rows[1].split()[-4:] == ["1024", "2", "20.0", "16.0"]
+
+
+def test_exec_options_validated_without_gpu():
+    """Execution options out of range are rejected by the host planner (the
+    same check kc_create and kc_set_exec run), and the smoother must be 0 or 1."""
+    ok = K.schedule_counts([(255, 0.4, 1e-3)], 2, smoother="zebra", zebra_wave_n=0)
+    assert ok["grid_launches"] > 0
+    for bad in (dict(zebra_wave_n=-1), dict(zebra_wave_n=16384), dict(coarse_threads=384),
+                dict(tiny_tile_n=4096), dict(wave_regs=2)):
+        with pytest.raises(K.KCycleError) as ei:
+            K.schedule_counts([(255, 0.4, 1e-3)], 2, **bad)
+        assert ei.value.status == K.KC_ERR_ARG, bad
+    with pytest.raises(K.KCycleError):
+        K.schedule_counts([(255, 0.4, 1e-3)], 2, smoother=2)
