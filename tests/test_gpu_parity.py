@@ -811,6 +811,30 @@ def test_degenerate_sizes(n, nc, mode):
     H32.close()
 
 
+def test_zebra_fused_batched_fp32_refinement():
+    """A ragged batch with FP32 zebra cycles and FP64 refinement in the fused
+    mode (calls at 63^2 in the persistent kernel): every instance reaches the
+    tolerance on its true FP64 residual within one cycle of the oracle's FP32
+    emulation, including a grid-aligned instance that damped Jacobi barely
+    reduces."""
+    banner("zebra fused batched FP32 refinement")
+    specs = [(511, 0.02, 1e-4), (255, 1.9, 1e-3), (127, 0.7, 1e-5), (1023, 3.1, 3e-5)]
+    rng = np.random.default_rng(33)
+    fs = [inputs.uniform_rhs(rng, s[0]) for s in specs]
+    H = K().Hierarchy(specs, "f32", exec=dict(coarse_cutover=63))
+    us = [torch.zeros((s[0], s[0]), dtype=torch.float64, device="cuda") for s in specs]
+    iters, relres, status = H.solve(us, [dev(f) for f in fs], kappa=3, tol=1e-8, maxit=300, smoother="zebra")
+    assert status == [0] * len(specs)
+    for k, (s, f) in enumerate(zip(specs, fs)):
+        Ho = O.Hierarchy(*s, smoother="zebra")
+        u_ir, rc, it_ir, _ = Ho.ir_solve(f, kappa=3, tol=1e-8, maxit=300)
+        assert rc == O.OK and abs(iters[k] - it_ir) <= 1, (k, iters[k], it_ir)
+        got = host(us[k])
+        assert np.linalg.norm(f - Ho.apply(got)) / np.linalg.norm(f) < 1e-8, k
+        assert relmax(got, u_ir) <= 1e-6, k
+    H.close()
+
+
 @pytest.mark.parametrize("n,nc,mode", [(1, 1, "fused"), (3, 1, "fused"), (3, 1, "paper"), (7, 7, "fused"),
                                        (7, 3, "paper"), (15, 1, "fused"), (15, 3, "paper")])
 def test_zebra_degenerate_sizes(n, nc, mode):
