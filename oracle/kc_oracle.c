@@ -6,8 +6,10 @@
  * multigrid cycles").  Only the tests, the smoke check and the benchmark's
  * CPU-baseline leg may load it.  It shares no code with the GPU library.
  *
- * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared (no fused
- * multiply-add anywhere: every product and sum is rounded on its own).
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared (no contracted
+ * multiply-add: every product and sum is rounded on its own; the one fused
+ * multiply-add is the explicit fma() that extracts a product's exact rounding
+ * error in the norms and dot products).
  *
  * What each part follows:
  *   - fine operator: the nine-point stencil table of Section 4;
@@ -240,6 +242,15 @@ void or_zebra_relax(or_hier* h, int dir, double* v, const double* f)
     h->d.f[0] = NULL;
 }
 
+int or_zebra_tables(const or_hier* h, int level, int dir, double* rp, double* um)
+{
+    if (level < 1 || level > h->d.L || (dir != 0 && dir != 1)) return OR_ERR_ARG;
+    const int k = level - 1;
+    memcpy(rp, h->d.zp[k][dir], sizeof(double) * (size_t)h->d.n[k]);
+    memcpy(um, h->d.zu[k][dir], sizeof(double) * (size_t)h->d.n[k]);
+    return OR_OK;
+}
+
 /* ------------------------------------------------------------------ */
 /* cycles                                                               */
 /* ------------------------------------------------------------------ */
@@ -271,19 +282,45 @@ void or_kcycle_f32(or_hier* h, int kappa, int nu1, int nu2, float* v, const floa
 /* drivers                                                              */
 /* ------------------------------------------------------------------ */
 
-static double sumsq(const double* x, size_t m)
+/* Norms and dot products: Dot2 of Ogita, Rump and Oishi ("Accurate sum and
+ * dot product", SIAM J. Sci. Comput. 26, 2005, Algorithm 5.3).  Every product
+ * is split into its rounded value and its exact rounding error (TwoProduct,
+ * with an explicit fused multiply-add), the running sum is split likewise
+ * (TwoSum, Knuth's six-operation form), the errors are summed in ordinary
+ * floating point and added once at the end.  The result is as accurate as if
+ * computed in twice the working precision and then rounded, so two
+ * summation orders agree to the last bit unless the exact value lies within
+ * about n u^2 (relative) of a rounding boundary. */
+static void two_sum(double a, double b, double* s, double* e)
 {
-    double acc = 0.0;
-    for (size_t k = 0; k < m; ++k) acc += x[k] * x[k];
-    return acc;
+    const double x = a + b;
+    const double z = x - a;
+    *e = (a - (x - z)) + (b - z);
+    *s = x;
+}
+
+static void two_prod(double a, double b, double* p, double* e)
+{
+    const double x = a * b;
+    *e = fma(a, b, -x);
+    *p = x;
 }
 
 static double dot(const double* x, const double* y, size_t m)
 {
-    double acc = 0.0;
-    for (size_t k = 0; k < m; ++k) acc += x[k] * y[k];
-    return acc;
+    double s = 0.0, c = 0.0;
+    for (size_t k = 0; k < m; ++k) {
+        double h, r, q;
+        two_prod(x[k], y[k], &h, &r);
+        two_sum(s, h, &s, &q);
+        c = c + (q + r);
+    }
+    return s + c;
 }
+
+static double sumsq(const double* x, size_t m) { return dot(x, x, m); }
+
+double or_dot2(const double* x, const double* y, int64_t m) { return dot(x, y, (size_t)m); }
 
 /* residual of the fine FP64 problem and its squared 2-norm */
 static double fine_residual(or_hier* h, const double* u, const double* f, double* r)
@@ -370,6 +407,16 @@ int or_ir_solve(or_hier* h, int kappa, int nu1, int nu2, double* u, const double
     }
 }
 
+/* Preconditioned CG (Section 4, the second solver): x_0 = 0, r_0 = f,
+ * z_k = B r_k with B one zero-guess kappa-cycle, Fletcher-Reeves
+ * beta_k = (r_k . z_k) / (r_{k-1} . z_{k-1}), p_k = z_k + beta_k p_{k-1},
+ * alpha_k = (r_k . z_k) / (p_k . A p_k), x_{k+1} = x_k + alpha_k p_k,
+ * r_{k+1} = r_k - alpha_k A p_k.  The recurrence residual r_k drifts from the
+ * true residual f - A x_k by rounding; when ||r_{k+1}|| / ||f|| falls below tol
+ * the true residual is formed in FP64 and decides: below tol the iteration
+ * stops, otherwise r_{k+1} is replaced by the true residual and the iteration
+ * goes on (residual replacement).  hist[k] is ||r_k|| / ||f|| of the residual
+ * the iteration carries after k steps (the true one where it was formed). */
 int or_pcg(or_hier* h, int kappa, int nu1, int nu2, int precond_f32_flag,
            double* u, const double* f, double tol, int maxit, int* iters, double* hist)
 {
@@ -422,6 +469,11 @@ int or_pcg(or_hier* h, int kappa, int nu1, int nu2, int precond_f32_flag,
         ssr = sumsq(r, m);
         ratio = sqrt(ssr) / normf;
         *iters = it + 1;
+        if (isfinite(ratio) && ratio < tol) {
+            /* the recurrence says converged: the true residual decides */
+            ssr = fine_residual(h, u, f, r);
+            ratio = sqrt(ssr) / normf;
+        }
         if (hist) hist[it + 1] = ratio;
         if (!isfinite(ratio)) { rc = OR_ERR_NONFINITE; break; }
         if (ratio < tol) break;

@@ -74,6 +74,14 @@ int or_set_smoother(or_hier* h, int smoother);
 
 /* one zebra relaxation on the fine level in place (dir 0: x-lines, 1: y-lines) */
 void or_zebra_relax(or_hier* h, int dir, double* v, const double* f);
+/* the line-elimination tables of level `level` (1-based) for x-lines (dir 0)
+ * or y-lines (dir 1): reciprocal pivots rp[q] = 1/p_q and upper multipliers
+ * um[q] = up/p_q, n_l entries each, FP64 */
+int or_zebra_tables(const or_hier* h, int level, int dir, double* rp, double* um);
+
+/* Dot2 dot product of Ogita, Rump and Oishi (the form of every norm and dot
+ * product the drivers take) */
+double or_dot2(const double* x, const double* y, int64_t m);
 
 /*
  * One cycle on the fine level (Algorithm 3 for kind 0, Algorithm 1 for kind 1
@@ -94,7 +102,9 @@ void or_kcycle_f32(or_hier* h, int kappa, int nu1, int nu2, float* v, const floa
 int or_solve(or_hier* h, int kappa, int nu1, int nu2, double* u, const double* f,
              double tol, int maxit, int mode, int* iters, double* hist);
 
-/* conjugate gradients preconditioned by one zero-guess kappa-cycle.
+/* conjugate gradients preconditioned by one zero-guess kappa-cycle, Fletcher-
+ * Reeves beta; once the recurrence residual is below tol the true residual
+ * decides (stop, or replace the recurrence residual and go on).
  * precond_f32 != 0 runs the cycle in FP32 (vectors and dots stay FP64). */
 int or_pcg(or_hier* h, int kappa, int nu1, int nu2, int precond_f32,
            double* u, const double* f, double tol, int maxit, int* iters, double* hist);

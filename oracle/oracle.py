@@ -81,6 +81,10 @@ def lib():
         L.or_ir_scale.argtypes = [C.c_double, C.c_int64]
         L.or_ir_scale.restype = C.c_double
         L.or_grad_params.argtypes = [hp, C.c_double, C.c_double, dp, dp, dp, dp]
+        L.or_zebra_tables.argtypes = [hp, C.c_int, C.c_int, dp, dp]
+        L.or_zebra_tables.restype = C.c_int
+        L.or_dot2.argtypes = [dp, dp, C.c_int64]
+        L.or_dot2.restype = C.c_double
         _lib = L
     return _lib
 
@@ -140,6 +144,14 @@ def galerkin_stencil(s: np.ndarray) -> np.ndarray:
     return sc.reshape(3, 3)
 
 
+def dot2(x: np.ndarray, y: np.ndarray) -> float:
+    """Dot2 dot product (Ogita, Rump and Oishi) as every driver computes it."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    y = np.ascontiguousarray(y, dtype=np.float64).ravel()
+    assert x.size == y.size
+    return lib().or_dot2(_dp(x), _dp(y), x.size)
+
+
 def ir_scale(sumsq: float, npoints: int) -> float:
     return lib().or_ir_scale(sumsq, npoints)
 
@@ -185,6 +197,15 @@ class Hierarchy:
         y = np.empty_like(x)
         lib().or_hier_apply(self._h, _dp(x), _dp(y))
         return y
+
+    def zebra_tables(self, level: int, direction: int):
+        """(reciprocal pivots, upper multipliers) of level `level` (1-based) for
+        x-lines (direction 0) or y-lines (1)."""
+        n = self.sizes[level - 1]
+        rp, um = np.zeros(n), np.zeros(n)
+        if lib().or_zebra_tables(self._h, level, direction, _dp(rp), _dp(um)) != OK:
+            raise ValueError("bad level or direction")
+        return rp, um
 
     def zebra_relax(self, v, f, direction: int):
         """One zebra line relaxation of the fine level (0: x-lines, 1: y-lines); returns the new v."""
