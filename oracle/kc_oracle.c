@@ -58,9 +58,24 @@ static void tr_push(or_tr* t, int op, int level, int counter)
 #undef REAL
 #undef SFX
 
+#define REAL double
+#define SFX(x) x##_d
+#include "kc_oracle_semi.inc"
+#undef REAL
+#undef SFX
+
+#define REAL float
+#define SFX(x) x##_s
+#include "kc_oracle_semi.inc"
+#undef REAL
+#undef SFX
+
 struct or_hier {
-    lv_d d;          /* FP64 hierarchy                                  */
+    lv_d d;          /* FP64 hierarchy (semi-coarsening: the fine level only) */
     lv_s s;          /* FP32 copy used by the FP32 cycle                */
+    int semi;        /* 1: x-line zebra with semi-coarsening along y    */
+    lvs_d sd;        /* semi-coarsened levels, FP64 and FP32            */
+    lvs_s ss;
     double theta, eps, omega;
     double* fine_v;  /* owned fine-level storage when no user array is bound */
     double* fine_f;
@@ -150,6 +165,15 @@ void or_hier_free(or_hier* h)
             free(h->s.zp[k][dir]); free(h->s.zu[k][dir]);
         }
     }
+    for (int k = 0; k < OR_MAXL; ++k) {
+        if (k > 0) {
+            free(h->sd.v[k]); free(h->sd.f[k]);
+            free(h->ss.v[k]); free(h->ss.f[k]);
+        }
+        free(h->sd.t[k]); free(h->ss.t[k]);
+        free(h->sd.zp[k]); free(h->sd.zu[k]);
+        free(h->ss.zp[k]); free(h->ss.zu[k]);
+    }
     free(h->fine_v); free(h->fine_f); free(h->fine_v32); free(h->fine_f32);
     free(h->d.chol);
     free(h->s.chol);
@@ -211,8 +235,69 @@ int or_hier_new(int n, double theta, double eps, int n_coarsest, double omega, o
     return OR_OK;
 }
 
+/* Fifth and sixth solvers of Section 4: x-line zebra relaxation, coarsening
+ * along y only, Galerkin coarse operators.  The fine level (d, L = 1) carries
+ * the fine operator for the drivers' residuals; the cycle runs on sd / ss. */
+int or_hier_new_semi(int n, double theta, double eps, or_hier** out)
+{
+    *out = NULL;
+    if (n < 1 || !is_pow2((long)n + 1)) return OR_ERR_ARG;
+    int L = 1;
+    while (((n + 1) >> (L - 1)) > 2) ++L;
+    if (L > OR_MAXL) return OR_ERR_ARG;
+    or_hier* h = (or_hier*)calloc(1, sizeof(or_hier));
+    if (!h) return OR_ERR_ARG;
+    h->semi = 1;
+    h->theta = theta; h->eps = eps; h->omega = 0.0;
+    h->d.L = h->s.L = 1;
+    h->d.n[0] = h->s.n[0] = n;
+    h->d.h2inv[0] = (double)(n + 1) * (double)(n + 1);
+    or_fine_stencil(theta, eps, h->d.s[0]);
+    h->d.smoother = h->s.smoother = 1;
+    h->sd.L = h->ss.L = L;
+    h->sd.nx = h->ss.nx = n;
+    h->sd.h2inv = h->d.h2inv[0];
+    h->ss.h2inv = (float)h->sd.h2inv;
+    int ok = 1;
+    for (int k = 0; k < L; ++k) {
+        const int ny = ((n + 1) >> k) - 1;
+        const size_t m = (size_t)n * ny;
+        h->sd.ny[k] = h->ss.ny[k] = ny;
+        if (k == 0) memcpy(h->sd.s[0], h->d.s[0], sizeof h->sd.s[0]);
+        else sgalerkin_d(h->sd.s[k - 1], h->sd.s[k]);
+        for (int q = 0; q < 9; ++q) h->ss.s[k][q] = (float)h->sd.s[k][q];
+        h->sd.t[k] = (double*)calloc(m, sizeof(double));
+        h->ss.t[k] = (float*)calloc(m, sizeof(float));
+        ok = ok && h->sd.t[k] && h->ss.t[k];
+        if (k > 0) {
+            h->sd.v[k] = (double*)calloc(m, sizeof(double));
+            h->sd.f[k] = (double*)calloc(m, sizeof(double));
+            h->ss.v[k] = (float*)calloc(m, sizeof(float));
+            h->ss.f[k] = (float*)calloc(m, sizeof(float));
+            ok = ok && h->sd.v[k] && h->sd.f[k] && h->ss.v[k] && h->ss.f[k];
+        }
+        ok = ok && sfactor_d(&h->sd, k) == OR_OK && sfactor_s(&h->ss, k) == OR_OK;
+    }
+    const size_t m0 = (size_t)n * n;
+    h->fine_v = (double*)calloc(m0, sizeof(double));
+    h->fine_f = (double*)calloc(m0, sizeof(double));
+    h->fine_v32 = (float*)calloc(m0, sizeof(float));
+    h->fine_f32 = (float*)calloc(m0, sizeof(float));
+    if (!ok || !h->fine_v || !h->fine_f || !h->fine_v32 || !h->fine_f32) { or_hier_free(h); return OR_ERR_ARG; }
+    *out = h;
+    return OR_OK;
+}
+
 int or_hier_info(const or_hier* h, int* nlevels, int* sizes, double* stencils)
 {
+    if (h->semi) {   /* sizes: lines per level; stencils in units of the fine h^2 */
+        *nlevels = h->sd.L;
+        for (int k = 0; k < h->sd.L; ++k) {
+            if (sizes) sizes[k] = h->sd.ny[k];
+            if (stencils) memcpy(stencils + 9 * k, h->sd.s[k], 9 * sizeof(double));
+        }
+        return OR_OK;
+    }
     *nlevels = h->d.L;
     for (int k = 0; k < h->d.L; ++k) {
         if (sizes) sizes[k] = h->d.n[k];
@@ -229,12 +314,21 @@ void or_hier_apply(const or_hier* h, const double* x, double* y)
 int or_set_smoother(or_hier* h, int smoother)
 {
     if (smoother != 0 && smoother != 1) return OR_ERR_ARG;
+    if (h->semi) return smoother == 1 ? OR_OK : OR_ERR_ARG;   /* always x-line zebra */
     h->d.smoother = h->s.smoother = smoother;
     return OR_OK;
 }
 
 void or_zebra_relax(or_hier* h, int dir, double* v, const double* f)
 {
+    if (h->semi) {   /* one x-line relaxation of the fine level (dir ignored) */
+        h->sd.v[0] = v;
+        h->sd.f[0] = (double*)f;
+        szebra_d(&h->sd, 0);
+        h->sd.v[0] = NULL;
+        h->sd.f[0] = NULL;
+        return;
+    }
     h->d.v[0] = v;
     h->d.f[0] = (double*)f;
     zebra_d(&h->d, 0, dir);
@@ -244,6 +338,12 @@ void or_zebra_relax(or_hier* h, int dir, double* v, const double* f)
 
 int or_zebra_tables(const or_hier* h, int level, int dir, double* rp, double* um)
 {
+    if (h->semi) {   /* x-lines only, nx entries */
+        if (level < 1 || level > h->sd.L || dir != 0) return OR_ERR_ARG;
+        memcpy(rp, h->sd.zp[level - 1], sizeof(double) * (size_t)h->sd.nx);
+        memcpy(um, h->sd.zu[level - 1], sizeof(double) * (size_t)h->sd.nx);
+        return OR_OK;
+    }
     if (level < 1 || level > h->d.L || (dir != 0 && dir != 1)) return OR_ERR_ARG;
     const int k = level - 1;
     memcpy(rp, h->d.zp[k][dir], sizeof(double) * (size_t)h->d.n[k]);
@@ -259,6 +359,15 @@ int64_t or_cycle(or_hier* h, int kind, int param, int nu1, int nu2,
                  double* v, const double* f, int32_t* tr, int64_t cap)
 {
     or_tr t = {tr, cap, 0};
+    if (h->semi) {   /* only the kappa-cycle (Algorithm 3) is defined on these levels */
+        if (kind != 0) return -1;
+        h->sd.v[0] = v;
+        h->sd.f[0] = (double*)f;
+        skcycle_d(&h->sd, 1, param, nu1, nu2, &t);
+        h->sd.v[0] = NULL;
+        h->sd.f[0] = NULL;
+        return t.len;
+    }
     h->d.v[0] = v;
     h->d.f[0] = (double*)f;
     if (kind == 0) kcycle_d(&h->d, 1, param, nu1, nu2, &t);
@@ -271,6 +380,14 @@ int64_t or_cycle(or_hier* h, int kind, int param, int nu1, int nu2,
 
 void or_kcycle_f32(or_hier* h, int kappa, int nu1, int nu2, float* v, const float* f)
 {
+    if (h->semi) {
+        h->ss.v[0] = v;
+        h->ss.f[0] = (float*)f;
+        skcycle_s(&h->ss, 1, kappa, nu1, nu2, NULL);
+        h->ss.v[0] = NULL;
+        h->ss.f[0] = NULL;
+        return;
+    }
     h->s.v[0] = v;
     h->s.f[0] = (float*)f;
     kcycle_s(&h->s, 1, kappa, nu1, nu2, NULL);
@@ -498,5 +615,6 @@ void or_grad_params(const or_hier* h, double theta, double eps, const double* la
     free(y);
 }
 
-/* the FP32 instantiation only needs the kappa-cycle */
+/* the FP32 instantiations only need the kappa-cycle */
 static void (*const or_unused_fcycle_s)(lv_s*, int, int, int, or_tr*) __attribute__((unused)) = fcycle_s;
+static void (*const or_unused_sgalerkin_s)(const float*, float*) __attribute__((unused)) = sgalerkin_s;

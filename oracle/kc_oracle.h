@@ -61,6 +61,14 @@ void or_galerkin_stencil(const double s_fine[9], double s_coarse[9]);
 
 /* hierarchy: n = fine points per side, n_coarsest in {1, 3, 7, ...} */
 int or_hier_new(int n, double theta, double eps, int n_coarsest, double omega, or_hier** out);
+/* the fifth / sixth solvers of Section 4: x-line zebra relaxation (two per
+ * smoothing step with nu = 2), coarsening along y only (level l has n points
+ * per line and (n+1)/2^(l-1) - 1 lines, down to one line, solved exactly by
+ * the line elimination), Galerkin operators s_{l+1} = R s_l P with linear
+ * interpolation P along y and R = P^T / 2.  Drivers and or_cycle (kind 0)
+ * work on it as on a standard hierarchy; or_hier_info reports lines per level
+ * and stencils in units of the fine h^2 */
+int or_hier_new_semi(int n, double theta, double eps, or_hier** out);
 void or_hier_free(or_hier* h);
 int or_hier_info(const or_hier* h, int* nlevels, int* sizes, double* stencils);
 /* y = A_1 x on the fine level */

@@ -63,6 +63,8 @@ def lib():
         L.or_galerkin_stencil.argtypes = [dp, dp]
         L.or_hier_new.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int, C.c_double, C.POINTER(hp)]
         L.or_hier_new.restype = C.c_int
+        L.or_hier_new_semi.argtypes = [C.c_int, C.c_double, C.c_double, C.POINTER(hp)]
+        L.or_hier_new_semi.restype = C.c_int
         L.or_hier_free.argtypes = [hp]
         L.or_hier_info.argtypes = [hp, ip, ip, dp]
         L.or_hier_apply.argtypes = [hp, dp, dp]
@@ -166,13 +168,20 @@ class Hierarchy:
     """Levels of the rotated anisotropic diffusion problem, Galerkin coarsened."""
 
     def __init__(self, n: int, theta: float, eps: float, n_coarsest: int = 1, omega: float = 0.8,
-                 smoother: str = "jacobi"):
-        """smoother: "jacobi" (damped, omega) or "zebra" (alternating line Gauss-Seidel)."""
+                 smoother: str = "jacobi", coarsening: str = "full"):
+        """smoother: "jacobi" (damped, omega) or "zebra" (alternating line Gauss-Seidel);
+        coarsening "semi": x-line zebra with coarsening along y only (the smoother is then
+        always x-line zebra, and `sizes` lists lines per level)."""
         self.n, self.theta, self.eps, self.omega = n, theta, eps, omega
+        self.coarsening = coarsening
         h = C.c_void_p()
-        rc = lib().or_hier_new(n, theta, eps, n_coarsest, omega, C.byref(h))
+        if coarsening == "semi":
+            rc = lib().or_hier_new_semi(n, theta, eps, C.byref(h))
+            smoother = "zebra"
+        else:
+            rc = lib().or_hier_new(n, theta, eps, n_coarsest, omega, C.byref(h))
         if rc != OK:
-            raise ValueError(f"or_hier_new failed ({rc}) for n={n}, n_coarsest={n_coarsest}")
+            raise ValueError(f"hierarchy construction failed ({rc}) for n={n}, n_coarsest={n_coarsest}")
         self._h = h
         self.smoother = smoother
         if lib().or_set_smoother(h, {"jacobi": 0, "zebra": 1}[smoother]) != OK:
@@ -201,7 +210,7 @@ class Hierarchy:
     def zebra_tables(self, level: int, direction: int):
         """(reciprocal pivots, upper multipliers) of level `level` (1-based) for
         x-lines (direction 0) or y-lines (1)."""
-        n = self.sizes[level - 1]
+        n = self.n if self.coarsening == "semi" else self.sizes[level - 1]
         rp, um = np.zeros(n), np.zeros(n)
         if lib().or_zebra_tables(self._h, level, direction, _dp(rp), _dp(um)) != OK:
             raise ValueError("bad level or direction")
