@@ -82,24 +82,50 @@ class KCycleSolve(torch.autograd.Function):
         ctx.eps_shape = torch.as_tensor(eps).shape
         ctx.theta_device = theta.device if torch.is_tensor(theta) else torch.device("cpu")
         ctx.eps_device = eps.device if torch.is_tensor(eps) else torch.device("cpu")
+        ctx.param_is_tensor = (torch.is_tensor(theta), torch.is_tensor(eps))
         return u
 
     @staticmethod
     def backward(ctx, gu):
         f, th, ep = ctx.saved_tensors
         cfg = ctx.cfg
+        want_f, want_th, want_ep = wanted_grads(ctx)
+        if not (want_f or want_th or want_ep):
+            return None, None, None, None
         n = f.shape[1]
         H = cfg.hierarchy(n, th.tolist(), ep.tolist())
-        u = cfg.solve(H, f.contiguous(), cfg.tol)
         lam = cfg.solve(H, gu.contiguous(), cfg.tol_adjoint)
-        dth, de = H.grad_params(list(lam), list(u))
+        dth = de = None
+        if want_th or want_ep:
+            u = cfg.solve(H, f.contiguous(), cfg.tol)   # recomputed: no forward iterate is kept
+            dth, de = H.grad_params(list(lam), list(u))
+        return assemble_grads(ctx, lam, dth, de)
+
+
+def wanted_grads(ctx):
+    """(dL/df, dL/dtheta, dL/deps) wanted: a parameter given as a Python
+    number is not a graph input and takes no gradient."""
+    th_t, ep_t = ctx.param_is_tensor
+    return (bool(ctx.needs_input_grad[0]), bool(ctx.needs_input_grad[1]) and th_t,
+            bool(ctx.needs_input_grad[2]) and ep_t)
+
+
+def assemble_grads(ctx, lam, dth, de):
+    """backward's return tuple: None for every input that takes no gradient,
+    parameter gradients summed for a scalar parameter and placed on its device."""
+    want_f, want_th, want_ep = wanted_grads(ctx)
+    gth = gep = None
+    if want_th:
         gth = torch.tensor(dth, dtype=torch.float64)
-        gep = torch.tensor(de, dtype=torch.float64)
         if len(ctx.theta_shape) == 0:
             gth = gth.sum()
+        gth = gth.to(ctx.theta_device)
+    if want_ep:
+        gep = torch.tensor(de, dtype=torch.float64)
         if len(ctx.eps_shape) == 0:
             gep = gep.sum()
-        return lam, gth.to(ctx.theta_device), gep.to(ctx.eps_device), None
+        gep = gep.to(ctx.eps_device)
+    return (lam if want_f else None), gth, gep, None
 
 
 def solve(f, theta, eps, cfg: SolveConfig | None = None):

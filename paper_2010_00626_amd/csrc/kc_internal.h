@@ -86,6 +86,7 @@ struct InstState {
     int32_t status;    // kc_status of this instance once done
     int32_t done;      // nonzero: every kernel skips this instance
     int32_t maxit;
+    int32_t check;     // PCG: the recurrence residual passed tol; the true residual decides next
 };
 
 // reduction kinds, applied per instance by the finalize kernel after a reduction
@@ -99,6 +100,7 @@ enum Finalize : int32_t {
     FIN_RZ = 6,         // rz_new = sum; beta = rz_new / rz
     FIN_GRAD = 7,       // dth, deps = sums
     FIN_PCG_INIT = 8,   // ssf = ||r_0||^2, first residual test, FP32 scale
+    FIN_PCG_TRUE = 9,   // PCG true-residual test on sum = ||F - S u||^2 (instances with check set)
 };
 
 // persistent coarse kernel operations
@@ -129,7 +131,7 @@ struct StageArgs {
     const InstDev* inst;
     InstState* st;
     const int32_t* tile_off;  // prefix sums over instances of tiles at this depth (count + 1)
-    double* partial;          // one or two doubles per block
+    double* partial;          // per block: two Dot2 sums (value, error term each)
     double* hist;             // relres history, HIST_CAP per instance
     int32_t count;
     int32_t depth;
@@ -185,6 +187,7 @@ enum GridKernel : int32_t {
     GK_ZERO_SELF = 22, // unfused: A[d] = 0 on the launch's own level
     GK_POSTPRE = 23,   // fused junction of sibling calls: post (nu2 = src) of the first + pre (nu) of the second
     GK_ZEBRA = 24,     // zebra line relaxation in place on buffer src, lines of colour dst, direction nu (0 x, 1 y)
+    GK_PCG_TRUE = 25,  // instances with check set: r = F - S u (FP64, replaces the recurrence residual), ||r||^2
 };
 
 // launches kernel k (and, when a.fin is set and with_finalize, the finalize kernel after it)

@@ -205,21 +205,68 @@ __device__ inline bool get_tile(const StageArgs& a, int depth_for_size, bool fin
     return a.st[i].done == 0;
 }
 
-template <int NT>
-__device__ inline double block_sum(double v, double* red)
+// Norms and dot products are Dot2 sums (Ogita, Rump and Oishi, "Accurate sum
+// and dot product", 2005): each product is split into its rounded value and
+// its exact error (explicit fused multiply-add), the running sum into its
+// rounded value and the exact error of the addition (TwoSum), and the errors
+// are summed apart and added once at the end.  Two partial sums combine by a
+// TwoSum of their values plus the sum of their error terms, so a thread, a
+// wave, a block and the finalize kernel each merge in their own fixed order
+// and the result is still as accurate as a sum in twice the working
+// precision, rounded once: it equals a sequential Dot2 of the same terms
+// unless the exact value lies within about n u^2 (relative) of a rounding
+// boundary.
+struct Acc2 {
+    double s, c;
+    __device__ __forceinline__ Acc2() : s(0.0), c(0.0) {}
+    __device__ __forceinline__ void add_prod(double a, double b)
+    {
+        const double p = a * b;
+        const double e = fma(a, b, -p);
+        const double x = s + p;
+        const double z = x - s;
+        const double q = (s - (x - z)) + (p - z);
+        s = x;
+        c = c + (q + e);
+    }
+    __device__ __forceinline__ void add_sq(double a) { add_prod(a, a); }
+    // TwoSum is exact in either argument order and the error terms add
+    // commutatively, so both lanes of a shuffle pair hold the same result
+    __device__ __forceinline__ void merge(double s2, double c2)
+    {
+        const double x = s + s2;
+        const double z = x - s;
+        const double q = (s - (x - z)) + (s2 - z);
+        s = x;
+        c = (c + c2) + q;
+    }
+    __device__ __forceinline__ double value() const { return s + c; }
+};
+
+__device__ __forceinline__ void wave_merge(Acc2& v)
 {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    for (int off = 32; off > 0; off >>= 1) v.merge(__shfl_xor(v.s, off, 64), __shfl_xor(v.c, off, 64));
+}
+
+// block total of a Dot2 accumulator (valid in thread 0); red holds 2 doubles per wave
+template <int NT>
+__device__ inline Acc2 block_sum(Acc2 v, double* red)
+{
+    wave_merge(v);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __syncthreads();
-    if (lane == 0) red[w] = v;
+    if (lane == 0) {
+        red[2 * w] = v.s;
+        red[2 * w + 1] = v.c;
+    }
     __syncthreads();
-    double s = 0.0;
+    Acc2 t;
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NT / 64; ++k) s += red[k];
+        for (int k = 0; k < NT / 64; ++k) t.merge(red[2 * k], red[2 * k + 1]);
     }
-    return s;   // valid in thread 0
+    return t;
 }
 
 __device__ inline double ir_scale(double ss, double npts)
@@ -297,8 +344,23 @@ __device__ void apply_fin(const StageArgs& a, int inst, double S0, double S1)
         }
         break;
     case FIN_PCG_R: {
+        // the recurrence residual drifts from F - S u by rounding: once it passes
+        // tol, the true residual (next launch) decides and, if still above tol,
+        // replaces it
         const double rel = sqrt(S0) / sqrt(s.ssf);
         s.iters += 1;
+        s.relres = rel;
+        if (s.iters < HIST_CAP) a.hist[(size_t)inst * HIST_CAP + s.iters] = rel;
+        s.scale = ir_scale(S0, npts);
+        if (!isfinite(rel)) { s.status = KC_ERR_NONFINITE; s.done = 1; }
+        else if (rel < s.tol) s.check = 1;
+        else if (s.iters >= s.maxit) { s.status = KC_NOT_CONVERGED; s.done = 1; }
+        break;
+    }
+    case FIN_PCG_TRUE: {
+        if (!s.check) break;
+        s.check = 0;
+        const double rel = sqrt(S0) / sqrt(s.ssf);
         s.relres = rel;
         if (s.iters < HIST_CAP) a.hist[(size_t)inst * HIST_CAP + s.iters] = rel;
         s.scale = ir_scale(S0, npts);
@@ -316,50 +378,49 @@ __device__ void apply_fin(const StageArgs& a, int inst, double S0, double S1)
     }
 }
 
-// every block of a reducing launch stores its two block sums; the finalize
-// kernel (one workgroup per instance, launched next on the stream) adds them
-// in block order and applies the solver's decision
-__device__ void reduce_partial(const StageArgs& a, const Tile& t, double v0, double v1)
+// every block of a reducing launch stores its two block sums (value and error
+// term of each); the finalize kernel (one workgroup per instance, launched next
+// on the stream) merges them in block order and applies the solver's decision
+__device__ void reduce_partial(const StageArgs& a, const Tile& t, const Acc2& v0, const Acc2& v1)
 {
-    __shared__ double red[2][GRID_THREADS / 64];
-    const double s0 = block_sum<GRID_THREADS>(v0, red[0]);
-    const double s1 = block_sum<GRID_THREADS>(v1, red[1]);
+    __shared__ double red[2][2 * (GRID_THREADS / 64)];
+    const Acc2 s0 = block_sum<GRID_THREADS>(v0, red[0]);
+    const Acc2 s1 = block_sum<GRID_THREADS>(v1, red[1]);
     if (threadIdx.x == 0) {
         const int gb = a.tile_off[t.inst] + t.blk;
-        a.partial[2 * gb] = s0;
-        a.partial[2 * gb + 1] = s1;
+        a.partial[4 * gb] = s0.s;
+        a.partial[4 * gb + 1] = s0.c;
+        a.partial[4 * gb + 2] = s1.s;
+        a.partial[4 * gb + 3] = s1.c;
     }
 }
 
 __global__ void __launch_bounds__(GRID_THREADS) k_finalize(StageArgs a)
 {
-    __shared__ double red[2][GRID_THREADS / 64];
+    __shared__ double red[2][2 * (GRID_THREADS / 64)];
     const int inst = blockIdx.x;
     const int b0 = a.tile_off[inst], nb = a.tile_off[inst + 1] - b0;
     if (nb == 0 || a.st[inst].done) return;
-    // thread t adds partials t, t + 256, ... in that order; loads go in groups of
-    // eight (clamped indices, masked at use) so that they are in flight together
-    constexpr int G = 8;
-    double t0 = 0.0, t1 = 0.0;
+    // thread t merges partials t, t + 256, ... in that order; loads go in groups of
+    // four (clamped indices, masked at use) so that they are in flight together
+    constexpr int G = 4;
+    Acc2 t0, t1;
+    const double4* P4 = (const double4*)a.partial;
     for (int k0 = threadIdx.x; k0 < nb; k0 += G * GRID_THREADS) {
-        double p0[G], p1[G];
+        double4 p[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int k = min(k0 + g * GRID_THREADS, nb - 1);
-            p0[g] = a.partial[2 * (b0 + k)];
-            p1[g] = a.partial[2 * (b0 + k) + 1];
-        }
+        for (int g = 0; g < G; ++g) p[g] = P4[b0 + min(k0 + g * GRID_THREADS, nb - 1)];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (k0 + g * GRID_THREADS < nb) {
-                t0 += p0[g];
-                t1 += p1[g];
+                t0.merge(p[g].x, p[g].y);
+                t1.merge(p[g].z, p[g].w);
             }
         }
     }
-    const double S0 = block_sum<GRID_THREADS>(t0, red[0]);
-    const double S1 = block_sum<GRID_THREADS>(t1, red[1]);
-    if (threadIdx.x == 0) apply_fin(a, inst, S0, S1);
+    const Acc2 S0 = block_sum<GRID_THREADS>(t0, red[0]);
+    const Acc2 S1 = block_sum<GRID_THREADS>(t1, red[1]);
+    if (threadIdx.x == 0) apply_fin(a, inst, S0.value(), S1.value());
 }
 
 template <typename T> __device__ inline T* buf(const LevelDev& L, int sel) { return (T*)(sel ? L.B : L.A); }
@@ -382,7 +443,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a)
     const T w = P<T>::w(I, d);
     const T fs = (T)Lv.fscale;
     const T* F = (const T*)Lv.F;
-    double nrm = 0.0;
+    Acc2 nrm;
     const int lds_ = a.src ? Lv.ldb : Lv.lda;   // leading dimension of the source buffer
     const int ldd_ = a.dst ? Lv.ldb : Lv.lda;   // leading dimension of the destination buffer
 
@@ -463,14 +524,14 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a)
             if (!in) break;
             const T* x = (const T*)Lv.A;
             const double r = (double)(fs * F[gf] - gapply(s, x, Lv.lda, n, j, i));
-            nrm += r * r;
+            nrm.add_sq(r);
             break;
         }
         default:
             break;
         }
     }
-    if (kind == GK_NORM) reduce_partial(a, t, nrm, 0.0);
+    if (kind == GK_NORM) reduce_partial(a, t, nrm, Acc2());
 }
 
 // ---------------------------------------------------------------------------
@@ -981,14 +1042,14 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
     }
     __syncthreads();
 
-    double nrm = 0.0;
+    Acc2 nrm;
     if (a.fin == FIN_STOP) {
         for (int p = threadIdx.x; p < TX * TY; p += GRID_THREADS) {
             const int rj = H + p / TX, ri = H + (p % TX);
             if (!inside(ry0 + rj, rx0 + ri, n)) continue;
             const int q = rj * RW + ri;
             const double r = (double)(sf[q] - s.apply(&sv[0][q], RW));
-            nrm += r * r;
+            nrm.add_sq(r);
         }
     }
 
@@ -1044,7 +1105,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
             Fc[(size_t)Jc * ldc + Ic] = fw_sum(&rs[q], RW);
         }
     }
-    if (a.fin == FIN_STOP) reduce_partial(a, t, nrm, 0.0);
+    if (a.fin == FIN_STOP) reduce_partial(a, t, nrm, Acc2());
 }
 
 // ---------------------------------------------------------------------------
@@ -1408,7 +1469,7 @@ __global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
     const bool fwc = own && (x & 1) && ((x - 1) >> 1) < nc;
     const int ylo = t.y0, yhi = min(t.y0 + R, n);   // rows this strip stores
     const int i0 = t.y0 - H;
-    double nrm = 0.0;
+    Acc2 nrm;
 
     const Row3<T> z3{T(0), T(0), T(0)};
     RowF<T> V0{z3, T(0)}, V1 = V0, V2 = V0;          // input rows i-2, i-1, i
@@ -1457,7 +1518,7 @@ __global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
                     val = in ? S1.x.c + w * res : T(0);
                     if (k == 1 && stop && own && r >= ylo && r < yhi) {
                         const double rd = (double)res;
-                        nrm += rd * rd;
+                        nrm.add_sq(rd);
                     }
                 }
                 const T fk = S1.f;
@@ -1478,7 +1539,7 @@ __global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
                 const T res = Q1.f - sten3(s, Q0.x, Q1.x, Q2.x);
                 if (NU == 0 && stop && !zg && own && r >= ylo && r < yhi) {
                     const double rd = (double)res;
-                    nrm += rd * rd;
+                    nrm.add_sq(rd);
                 }
                 R0 = R1;
                 R1 = R2;
@@ -1497,7 +1558,7 @@ __global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
         Tile tt;
         tt.inst = t.inst;
         tt.blk = t.blk;
-        reduce_partial(a, tt, nrm, 0.0);
+        reduce_partial(a, tt, nrm, Acc2());
     }
 }
 
@@ -2485,25 +2546,27 @@ __global__ void __launch_bounds__(THREADS) k_subtree(SubArgs a)
     T* f0 = S.bufp(off0, lg0, 2);
 
     if (a.fin == FIN_STOP) {
-        __shared__ double red[16];
+        __shared__ double red[32];
         __shared__ int stop;
         Sten<T> s;
         s.load(pp.s[d0]);
-        double nrm = 0.0;
+        Acc2 nrm;
         for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
             const int j = p / n, i = p - j * n;
             const int q = (j + 1) * Pst + (i + 1);
             const double r = (double)(f0[q] - s.apply(&v0[q], Pst));
-            nrm += r * r;
+            nrm.add_sq(r);
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) nrm += __shfl_xor(nrm, off, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+        wave_merge(nrm);
+        if ((threadIdx.x & 63) == 0) {
+            red[2 * (threadIdx.x >> 6)] = nrm.s;
+            red[2 * (threadIdx.x >> 6) + 1] = nrm.c;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double ss = 0.0;
-            for (int k = 0; k < (int)(blockDim.x >> 6); ++k) ss += red[k];
-            stop_test(a.st[inst], a.hist, inst, ss);
+            Acc2 ss;
+            for (int k = 0; k < (int)(blockDim.x >> 6); ++k) ss.merge(red[2 * k], red[2 * k + 1]);
+            stop_test(a.st[inst], a.hist, inst, ss.value());
             stop = a.st[inst].done;
         }
         __syncthreads();
@@ -2593,7 +2656,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
     Sten<double> s;
     s.load(I.s64[0]);
     const double h2 = I.h2;
-    double acc0 = 0.0, acc1 = 0.0;
+    Acc2 acc0, acc1;
     const LevelDev& L0 = I.lev[0];
     const double scale = st.scale, scale_used = st.scale_used;
     const double alpha = st.alpha, beta = st.beta;
@@ -2621,7 +2684,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
 #pragma unroll
         for (int r = 0; r < DR; ++r) {
             const double f = h2 * F[r];
-            if (ok(r)) acc0 += f * f;
+            if (ok(r)) acc0.add_sq(f);
         }
     } else if constexpr (kind == GK_IR_RESID) {
         DWin<double> w;
@@ -2633,7 +2696,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
         for (int r = 0; r < DR; ++r) {
             const double res = h2 * F[r] - w.apply(s, r);
             if (ok(r)) {
-                acc0 += res * res;
+                acc0.add_sq(res);
                 if (F32) F32f[row0(r)] = (float)(scale * res);
             }
         }
@@ -2657,7 +2720,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
             if (ok(r)) {
                 U[rowu(r)] = 0.0;
                 R[rowv(r)] = f;
-                acc0 += f * f;
+                acc0.add_sq(f);
             }
         }
     } else if constexpr (kind == GK_PCG_PRECIN) {
@@ -2679,7 +2742,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
             const double z = F32 ? E[r] / scale : E[r];
             if (ok(r)) {
                 if (F32) Z[rowv(r)] = z;
-                acc0 += V[r] * z;
+                acc0.add_prod(V[r], z);
             }
         }
     } else if constexpr (kind == GK_PCG_P) {
@@ -2700,7 +2763,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
             const double q = w.apply(s, r);
             if (ok(r)) {
                 Q[rowv(r)] = q;
-                acc0 += w.v[r + 1][1] * q;
+                acc0.add_prod(w.v[r + 1][1], q);
             }
         }
     } else if constexpr (kind == GK_PCG_UPD) {
@@ -2718,7 +2781,22 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
             if (ok(r)) {
                 U[rowu(r)] = V[r] + alpha * Pp[r];
                 R[rowv(r)] = res;
-                acc0 += res * res;
+                acc0.add_sq(res);
+            }
+        }
+    } else if constexpr (kind == GK_PCG_TRUE) {
+        if (!st.check) return;   // uniform over the block: no barrier is skipped by part of it
+        DWin<double> w;
+        w.load(Uc, I.ldu, n, jb, i);
+        double F[DR];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) F[r] = Fv[rowf(r)];
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            const double res = h2 * F[r] - w.apply(s, r);
+            if (ok(r)) {
+                R[rowv(r)] = res;
+                acc0.add_sq(res);
             }
         }
     } else if constexpr (kind == GK_APPLY) {
@@ -2743,8 +2821,8 @@ __global__ void __launch_bounds__(GRID_THREADS) k_driver(StageArgs a)
             const double yt = w.apply(dt, r) * I.h2inv;
             const double ye = w.apply(de, r) * I.h2inv;
             if (ok(r)) {
-                acc0 += Lm[r] * yt;
-                acc1 += Lm[r] * ye;
+                acc0.add_prod(Lm[r], yt);
+                acc1.add_prod(Lm[r], ye);
             }
         }
     }
@@ -2855,6 +2933,7 @@ static hipError_t launch_driver(GridKernel k, const StageArgs& a, int nb, hipStr
     case GK_PCG_P: k_driver<F32, GK_PCG_P><<<g, b, 0, s>>>(a); break;
     case GK_PCG_AP: k_driver<F32, GK_PCG_AP><<<g, b, 0, s>>>(a); break;
     case GK_PCG_UPD: k_driver<F32, GK_PCG_UPD><<<g, b, 0, s>>>(a); break;
+    case GK_PCG_TRUE: k_driver<F32, GK_PCG_TRUE><<<g, b, 0, s>>>(a); break;
     case GK_APPLY: k_driver<F32, GK_APPLY><<<g, b, 0, s>>>(a); break;
     case GK_GRAD: k_driver<F32, GK_GRAD><<<g, b, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;

@@ -224,7 +224,7 @@ kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Lay
                            tiles_tiny(probs[i].n));   // any shape at depth 0
     }
     lay.total_tiles0 = tiles0;
-    lay.partial = take(sizeof(double) * 2 * (size_t)tiles0);
+    lay.partial = take(sizeof(double) * 4 * (size_t)tiles0);
     lay.hist = take(sizeof(double) * (size_t)HIST_CAP * count);
     for (int i = 0; i < count; ++i) {
         InstLayout& il = lay.il[i];
@@ -907,6 +907,9 @@ void iteration(kc_hier* h, int drv, const kc_cycle_params& c, std::vector<Launch
         Launch up = grid(h, GK_PCG_UPD, f32, tt_all0(), 0);
         up.sa.fin = FIN_PCG_R;
         out.push_back(up);
+        Launch tr = grid(h, GK_PCG_TRUE, false, tt_all0(), 0);
+        tr.sa.fin = FIN_PCG_TRUE;
+        out.push_back(tr);
         break;
     }
     }
@@ -1077,6 +1080,22 @@ kc_status check_ptrs(kc_hier* h, PtrT const* p, const int64_t* ld, const char* w
         if (!p[i]) return fail(KC_ERR_ARG, std::string("null device pointer in ") + what);
         if (ld[i] < h->hi[i].il.n[0] || ld[i] > INT32_MAX) return fail(KC_ERR_ARG, std::string("bad leading dimension of ") + what);
     }
+    return KC_OK;
+}
+
+// the zebra line kernels index a level with 32-bit offsets (line * ld + point):
+// a caller's array bound as the fine level must keep (n - 1) * ld + n - 1 in range
+template <typename PtrT>
+kc_status check_zebra_ld(kc_hier* h, const kc_cycle_params* c, PtrT const* p, const int64_t* ld, const char* what)
+{
+    if (c->smoother != 1) return KC_OK;
+    for (int i = 0; i < h->count; ++i) {
+        const int64_t n = h->hi[i].il.n[0];
+        if ((n - 1) * ld[i] + (n - 1) > (int64_t)INT32_MAX)
+            return fail(KC_ERR_ARG, std::string("leading dimension of ") + what +
+                                        " too large for the zebra smoother ((n - 1) * ld + n - 1 must be < 2^31)");
+    }
+    (void)p;
     return KC_OK;
 }
 
@@ -1525,6 +1544,8 @@ kc_status kc_cycle(kc_hier* h, double* const* d_v, const int64_t* ldv, const dou
     kc_status s;
     if ((s = check_ptrs(h, d_v, ldv, "v")) != KC_OK || (s = check_ptrs(h, d_f, ldf, "f")) != KC_OK) return s;
     if ((s = prepare_call(h, c)) != KC_OK) return s;
+    if ((s = check_zebra_ld(h, c, d_v, ldv, "v")) != KC_OK || (s = check_zebra_ld(h, c, d_f, ldf, "f")) != KC_OK)
+        return s;
     if ((s = enter(h)) != KC_OK) return s;
     bind_level0_user(h, d_v, ldv, d_f, ldf);
     if ((s = upload_inst(h)) != KC_OK) return s;
@@ -1542,6 +1563,8 @@ kc_status kc_solve(kc_hier* h, double* const* d_u, const int64_t* ldu, const dou
     if ((s = check_ptrs(h, d_u, ldu, "u")) != KC_OK || (s = check_ptrs(h, d_f, ldf, "f")) != KC_OK) return s;
     if (maxit < 0 || !(tol >= 0.0)) return fail(KC_ERR_ARG, "maxit must be >= 0 and tol >= 0");
     if ((s = prepare_call(h, c)) != KC_OK) return s;
+    if ((s = check_zebra_ld(h, c, d_u, ldu, "u")) != KC_OK || (s = check_zebra_ld(h, c, d_f, ldf, "f")) != KC_OK)
+        return s;
     if ((s = enter(h)) != KC_OK) return s;
     const bool f32 = h->prec == KC_F32_CYCLE;
     if (f32) {
@@ -1728,6 +1751,8 @@ kc_status kc_time_cycles(kc_hier* h, double* const* d_v, const int64_t* ldv, con
     kc_status s;
     if ((s = check_ptrs(h, d_v, ldv, "v")) != KC_OK || (s = check_ptrs(h, d_f, ldf, "f")) != KC_OK) return s;
     if ((s = prepare_call(h, c)) != KC_OK) return s;
+    if ((s = check_zebra_ld(h, c, d_v, ldv, "v")) != KC_OK || (s = check_zebra_ld(h, c, d_f, ldf, "f")) != KC_OK)
+        return s;
     if ((s = enter(h)) != KC_OK) return s;
     bind_level0_user(h, d_v, ldv, d_f, ldf);
     if ((s = upload_inst(h)) != KC_OK) return s;

@@ -4,9 +4,12 @@ gradient and against central finite differences.
 Loss L = 1/2 ||u - u*||^2 with u = A(theta, eps)^{-1} f and u* the solution
 for (theta + 0.1, 2 eps) and the same f (held constant).  Finite differences
 use step 1e-6 for theta and a relative step 1e-4 for eps, with forward and
-adjoint solves converged to 1e-13: with eps near 1e-4 a relative step of 1e-6
-makes the difference quotient carry the solver tolerance (about 1e-13 / 1e-10
-relative), while the central-difference truncation error at 1e-4 is ~1e-8."""
+adjoint solves converged to 1e-12 on the true FP64 residual (PCG confirms
+convergence on f - A u; the attainable floor of these problems is 5e-13 to
+9e-13 at 127^2 and up to 2.4e-12 at 255^2): with eps near 1e-4 a relative
+step of 1e-6 makes the difference quotient carry the solver tolerance (about
+1e-12 / 1e-10 relative), while the central-difference truncation error at
+1e-4 is ~1e-8."""
 import math
 
 import numpy as np
@@ -43,7 +46,7 @@ def test_adjoint_matches_oracle_and_fd():
     n, count = 127, 3
     print("[gpu-adjoint] n=127 batch=3", flush=True)
     th, ep, fs = batch(n, count, 3)
-    cfg = ag.SolveConfig(kappa=3, nu1=1, nu2=1, tol=1e-13, tol_adjoint=1e-13, maxit=500)
+    cfg = ag.SolveConfig(kappa=3, nu1=1, nu2=1, tol=1e-12, tol_adjoint=1e-12, maxit=500)
     f = torch.from_numpy(fs).cuda()
     with torch.no_grad():
         target = ag.solve(f, torch.tensor(th + 0.1), torch.tensor(2 * ep), cfg)
@@ -54,13 +57,13 @@ def test_adjoint_matches_oracle_and_fd():
     L.backward()
     gth, gep, gf = tht.grad.numpy(), ept.grad.numpy(), fr.grad.cpu().numpy()
 
-    # oracle gradient: u, u*, lam by the oracle's PCG at 1e-13, then its inner products
+    # oracle gradient: u, u*, lam by the oracle's PCG at 1e-12, then its inner products
     for k in range(count):
         H = O.Hierarchy(n, th[k], ep[k])
         Hs = O.Hierarchy(n, th[k] + 0.1, 2 * ep[k])
-        u, rc, _, _ = H.pcg(fs[k], kappa=3, tol=1e-13, maxit=500)
-        us, rc2, _, _ = Hs.pcg(fs[k], kappa=3, tol=1e-13, maxit=500)
-        lam, rc3, _, _ = H.pcg(u - us, kappa=3, tol=1e-13, maxit=500)
+        u, rc, _, _ = H.pcg(fs[k], kappa=3, tol=1e-12, maxit=500)
+        us, rc2, _, _ = Hs.pcg(fs[k], kappa=3, tol=1e-12, maxit=500)
+        lam, rc3, _, _ = H.pcg(u - us, kappa=3, tol=1e-12, maxit=500)
         assert rc == rc2 == rc3 == O.OK
         ot, oe = H.grad_params(lam, u)
         assert abs(gth[k] - ot) <= 1e-8 * abs(ot) + 1e-14, (k, gth[k], ot)
@@ -94,14 +97,15 @@ def test_adjoint_matches_oracle_and_fd():
 
 
 def test_adjoint_tolerance_1e8_error_is_reported_small():
-    """At the workload tolerance 1e-8 the gradient stays close to the 1e-13 one."""
+    """At the workload tolerance 1e-8 the gradient stays close to the one at
+    5e-12 (near the FP64 floor of these problems)."""
     from paper_2010_00626_amd import autograd as ag
     n, count = 255, 2
-    print("[gpu-adjoint] n=255 batch=2 tol 1e-8 vs 1e-13", flush=True)
+    print("[gpu-adjoint] n=255 batch=2 tol 1e-8 vs 5e-12", flush=True)
     th, ep, fs = batch(n, count, 4)
     f = torch.from_numpy(fs).cuda()
     grads = []
-    for tol in (1e-8, 1e-13):
+    for tol in (1e-8, 5e-12):
         cfg = ag.SolveConfig(kappa=3, nu1=1, nu2=1, tol=tol, tol_adjoint=tol, maxit=800)
         with torch.no_grad():
             target = ag.solve(f, torch.tensor(th + 0.1), torch.tensor(2 * ep), cfg)

@@ -207,3 +207,37 @@ def test_exec_options_validated_without_gpu():
         assert ei.value.status == K.KC_ERR_ARG, bad
     with pytest.raises(K.KCycleError):
         K.schedule_counts([(255, 0.4, 1e-3)], 2, smoother=2)
+
+
+def test_autograd_gradient_return_for_number_parameters():
+    """theta / eps given as Python numbers are no graph inputs: backward
+    returns None for them (autograd rejects a tensor there), and tensor
+    parameters get their (summed, for a scalar) gradient.  A CPU stand-in
+    for the solve exercises the same return assembly as the GPU Function."""
+    import torch
+    from paper_2010_00626_amd import autograd as ag
+
+    class Stub(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, f, theta, eps):
+            ctx.theta_shape = torch.as_tensor(theta).shape
+            ctx.eps_shape = torch.as_tensor(eps).shape
+            ctx.theta_device = theta.device if torch.is_tensor(theta) else torch.device("cpu")
+            ctx.eps_device = eps.device if torch.is_tensor(eps) else torch.device("cpu")
+            ctx.param_is_tensor = (torch.is_tensor(theta), torch.is_tensor(eps))
+            return 2.0 * f
+
+        @staticmethod
+        def backward(ctx, gu):
+            B = gu.shape[0]
+            return ag.assemble_grads(ctx, 2.0 * gu, [1.0] * B, [3.0] * B)[:3]
+
+    f = torch.ones((2, 3, 3), dtype=torch.float64, requires_grad=True)
+    Stub.apply(f, 0.3, 1e-3).sum().backward()           # numbers: no gradient for them, no error
+    assert torch.equal(f.grad, torch.full_like(f, 2.0))
+    th = torch.tensor(0.3, dtype=torch.float64, requires_grad=True)
+    ep = torch.tensor([1e-3, 2e-3], dtype=torch.float64, requires_grad=True)
+    Stub.apply(f.detach(), th, ep).sum().backward()
+    assert float(th.grad) == 2.0 and ep.grad.tolist() == [3.0, 3.0]
+    ep2 = torch.tensor([1e-3, 2e-3], dtype=torch.float64)   # a tensor that needs no gradient
+    Stub.apply(f, th.detach(), ep2).sum().backward()
