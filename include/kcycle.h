@@ -158,16 +158,21 @@ kc_status kc_solve(kc_hier* h, double* const* d_u, const int64_t* ldu, const dou
                    int32_t* iters, double* relres, int32_t* status);
 
 /* conjugate gradients preconditioned by one zero-guess kappa-cycle per
- * iteration (Section 4, second solver), x_0 = 0, Fletcher-Reeves beta, stop
- * on the recurrence residual ||r_k|| / ||f|| < tol.  Vectors and dot products
- * in FP64; the cycle in FP32 on FP32 hierarchies.  Synchronises. */
+ * iteration (Section 4, second solver), x_0 = 0, Fletcher-Reeves beta.  Once
+ * the recurrence residual gives ||r_k|| / ||f|| < tol, the true residual
+ * f - A u_k is formed in FP64 and decides: below tol the solve stops,
+ * otherwise it replaces r_k and CG goes on (residual replacement), so a
+ * converged instance has a true relative residual below tol.  Vectors and
+ * dot products (Dot2 sums) in FP64; the cycle in FP32 on FP32 hierarchies.
+ * Synchronises. */
 kc_status kc_pcg(kc_hier* h, double* const* d_u, const int64_t* ldu, const double* const* d_f,
                  const int64_t* ldf, const kc_cycle_params* c, double tol, int32_t maxit,
                  int32_t* iters, double* relres, int32_t* status);
 
 /* relative-residual history of instance `instance` in the last kc_solve or
  * kc_pcg on h: out[k] = ||r_k|| / ||f|| after k cycles (stand-alone; out[0]
- * is the initial guess) or k CG iterations (recurrence residual, out[0] = 1).
+ * is the initial guess) or k CG iterations (recurrence residual, or the true
+ * residual where PCG formed it; out[0] = 1).
  * *count receives the number of entries recorded, min(iters + 1, 8192): the
  * first 8192 are kept, longer runs are not limited by this.  Copies
  * min(cap, *count) entries to the host buffer out (may be NULL when cap is
@@ -183,6 +188,27 @@ kc_status kc_apply_A(kc_hier* h, double* const* d_y, const int64_t* ldy, const d
  * lam the adjoint solution (A is symmetric).  FP64.  Synchronises. */
 kc_status kc_grad_params(kc_hier* h, const double* const* d_lam, const int64_t* ldl, const double* const* d_u,
                          const int64_t* ldu, double* dtheta, double* deps);
+
+/* For callers that cannot allocate device memory or create a hierarchy (code
+ * under graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the gradient inner products of kc_grad_params for `count` instances given
+ * by probs (n, theta, eps; n_coarsest is checked but unused), without a
+ * hierarchy or workspace.  lam and u are caller-owned FP64 arrays in the
+ * layout above; dtheta / deps are host arrays of count entries.  The instance
+ * table, per-instance state, block table and the Dot2 block partials (32 B
+ * per 64 x 32 tile of every instance) live in a static device array of
+ * KC_NOALLOC_SCRATCH_BYTES, one per GPU, held until the process ends; the
+ * call allocates no device memory.  KC_ERR_ARG when count exceeds
+ * KC_NOALLOC_MAX_INSTANCES or the tiles do not fit (one 16383^2 instance
+ * does, two do not).  Runs on the current device, ordered on hip_stream
+ * (NULL = default stream), and synchronises it.  Calls on one GPU share the
+ * array: calls that overlap (other host threads are serialised by a lock,
+ * other processes are not) race.  Results are those of kc_grad_params. */
+#define KC_NOALLOC_SCRATCH_BYTES (8 << 20)
+#define KC_NOALLOC_MAX_INSTANCES 64
+kc_status kc_grad_params_noalloc(const kc_problem* probs, int32_t count, const double* const* d_lam,
+                                 const int64_t* ldl, const double* const* d_u, const int64_t* ldu, void* hip_stream,
+                                 double* dtheta, double* deps);
 
 /* host-only: the h^2-scaled 3x3 stencils of every level of one problem,
  * s[9*l + 3*(b+1) + (a+1)] for offset (a, b) in (x, y); no GPU needed */

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -1912,3 +1913,118 @@ kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// gradient inner products without a hierarchy or workspace: the instance table,
+// the per-instance state, the block table and the Dot2 block partials live in a
+// static device array of fixed size (one copy per GPU, held until the process
+// ends); nothing allocates device memory
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[KC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;                       // host staging below and the per-device addresses
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {}; // device address of `scratch` on each GPU
+
+struct NoallocStaging {
+    InstDev inst[KC_NOALLOC_MAX_INSTANCES];
+    InstState st[KC_NOALLOC_MAX_INSTANCES];
+    int32_t tile_off[KC_NOALLOC_MAX_INSTANCES + 1];
+};
+NoallocStaging g_noalloc_host;                 // host-side tables of the call in progress (guarded by the mutex)
+
+// the scratch array's address on the current device, looked up once per device
+kc_status scratch_address(void** out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(KC_ERR_ARG, "device index out of range");
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(KC_ERR_HIP, "hipGetSymbolAddress returned a null scratch address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return KC_OK;
+}
+
+}  // namespace
+
+extern "C" kc_status kc_grad_params_noalloc(const kc_problem* probs, int32_t count, const double* const* d_lam,
+                                            const int64_t* ldl, const double* const* d_u, const int64_t* ldu,
+                                            void* hip_stream, double* dtheta, double* deps)
+{
+    if (!probs || !d_lam || !ldl || !d_u || !ldu || !dtheta || !deps) return fail(KC_ERR_ARG, "null argument");
+    if (count < 1 || count > KC_NOALLOC_MAX_INSTANCES)
+        return fail(KC_ERR_ARG, "count must be in 1.." + std::to_string(KC_NOALLOC_MAX_INSTANCES));
+    // scratch layout: instance table | states | block table | partials (4 doubles per 64 x 32 tile)
+    const size_t off_st = align_up(sizeof(InstDev) * (size_t)count);
+    const size_t off_tiles = off_st + align_up(sizeof(InstState) * (size_t)count);
+    const size_t off_part = off_tiles + align_up(sizeof(int32_t) * (size_t)(count + 1));
+    int64_t tiles = 0;
+    for (int i = 0; i < count; ++i) {
+        int L;
+        kc_status st = check_problem(probs[i], L);
+        if (st != KC_OK) return st;
+        tiles += tiles_of(probs[i].n);
+    }
+    if (off_part + (size_t)tiles * 4 * sizeof(double) > (size_t)KC_NOALLOC_SCRATCH_BYTES)
+        return fail(KC_ERR_ARG, "inputs need " + std::to_string(off_part + (size_t)tiles * 32) +
+                                    " B of scratch; the static array holds " + std::to_string(KC_NOALLOC_SCRATCH_BYTES));
+    for (int i = 0; i < count; ++i) {
+        const int64_t n = probs[i].n;
+        if (!d_lam[i] || !d_u[i]) return fail(KC_ERR_ARG, "null device pointer in lam or u");
+        if (ldl[i] < n || ldl[i] > INT32_MAX || ldu[i] < n || ldu[i] > INT32_MAX)
+            return fail(KC_ERR_ARG, "bad leading dimension of lam or u");
+    }
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    void* base = nullptr;
+    kc_status s = scratch_address(&base);
+    if (s != KC_OK) return s;
+    unsigned char* sc = (unsigned char*)base;
+    NoallocStaging& hs = g_noalloc_host;
+    hs.tile_off[0] = 0;
+    for (int i = 0; i < count; ++i) {
+        const kc_problem& p = probs[i];
+        InstDev& I = hs.inst[i];
+        std::memset(&I, 0, sizeof I);
+        I.L = 1;
+        I.n0 = p.n;
+        double s9[9];
+        fine_stencil(p.theta, p.eps, s9);
+        for (int q = 0; q < 9; ++q) I.s64[0][q] = s9[q];
+        const double hh = 1.0 / (double)(p.n + 1);
+        I.h2 = hh * hh;
+        I.h2inv = (double)(p.n + 1) * (double)(p.n + 1);
+        fine_stencil_derivs(p.theta, p.eps, I.ds_th, I.ds_ep);
+        I.x = d_lam[i];
+        I.ldx = (int32_t)ldl[i];
+        I.y = (double*)d_u[i];
+        I.ldy = (int32_t)ldu[i];
+        std::memset(&hs.st[i], 0, sizeof(InstState));
+        hs.tile_off[i + 1] = hs.tile_off[i] + tiles_of(p.n);
+    }
+    hipStream_t stream = (hipStream_t)hip_stream;
+    HIPCHK(hipMemcpyAsync(sc, hs.inst, sizeof(InstDev) * count, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(sc + off_st, hs.st, sizeof(InstState) * count, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(sc + off_tiles, hs.tile_off, sizeof(int32_t) * (count + 1), hipMemcpyHostToDevice, stream));
+    StageArgs a{};
+    a.inst = (const InstDev*)sc;
+    a.st = (InstState*)(sc + off_st);
+    a.tile_off = (const int32_t*)(sc + off_tiles);
+    a.partial = (double*)(sc + off_part);
+    a.hist = nullptr;
+    a.count = count;
+    a.fin = FIN_GRAD;
+    HIPCHK(launch_grid(GK_GRAD, false, a, (int32_t)tiles, stream));
+    HIPCHK(hipMemcpyAsync(hs.st, sc + off_st, sizeof(InstState) * count, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int i = 0; i < count; ++i) {
+        dtheta[i] = hs.st[i].dth;
+        deps[i] = hs.st[i].deps;
+    }
+    return KC_OK;
+}

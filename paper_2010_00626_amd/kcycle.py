@@ -81,6 +81,7 @@ def lib():
         L.kc_apply_A.argtypes = arr
         L.kc_residual_history.argtypes = [vp, i32, P(dbl), i32, P(i32)]
         L.kc_grad_params.argtypes = arr + [P(dbl), P(dbl)]
+        L.kc_grad_params_noalloc.argtypes = [P(Problem), i32, P(vp), P(i64), P(vp), P(i64), vp, P(dbl), P(dbl)]
         L.kc_level_stencils.argtypes = [P(Problem), i32, P(i32), P(dbl)]
         L.kc_schedule_counts.argtypes = [P(Problem), i32, P(Exec), P(CycleParams), P(i64), P(i64), P(i64)]
         L.kc_stats.argtypes = [vp, C.c_char_p, sz]
@@ -93,7 +94,7 @@ def lib():
         L.kc_last_error.restype = C.c_char_p
         for name in ("kc_workspace_bytes", "kc_create", "kc_destroy", "kc_set_exec", "kc_cycle", "kc_solve",
                      "kc_pcg", "kc_apply_A", "kc_residual_history", "kc_grad_params", "kc_level_stencils", "kc_schedule_counts",
-                     "kc_stats", "kc_time_stage", "kc_time_cycles", "kc_profile_iteration"):
+                     "kc_stats", "kc_time_stage", "kc_time_cycles", "kc_profile_iteration", "kc_grad_params_noalloc"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -174,6 +175,45 @@ def schedule_counts(problems, kappa: int, nu1: int = 2, nu2: int = 2, omega: flo
     g, s, st = C.c_int64(), C.c_int64(), C.c_int64()
     _check(lib().kc_schedule_counts(arr, n, C.byref(e), C.byref(c), C.byref(g), C.byref(s), C.byref(st)))
     return {"grid_launches": g.value, "subtree_launches": s.value, "subtree_stages": st.value}
+
+
+def _device_arrays(xs, sizes, what: str):
+    """host arrays of device pointers and leading dimensions of FP64 tensors"""
+    import torch
+    if isinstance(xs, torch.Tensor):
+        xs = [xs]
+    xs = list(xs)
+    if len(xs) != len(sizes):
+        raise ValueError(f"{what}: expected {len(sizes)} tensors, got {len(xs)}")
+    ptrs = (C.c_void_p * len(xs))()
+    lds = (C.c_int64 * len(xs))()
+    for i, (t, n) in enumerate(zip(xs, sizes)):
+        if t.dtype != torch.float64 or not t.is_cuda:
+            raise TypeError(f"{what}[{i}] must be a float64 GPU tensor")
+        if t.dim() != 2 or t.shape[0] != n or t.shape[1] != n or t.stride(1) != 1 or t.stride(0) < n:
+            raise ValueError(f"{what}[{i}] must be a row-major ({n}, {n}) tensor")
+        ptrs[i] = t.data_ptr()
+        lds[i] = t.stride(0)
+    return ptrs, lds
+
+
+def grad_params_noalloc(problems, lam, u, stream=None):
+    """kc_grad_params_noalloc: the gradient inner products of
+    Hierarchy.grad_params without a hierarchy or workspace (the library keeps
+    its tables and partial sums in a static device array).  Runs on the
+    current device and stream unless `stream` is given."""
+    import torch
+    arr, count = _problems(problems)
+    sizes = [arr[i].n for i in range(count)]
+    pl, ll = _device_arrays(lam, sizes, "lam")
+    pu, lu = _device_arrays(u, sizes, "u")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    handle = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    dth = (C.c_double * count)()
+    de = (C.c_double * count)()
+    _check(lib().kc_grad_params_noalloc(arr, count, pl, ll, pu, lu, handle, dth, de))
+    return list(dth), list(de)
 
 
 class Hierarchy:
