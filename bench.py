@@ -5,8 +5,12 @@ Workload (default): 1023 x 1023 interior grid (10 levels to 1 x 1), theta=pi/6,
 eps=1e-4, damped Jacobi omega=0.8 with nu1=nu2=2, f i.i.d. U[-1,1] from seed 1,
 zero initial guess, stop at ||f - A u|| / ||f|| < 1e-8.  Every kappa in
 {1, 2, 3, 4, 6, W} is run with FP64 cycles and with FP32 cycles inside FP64
-iterative refinement; the headline `value` is the fastest of these, timed over
-`--steps` complete solves (inputs resident in HBM, setup excluded).
+iterative refinement; the headline `value` is the fastest FP64 configuration
+(the paper's arithmetic), timed over `--steps` complete solves (inputs
+resident in HBM, setup excluded).  The FP32-cycle results are reported beside
+it, and the last key of the line, `summary`, repeats the figures the extras
+measure (batched speed-up, PCG true residuals, fine-level bandwidth, the
+model's predicted best kappa).
 
 Prints ONE JSON line.  `--gpus N` with N > 1 exits: every run is one GPU.
 """
@@ -27,7 +31,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fine-grid unknowns/s to 1e-8 rel. residual per κ; batched+FP32 vs plain FP64"
 HBM_PEAK_GBS = 8000.0
-VECTOR_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X dense vector peaks (FP32 counts packed issue)
+# MI355X vector peak: 256 CUs x 2.4 GHz x 64 lanes x 2 flops (FMA) = 78.6 TFLOP/s in FP64 and, without
+# packed issue (the library is compiled with packed FP32 off), in FP32 as well
+VECTOR_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
+CUS = 256
 
 
 def traffic_of(kernel: str):
@@ -56,9 +63,12 @@ def kernel_row(k, prec):
     """Roofline entry of one kernel from the library's per-launch profile."""
     avg_s = k["avg_ms"] * 1e-3
     if k["name"].startswith("k_subtree"):
+        # one workgroup per instance on one CU: the chip-wide fraction is tiny by construction, so the
+        # per-CU fraction (one instance here) is reported beside it
         peak = VECTOR_PEAK_TFLOPS[prec]
         ach = k["flops_per_launch"] / avg_s / 1e12 if avg_s > 0 else 0.0
-        return {"bound": "alu", "achieved": round(ach, 4), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 5)}
+        return {"bound": "alu", "achieved": round(ach, 4), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 6),
+                "frac_of_one_cu": round(ach / (peak / CUS), 4)}
     ach = k["bytes_per_launch"] / avg_s / 1e9 if avg_s > 0 else 0.0
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4)}
@@ -74,7 +84,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=40, help="oracle cycles timed for the CPU baseline")
     ap.add_argument("--kappa", type=int, default=0, help="force the headline kappa (0 = fastest of the sweep)")
-    ap.add_argument("--precision", default="", help="force the headline precision (f64 or f32)")
+    ap.add_argument("--precision", default="f64", help="headline precision (f64, the paper's arithmetic, or f32)")
+    ap.add_argument("--no-model", action="store_true", help="skip the run-time model's calibration sweep")
     ap.add_argument("--no-tune", action="store_true", help="skip the execution-option autotuner")
     ap.add_argument("--exec", default="", help="JSON execution options for the headline configuration "
                     "(instead of the autotuned ones)")
@@ -142,29 +153,30 @@ def main():
                 elif key in u64:   # max-norm error of the FP32-cycle solution against the FP64 one
                     err = float((u - u64[key]).abs().max() / u64[key].abs().max())
                 per.setdefault(key, {})[prec] = {
-                    "cycles": its[0], "relres": rr[0], "ms": round(med * 1e3, 3), "err_vs_f64_oracle": err,
+                    "cycles": its[0], "relres": rr[0], "ms": round(med * 1e3, 3),
                     "ms_per_cycle": round(med * 1e3 / max(its[0], 1), 4),
-                    "unknowns_per_s": N / med,
+                    "unknowns_per_s": round(N / med),
                     "grid_launches_per_cycle": stats["grid_launches_per_iteration"],
                     "persistent_launches_per_cycle": stats["subtree_launches_per_iteration"],
                     "persistent_stages_per_cycle": stats["subtree_stages_per_iteration"],
-                    "exec": cfg,
                 }
+                if err is not None:
+                    # the FP64 solutions equal the CPU oracle's bit for bit (full-size GPU test)
+                    per[key][prec]["err_vs_f64_oracle"] = err
                 print(f"[bench] {prec} kappa={key}: {its[0]} cycles, {med * 1e3:.2f} ms", file=sys.stderr, flush=True)
 
-    # headline configuration
+    # headline configuration: the fastest kappa in the headline precision
+    best_p = args.precision
     if args.kappa:
-        best_k, best_p = args.kappa, (args.precision or "f32")
+        best_k = args.kappa
     elif per:
-        best_p, best_k, best_t = None, None, math.inf
+        best_k, best_t = None, math.inf
         for key, d in per.items():
-            for prec, r in d.items():
-                if r["ms"] < best_t:
-                    best_t, best_p, best_k = r["ms"], prec, (kcycle.KAPPA_W if key == "W" else int(key))
-        if args.precision:
-            best_p = args.precision
+            r = d.get(best_p)
+            if r and r["ms"] < best_t:
+                best_t, best_k = r["ms"], (kcycle.KAPPA_W if key == "W" else int(key))
     else:
-        best_k, best_p = 3, (args.precision or "f32")
+        best_k = 2
 
     if args.exec:
         tuned[(best_p, best_k)] = json.loads(args.exec)
@@ -209,26 +221,12 @@ def main():
     fine = {"kernel": "fine-level pre-smoothing", "avg_us": round(ms_pre * 1e3, 2),
             "GB_s": round(bytes_pre / (ms_pre * 1e-3) / 1e9, 1), "bytes_per_launch": bytes_pre}
 
-    # run-time model (Section 3) fitted to the sweep's per-cycle times and the kappa it predicts.
-    # A call of the fused schedule is a grid launch or a stage (pre, post or solve op) of the
-    # persistent kernel: each is one serialised step whose cost is the model's alpha.
+    # run-time model (Section 3): alpha and beta fitted on a calibration sweep of other sizes (6-9 and 11
+    # levels, kappa in {1, 2, 3, 4, W}, the default execution options), then used to predict the time per
+    # cycle of the 1023^2 problem (10 levels) and, with the measured cycle counts, its best kappa
     model_info = None
-    if per:
-        rows = []
-        for key, d in per.items():
-            r = d[best_p]
-            k = kcycle.KAPPA_W if key == "W" else int(key)
-            calls = r["grid_launches_per_cycle"] + r["persistent_stages_per_cycle"]
-            rows.append((key, calls, model.n_ops_2d(k, levels), r["ms_per_cycle"]))
-        fitted = model.fit(rows)
-        cyc = {row[0]: per[row[0]][best_p]["cycles"] for row in rows}
-        pred = {row[0]: fitted.predict(row[1], row[2]) * cyc[row[0]] for row in rows}
-        model_info = {"alpha_ms": fitted.alpha, "beta_ms": fitted.beta, "calls": "grid launches + persistent stages",
-                      "predicted_best_kappa": min(pred, key=pred.get),
-                      "predicted_solve_ms": {k: round(v, 2) for k, v in pred.items()},
-                      "measured_best_kappa": "W" if best_k == kcycle.KAPPA_W else str(best_k),
-                      "rel_errors": {k: round(v, 4) for k, v in fitted.rel_errors.items()}}
-
+    if per and not args.no_model:
+        model_info = model_prediction(kcycle, model, torch, inst, w, per, f)
     extras = {}
     ex = set(x for x in args.extras.split(",") if x)
     del H, u64
@@ -248,6 +246,14 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inst, w, best_k, per, args.cpu_cycles)
 
+    f32_best = None
+    if per:
+        ks = [(d["f32"]["ms"], key) for key, d in per.items() if "f32" in d]
+        if ks:
+            key = min(ks)[1]
+            f32_best = {"kappa": key, "ms": per[key]["f32"]["ms"], "cycles": per[key]["f32"]["cycles"],
+                        "unknowns_per_s": per[key]["f32"]["unknowns_per_s"],
+                        "err_vs_f64_oracle": per[key]["f32"].get("err_vs_f64_oracle")}
     out = {
         "metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -258,11 +264,86 @@ def main():
                    "kappa": "W" if best_k == kcycle.KAPPA_W else best_k, "precision": best_p,
                    "exec": tuned.get((best_p, best_k)),
                    "cycles": its[0], "unknowns": N},
-        "roofline": roofline, "kernels": kernels, "iteration_ms": round(it_ms, 4), "fine_level": fine,
+        "roofline": roofline, "iteration_ms": round(it_ms, 4), "fine_level": fine,
+        "kernels": dict(list(kernels.items())[:8]),
         "per_kappa": per, "model": model_info,
         "extras": extras, "cpu_baseline": cpu,
     }
+    out["summary"] = summary(out, f32_best)
     print(json.dumps(out))
+
+
+def summary(out, f32_best):
+    """The figures a reader wants first, repeated as the line's last key."""
+    ex = out.get("extras", {})
+    sm = {"headline": {"dtype": out["dtype"], "kappa": out["config"]["kappa"], "unknowns_per_s": round(out["value"]),
+                       "ms_per_solve": round(out["ms_per_step"], 3), "cycles": out["config"]["cycles"]},
+          "best_f32_cycles_f64_refinement": f32_best}
+    if "c4_batched" in ex:
+        c4 = ex["c4_batched"]
+        sm["c4"] = {k: c4.get(k) for k in ("batched_f32_ms", "per_instance_f64_loop_ms",
+                                           "speedup_batched_f32_vs_loop_f64", "batched_zebra_f32_ms",
+                                           "per_instance_zebra_f64_loop_ms",
+                                           "speedup_batched_zebra_f32_vs_zebra_loop_f64",
+                                           "max_err_batched_f32_vs_f64")}
+    if "c3_pcg" in ex:
+        sm["c3_true_relres_f64"] = {k: v["true_relres_f64"] for k, v in ex["c3_pcg"].items()}
+        sm["c3_ms"] = {k: v["ms"] for k, v in ex["c3_pcg"].items()}
+    if "fine_kernels_hbm" in ex:
+        hb = ex["fine_kernels_hbm"]
+        sm["fine_TB_s_nu2"] = {f"{name}_{n}": round(hb[f"by_nu_{n}"][f"{name}_nu2"]["GB_s"] / 1e3, 3)
+                               for n in (8191, 16383) for name in ("pre", "post") if f"by_nu_{n}" in hb}
+    if "c5_adjoint" in ex:
+        sm["c5_forward_backward_ms"] = ex["c5_adjoint"]["forward_backward_ms"]
+    if out.get("model"):
+        m = out["model"]
+        sm["model"] = {"predicted_best_kappa": m["predicted_best_kappa"],
+                       "measured_best_kappa": str(out["config"]["kappa"]),
+                       "max_rel_err": max(abs(v) for v in m["rel_err"].values())}
+    sm["roofline"] = {k: out["roofline"].get(k) for k in ("kernel", "bound", "frac", "share_of_iteration")}
+    return sm
+
+
+def model_prediction(kcycle, model, torch, inst, w, per, f):
+    """Calibrate T = alpha N_calls + beta N_ops (N_calls = grid launches +
+    persistent-kernel stages, one serialised step each; N_ops = N 2(1 - 3^-kappa))
+    on problems of 6-9 and 11 levels, predict the 1023^2 problem's time per cycle
+    for every kappa (default execution options, checked against a measurement
+    of the same), and its best kappa as argmin predicted time per cycle x
+    measured cycles."""
+    from paper_2010_00626_amd import fit_model
+    kappas = [1, 2, 3, 4, kcycle.KAPPA_W]
+    rows = []
+    for k in kappas:
+        for nl in (6, 7, 8, 9, 11):
+            ms, launches, stages, _ = fit_model.measure("fused", k, nl, nu=w.nu1 + w.nu2, theta=inst.theta,
+                                                        eps=inst.eps, budget_ms=40.0)
+            rows.append(((k, nl), fit_model.n_calls(launches, stages), model.n_ops_2d(k, nl), ms))
+    fitted = model.fit(rows)
+    n = inst.n
+    levels = int(round(math.log2(n + 1)))
+    Hd = kcycle.Hierarchy([(n, inst.theta, inst.eps, w.n_coarsest)], "f64")
+    v = torch.zeros_like(f)
+    pred, meas, pred_total, meas_total = {}, {}, {}, {}
+    for k in kappas:
+        key = "W" if k == kcycle.KAPPA_W else str(k)
+        ms = Hd.time_cycles(v, f, kappa=k, nu1=w.nu1, nu2=w.nu2, omega=w.omega, reps=40)
+        st = Hd.stats()
+        calls = fit_model.n_calls(st["grid_launches_per_iteration"], st["subtree_stages_per_iteration"])
+        pred[key] = fitted.predict(calls, model.n_ops_2d(k, levels))
+        meas[key] = ms
+        cyc = per[key]["f64"]["cycles"]
+        pred_total[key] = pred[key] * cyc
+        meas_total[key] = ms * cyc
+    Hd.close()
+    return {"alpha_us": round(fitted.alpha * 1e3, 4), "beta_ns_per_op": round(fitted.beta * 1e6, 6),
+            "calls": "grid launches + persistent-kernel stages", "calibration": "6-9 and 11 levels, kappa 1-4 and W",
+            "calibration_rel_err_max": round(max(abs(e) for e in fitted.rel_errors.values()), 4),
+            "predicted_ms_per_cycle": {k: round(v, 4) for k, v in pred.items()},
+            "measured_ms_per_cycle": {k: round(v, 4) for k, v in meas.items()},
+            "rel_err": {k: round((pred[k] - meas[k]) / meas[k], 4) for k in pred},
+            "predicted_best_kappa": min(pred_total, key=pred_total.get),
+            "measured_best_kappa_default_exec": min(meas_total, key=meas_total.get)}
 
 
 def hbm_kernel(kcycle, torch):
@@ -364,6 +445,23 @@ def c4_batched(inputs, kcycle, autotune, torch):
     true_z = [float(torch.linalg.vector_norm(fx - a) / torch.linalg.vector_norm(fx)) for fx, a in zip(fs, az)]
     Hz.close()
     del Hz, uz, az
+    # like for like: the per-instance FP64 loop with the same zebra smoother (fused mode, cutover 63)
+    Hzs = [kcycle.Hierarchy([p], "f64", exec=dict(coarse_cutover=63)) for p in probs]
+    for h_, x, fx in zip(Hzs, us, fs):
+        x.zero_()
+        h_.solve(x, fx, **dict(kw, maxit=3), smoother="zebra")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    itsz64 = []
+    for h_, x, fx in zip(Hzs, us, fs):
+        x.zero_()
+        iz, _, sz = h_.solve(x, fx, **kw, smoother="zebra")
+        itsz64.append(iz[0])
+        assert sz == [0]
+    torch.cuda.synchronize()
+    tlz = time.perf_counter() - t0
+    for h_ in Hzs:
+        h_.close()
     sizes = sorted(set(p[0] for p in probs))
     return {"instances": len(probs), "sizes": {str(s): sum(1 for p in probs if p[0] == s) for s in sizes},
             "unknowns": N, "kappa": 3, "batched_f32_ms": round(tb * 1e3, 2),
@@ -376,39 +474,47 @@ def c4_batched(inputs, kcycle, autotune, torch):
             "speedup_batched_f32_vs_loop_f64": round(tl / tb, 3),
             "batched_zebra_f32_ms": round(tz * 1e3, 2), "batched_zebra_max_cycles": max(itz),
             "batched_zebra_median_cycles": statistics.median(itz), "batched_zebra_max_true_relres": max(true_z),
-            "speedup_batched_zebra_f32_vs_loop_f64": round(tl / tz, 3)}
+            "per_instance_zebra_f64_loop_ms": round(tlz * 1e3, 2), "per_instance_zebra_max_cycles": max(itsz64),
+            "speedup_batched_zebra_f32_vs_zebra_loop_f64": round(tlz / tz, 3)}
 
 
 def c3_pcg(inputs, kcycle, torch):
     """4095^2, theta=3pi/8, eps=1e-5: CG preconditioned by one kappa-cycle
-    (nu=1+1), FP32 cycles with FP64 CG vectors, to 1e-8, per kappa."""
+    (nu=1+1), FP32 cycles with FP64 CG vectors, to 1e-8, per kappa; for each
+    kappa the true FP64 relative residual of the result (the library confirms
+    convergence on it) and its max-norm error against the FP64-preconditioned
+    PCG solution (whose iterates equal the oracle's to 1e-11)."""
     wl = inputs.config3()
     inst = wl.instances[0]
     n = inst.n
     f = torch.from_numpy(inst.f).to("cuda")
     u = torch.zeros_like(f)
+    u64 = torch.zeros_like(f)
+    r = torch.empty_like(f)
     Hc = kcycle.Hierarchy([(n, inst.theta, inst.eps)], "f32")
+    H64 = kcycle.Hierarchy([(n, inst.theta, inst.eps)], "f64")
+    kw = dict(nu1=1, nu2=1, omega=wl.omega, tol=wl.tol, maxit=1000)
+    nf = torch.linalg.vector_norm(f)
     out = {}
     for k in wl.kappas:
         u.zero_()
-        Hc.pcg(u, f, kappa=k, nu1=1, nu2=1, omega=wl.omega, tol=wl.tol, maxit=1000)
+        Hc.pcg(u, f, kappa=k, **kw)
         u.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        it, rr, st = Hc.pcg(u, f, kappa=k, nu1=1, nu2=1, omega=wl.omega, tol=wl.tol, maxit=1000)
+        it, rr, st = Hc.pcg(u, f, kappa=k, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        out[str(k)] = {"iterations": it[0], "relres": rr[0], "status": st[0], "ms": round(dt * 1e3, 2),
-                       "ms_per_iteration": round(dt * 1e3 / max(it[0], 1), 4), "unknowns_per_s": n * n / dt}
-    Hc.close()
-    # error of the FP32-preconditioned result against the FP64-preconditioned one (kappa = 2, same tolerance)
-    u.zero_()
-    H64 = kcycle.Hierarchy([(n, inst.theta, inst.eps)], "f64")
-    H64.pcg(u, f, kappa=2, nu1=1, nu2=1, omega=wl.omega, tol=wl.tol, maxit=1000)
-    u32 = torch.zeros_like(u)
-    Hc = kcycle.Hierarchy([(n, inst.theta, inst.eps)], "f32")
-    Hc.pcg(u32, f, kappa=2, nu1=1, nu2=1, omega=wl.omega, tol=wl.tol, maxit=1000)
-    out["2"]["err_vs_f64"] = float((u32 - u).abs().max() / u.abs().max())
+        H64.apply_A(r, u)
+        true_rel = float(torch.linalg.vector_norm(f - r) / nf)
+        u64.zero_()
+        it64, _, st64 = H64.pcg(u64, f, kappa=k, **kw)
+        out[str(k)] = {"iterations": it[0], "relres": rr[0], "true_relres_f64": true_rel, "status": st[0],
+                       "ms": round(dt * 1e3, 2), "ms_per_iteration": round(dt * 1e3 / max(it[0], 1), 4),
+                       "unknowns_per_s": round(n * n / dt), "f64_precond_iterations": it64[0],
+                       "err_vs_f64_precond": float((u - u64).abs().max() / u64.abs().max())}
+        print(f"[bench] c3 pcg kappa={k}: {it[0]} iterations, {dt * 1e3:.1f} ms, true relres {true_rel:.2e}",
+              file=sys.stderr, flush=True)
     Hc.close()
     H64.close()
     return out
@@ -498,7 +604,20 @@ def cpu_baseline(inst, w, kappa, per, cycles):
     total = per_cycle * (need + 1)   # cycles plus the final residual test (about one cycle's cost or less)
     return {"value": inst.n * inst.n / total, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
             "sample": f"{cycles} FP64 kappa={key} cycles on the full 1023^2 problem ({dt:.1f} s), "
-                      f"scaled to the {need} cycles the solve needs"}
+                      f"scaled to the {need} cycles the solve needs",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (the lscpu 'Model name' field, read from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":

@@ -5,9 +5,13 @@ For each execution mode ("paper": one kernel per operation of Algorithm 4;
 "fused": the library's default schedule) and each kappa in {1, 2, 3, 4, W},
 n = 4..13 levels (N = (2^n - 1)^2), it times back-to-back cycles, then solves
 the least-squares problem for (alpha, beta) in T = alpha * N_calls +
-beta * N_ops, with N_ops = N * 2(1 - 3^-kappa) and N_calls the launches per
-cycle of that mode (for "paper" exactly (5+nu) totalCalls(n-1) + totalCalls(n)
-- totalCalls(n-1)).  Prints one JSON object.
+beta * N_ops, with N_ops = N * 2(1 - 3^-kappa) and N_calls the serialised
+steps per cycle of that mode: grid launches plus persistent-kernel stages
+(for "paper" exactly the paper's (5+nu) totalCalls(n-1) + totalCalls(n) -
+totalCalls(n-1) launches).  As the paper cautions (Section 3.5), the work
+term's cost depends on where the data live: the fit is made over all sizes
+and separately for hierarchies inside the 256 MB Infinity Cache (up to 11
+levels in FP64) and beyond it.  Prints one JSON object.
 
 Usage: python -m paper_2010_00626_amd.fit_model [--nmax 13] [--modes paper,fused]
 """
@@ -36,9 +40,19 @@ def measure(mode: str, kappa: int, n_levels: int, nu: int = 2, theta: float = ma
     reps = int(max(3, min(200, budget_ms / max(ms1, 1e-3))))
     ms = H.time_cycles(v, f, kappa=kappa, nu1=nu // 2, nu2=nu - nu // 2, reps=reps)
     st = H.stats()
-    calls = st["grid_launches_per_iteration"] + st["subtree_launches_per_iteration"]
     H.close()
-    return ms, calls, st["subtree_stages_per_iteration"], reps
+    return ms, st["grid_launches_per_iteration"], st["subtree_stages_per_iteration"], reps
+
+
+def n_calls(grid_launches: int, persistent_stages: int) -> int:
+    """N_gpuCalls of a schedule: every grid launch and every stage (pre, post or
+    coarsest-solve operation) of the persistent kernel is one serialised step;
+    in the one-kernel-per-operation mode there are no persistent stages and
+    this is the paper's launch count."""
+    return grid_launches + persistent_stages
+
+
+CACHE_LEVELS = 11   # FP64 hierarchies up to 2047^2 (about 134 MB) stay in the 256 MB Infinity Cache
 
 
 def main(argv=None):
@@ -49,32 +63,45 @@ def main(argv=None):
     ap.add_argument("--nu", type=int, default=4)
     args = ap.parse_args(argv)
     kappas = [1, 2, 3, 4, kcycle.KAPPA_W]
-    out = {"alpha_beta_units": "ms", "nu": args.nu, "modes": {}}
+    out = {"units": "alpha in us per call, beta in ns per operation unit", "nu": args.nu,
+           "calls": "grid launches + persistent-kernel stages (the paper's launch count in the paper mode)",
+           "regimes": {"cache": f"n <= {CACHE_LEVELS} levels (FP64 hierarchy inside the 256 MB Infinity Cache)",
+                       "hbm": f"n > {CACHE_LEVELS} levels"}, "modes": {}}
     for mode in args.modes.split(","):
         rows, table = [], {}
         for k in kappas:
             key = "W" if k == kcycle.KAPPA_W else str(k)
             for nl in range(args.nmin, args.nmax + 1):
                 t0 = time.perf_counter()
-                ms, calls, stages, reps = measure(mode, k, nl, args.nu)
+                ms, grid, stages, reps = measure(mode, k, nl, args.nu)
+                calls = n_calls(grid, stages)
                 if mode == "paper":
                     expect = model.n_gpu_calls_paper(k, nl, args.nu) + (args.nu % 2)
                     assert calls == expect, (calls, expect)
                 ops = model.n_ops_2d(k, nl)
                 rows.append(((key, nl), calls, ops, ms))
                 table[f"{key},{nl}"] = {"ms": ms, "calls": calls, "persistent_stages": stages, "reps": reps}
-                print(f"[fit] {mode} kappa={key} n={nl}: {ms:.4f} ms/cycle, {calls} launches "
+                print(f"[fit] {mode} kappa={key} n={nl}: {ms:.4f} ms/cycle, {calls} calls "
                       f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
-        fit = model.fit(rows)
-        errs = {f"{k[0]},{k[1]}": round(100.0 * e, 2) for k, e in fit.rel_errors.items() if k[1] >= 8}
-        tps = {}
-        if mode == "paper" and fit.alpha > 0 and fit.beta > 0:
-            for k in (1, 2, 3, 4, math.inf):
-                ntp = model.paper_turning_point(fit.alpha, fit.beta, k, 5 + args.nu)
-                tps["W" if math.isinf(k) else str(k)] = {"n_tp": round(ntp, 2), "N_tp": round((2 ** ntp - 1) ** 2)}
-        out["modes"][mode] = {"alpha_ms": fit.alpha, "beta_ms": fit.beta, "alpha_over_beta": fit.alpha / fit.beta
-                              if fit.beta else None, "rel_errors_percent_n8plus": errs,
-                              "turning_points": tps, "measurements": table}
+        res = {"measurements": table}
+        for regime, sel in (("all", lambda nl: True), ("cache", lambda nl: nl <= CACHE_LEVELS),
+                            ("hbm", lambda nl: nl > CACHE_LEVELS)):
+            sub = [r for r in rows if sel(r[0][1])]
+            if len(sub) < 3:
+                continue
+            fit = model.fit(sub)
+            errs = {f"{k[0]},{k[1]}": round(100.0 * e, 2) for k, e in fit.rel_errors.items() if k[1] >= 8}
+            tps = {}
+            if mode == "paper" and fit.alpha > 0 and fit.beta > 0:
+                for k in (1, 2, 3, 4, math.inf):
+                    ntp = model.paper_turning_point(fit.alpha, fit.beta, k, 5 + args.nu)
+                    tps["W" if math.isinf(k) else str(k)] = {"n_tp": round(ntp, 2), "N_tp": round((2 ** ntp - 1) ** 2)}
+            res[regime] = {"alpha_us": fit.alpha * 1e3, "beta_ns": fit.beta * 1e6,
+                           "alpha_over_beta": fit.alpha / fit.beta if fit.beta else None,
+                           "rel_errors_percent_n8plus": errs,
+                           "max_abs_err_percent_n8plus": max((abs(v) for v in errs.values()), default=None),
+                           "turning_points": tps}
+        out["modes"][mode] = res
     print(json.dumps(out))
 
 

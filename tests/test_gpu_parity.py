@@ -569,8 +569,9 @@ def test_model_fit_paper_mode_counts():
     rows = []
     for kappa in (1, 2, K().KAPPA_W):
         for nl in (5, 6, 7, 8):
-            ms, calls, stages, reps = fit_model.measure("paper", kappa, nl, nu=4, budget_ms=10.0)
-            assert calls == model.n_gpu_calls_paper(kappa, nl, 4)
+            ms, grid, stages, reps = fit_model.measure("paper", kappa, nl, nu=4, budget_ms=10.0)
+            calls = fit_model.n_calls(grid, stages)
+            assert stages == 0 and calls == model.n_gpu_calls_paper(kappa, nl, 4)
             rows.append(((kappa, nl), calls, model.n_ops_2d(kappa, nl), ms))
     fit = model.fit(rows)
     assert fit.alpha > 0 and fit.beta >= 0
