@@ -74,6 +74,7 @@ struct or_hier {
     lv_d d;          /* FP64 hierarchy (semi-coarsening: the fine level only) */
     lv_s s;          /* FP32 copy used by the FP32 cycle                */
     int semi;        /* 1: x-line zebra with semi-coarsening along y    */
+    int conv;        /* 1: convection term set (nonsymmetric operator)  */
     lvs_d sd;        /* semi-coarsened levels, FP64 and FP32            */
     lvs_s ss;
     double theta, eps, omega;
@@ -96,6 +97,26 @@ void or_fine_stencil(double theta, double eps, double s[9])
     s[0] = -cross; s[1] = sn;                s[2] = cross;    /* SW  S  SE */
     s[3] = we;     s[4] = 2.0 * (1.0 + eps); s[5] = we;       /* W   C  E  */
     s[6] = cross;  s[7] = sn;                s[8] = -cross;   /* NW  N  NE */
+}
+
+/* Convection-diffusion (the nonsymmetric problem the conclusions propose):
+ * -div(D grad u) + b . grad u = f with the diffusion of the Section 4 table
+ * and a constant velocity b = (bx, by), the convection discretised by
+ * first-order upwind differences (backward along a positive velocity
+ * component, forward along a negative one), which keeps the matrix an
+ * M-matrix.  In h^2-scaled units the convection adds h |bx| + h |by| to the
+ * centre and subtracts h max(bx, 0) from the west, h max(-bx, 0) from the
+ * east, h max(by, 0) from the south and h max(-by, 0) from the north entry. */
+void or_convection_stencil(int n, double theta, double eps, double bx, double by, double s[9])
+{
+    or_fine_stencil(theta, eps, s);
+    const double h = 1.0 / (double)(n + 1);
+    const double cx = h * bx, cy = h * by;
+    s[4] = s[4] + (fabs(cx) + fabs(cy));
+    s[3] = s[3] - fmax(cx, 0.0);
+    s[5] = s[5] - fmax(-cx, 0.0);
+    s[1] = s[1] - fmax(cy, 0.0);
+    s[7] = s[7] - fmax(-cy, 0.0);
 }
 
 void or_fine_stencil_derivs(double theta, double eps, double dth[9], double deps[9])
@@ -311,9 +332,36 @@ void or_hier_apply(const or_hier* h, const double* x, double* y)
     apply_d(h->d.n[0], h->d.s[0], h->d.h2inv[0], x, y);
 }
 
+/* Replaces the operator by the convection-diffusion one.  Every level takes
+ * the stencil above at its own mesh width (coarse operators by
+ * rediscretisation): Galerkin operators R A P of the upwind operator with
+ * bilinear P and full weighting R lose the M-matrix property on coarse levels
+ * and the cycle diverges once h |b| is of order one there, while the
+ * rediscretised upwind operators keep it.  Damped Jacobi only, and a 1 x 1
+ * coarsest level (its "Cholesky factor" is the square root of a positive
+ * scalar; larger coarsest matrices are no longer symmetric). */
+int or_set_convection(or_hier* h, double bx, double by)
+{
+    if (h->semi || h->d.smoother != 0 || h->d.nc2 != 1) return OR_ERR_ARG;
+    lv_d* D = &h->d;
+    lv_s* F = &h->s;
+    for (int k = 0; k < D->L; ++k) {
+        or_convection_stencil(D->n[k], h->theta, h->eps, bx, by, D->s[k]);
+        D->wjac[k] = h->omega / (D->s[k][4] * D->h2inv[k]);
+        for (int q = 0; q < 9; ++q) F->s[k][q] = (float)D->s[k][q];
+        F->wjac[k] = (float)D->wjac[k];
+    }
+    free(D->chol); D->chol = NULL;
+    free(F->chol); F->chol = NULL;
+    if (factor_coarsest_d(D) != OR_OK || factor_coarsest_s(F) != OR_OK) return OR_BREAKDOWN;
+    h->conv = 1;
+    return OR_OK;
+}
+
 int or_set_smoother(or_hier* h, int smoother)
 {
     if (smoother != 0 && smoother != 1) return OR_ERR_ARG;
+    if (h->conv && smoother != 0) return OR_ERR_ARG;   /* convection-diffusion: damped Jacobi only */
     if (h->semi) return smoother == 1 ? OR_OK : OR_ERR_ARG;   /* always x-line zebra */
     h->d.smoother = h->s.smoother = smoother;
     return OR_OK;
@@ -541,6 +589,7 @@ int or_pcg(or_hier* h, int kappa, int nu1, int nu2, int precond_f32_flag,
     int rc = OR_OK;
     *iters = 0;
     if (kappa < 1 || nu1 < 0 || nu2 < 0 || maxit < 0) return OR_ERR_ARG;
+    if (h->conv) return OR_ERR_ARG;   /* CG needs a symmetric operator */
     double* r = (double*)malloc(m * sizeof(double));
     double* z = (double*)malloc(m * sizeof(double));
     double* p = (double*)malloc(m * sizeof(double));

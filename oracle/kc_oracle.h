@@ -80,6 +80,14 @@ void or_hier_apply(const or_hier* h, const double* x, double* y);
  * even index first) */
 int or_set_smoother(or_hier* h, int smoother);
 
+/* convection-diffusion: h^2-scaled stencil of -div(D grad u) + b . grad u
+ * (first-order upwind convection) on an n x n grid, and the switch of a
+ * hierarchy to it (every level rediscretised at its mesh width; damped Jacobi
+ * and a 1 x 1 coarsest level only, else OR_ERR_ARG; or_pcg then returns
+ * OR_ERR_ARG) */
+void or_convection_stencil(int n, double theta, double eps, double bx, double by, double s[9]);
+int or_set_convection(or_hier* h, double bx, double by);
+
 /* one zebra relaxation on the fine level in place (dir 0: x-lines, 1: y-lines) */
 void or_zebra_relax(or_hier* h, int dir, double* v, const double* f);
 /* the line-elimination tables of level `level` (1-based) for x-lines (dir 0)

@@ -70,6 +70,9 @@ def lib():
         L.or_hier_apply.argtypes = [hp, dp, dp]
         L.or_set_smoother.argtypes = [hp, C.c_int]
         L.or_set_smoother.restype = C.c_int
+        L.or_convection_stencil.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, dp]
+        L.or_set_convection.argtypes = [hp, C.c_double, C.c_double]
+        L.or_set_convection.restype = C.c_int
         L.or_zebra_relax.argtypes = [hp, C.c_int, dp, dp]
         L.or_cycle.argtypes = [hp, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, i32p, C.c_int64]
         L.or_cycle.restype = C.c_int64
@@ -105,6 +108,13 @@ def fine_stencil(theta: float, eps: float) -> np.ndarray:
     """Section 4 nine-point stencil as a 3x3 array s[b+1, a+1] (b along +y)."""
     s = np.zeros(9)
     lib().or_fine_stencil(theta, eps, _dp(s))
+    return s.reshape(3, 3)
+
+
+def convection_stencil(n: int, theta: float, eps: float, bx: float, by: float) -> np.ndarray:
+    """h^2-scaled fine stencil of -div(D grad u) + b . grad u (upwind convection), 3 x 3."""
+    s = np.zeros(9)
+    lib().or_convection_stencil(n, theta, eps, bx, by, _dp(s))
     return s.reshape(3, 3)
 
 
@@ -168,10 +178,12 @@ class Hierarchy:
     """Levels of the rotated anisotropic diffusion problem, Galerkin coarsened."""
 
     def __init__(self, n: int, theta: float, eps: float, n_coarsest: int = 1, omega: float = 0.8,
-                 smoother: str = "jacobi", coarsening: str = "full"):
+                 smoother: str = "jacobi", coarsening: str = "full", convection=None):
         """smoother: "jacobi" (damped, omega) or "zebra" (alternating line Gauss-Seidel);
         coarsening "semi": x-line zebra with coarsening along y only (the smoother is then
-        always x-line zebra, and `sizes` lists lines per level)."""
+        always x-line zebra, and `sizes` lists lines per level); convection (bx, by): the
+        convection-diffusion operator -div(D grad u) + b . grad u (upwind), damped Jacobi
+        and a 1 x 1 coarsest level only."""
         self.n, self.theta, self.eps, self.omega = n, theta, eps, omega
         self.coarsening = coarsening
         h = C.c_void_p()
@@ -186,6 +198,12 @@ class Hierarchy:
         self.smoother = smoother
         if lib().or_set_smoother(h, {"jacobi": 0, "zebra": 1}[smoother]) != OK:
             raise ValueError(f"unknown smoother {smoother}")
+        self.convection = None
+        if convection is not None:
+            bx, by = (float(c) for c in convection)
+            if lib().or_set_convection(h, bx, by) != OK:
+                raise ValueError("convection needs damped Jacobi, full coarsening and a 1 x 1 coarsest level")
+            self.convection = (bx, by)
         nl = C.c_int()
         sizes = (C.c_int * 16)()
         st = np.zeros(16 * 9)
