@@ -89,9 +89,10 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the execution-option autotuner")
     ap.add_argument("--exec", default="", help="JSON execution options for the headline configuration "
                     "(instead of the autotuned ones)")
-    ap.add_argument("--extras", default="c4,c3,c5,hbm,zebra",
+    ap.add_argument("--extras", default="c4,c3,c5,hbm,zebra,convection",
                     help="extra measurements: c4 (batched uneven), c3 (PCG 4095^2), c5 (adjoint), hbm (8191^2 and 16383^2 kernels), "
-                         "zebra (the 1023^2 problem with alternating zebra line relaxation)")
+                         "zebra (the 1023^2 problem with alternating zebra line relaxation), "
+                         "convection (1023^2 convection-diffusion per kappa)")
     return ap.parse_args()
 
 
@@ -241,6 +242,8 @@ def main():
         extras["c5_adjoint"] = c5_adjoint(inputs, torch)
     if "zebra" in ex:
         extras["zebra_c2"] = zebra_c2(inputs, kcycle, torch)
+    if "convection" in ex:
+        extras["convection_c2"] = convection_c2(inputs, kcycle, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -295,6 +298,8 @@ def summary(out, f32_best):
                                for n in (8191, 16383) for name in ("pre", "post") if f"by_nu_{n}" in hb}
     if "c5_adjoint" in ex:
         sm["c5_forward_backward_ms"] = ex["c5_adjoint"]["forward_backward_ms"]
+    if "convection_c2" in ex:
+        sm["convection_ms"] = {k: v["ms"] for k, v in ex["convection_c2"].items()}
     if out.get("model"):
         m = out["model"]
         sm["model"] = {"predicted_best_kappa": m["predicted_best_kappa"],
@@ -552,6 +557,34 @@ def zebra_c2(inputs, kcycle, torch):
             print(f"[bench] zebra {mode} kappa={key}: {it[0]} cycles, {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
         H.close()
         out[mode] = res
+    return out
+
+
+def convection_c2(inputs, kcycle, torch):
+    """Convection-diffusion (the nonsymmetric problem of the conclusions) on the
+    1023^2 grid: -div(D grad u) + b . grad u with theta = pi/6, eps = 1e-2,
+    b = (20, 10), upwind convection, rediscretised levels, damped Jacobi
+    nu = 2+2, f ~ U[-1,1] (seed 1), stand-alone FP64 to 1e-8, per kappa."""
+    w = inputs.config2()
+    n = w.instances[0].n
+    f = torch.from_numpy(w.instances[0].f).to("cuda")
+    u = torch.zeros_like(f)
+    H = kcycle.Hierarchy([(n, math.pi / 6, 1e-2)], "f64")
+    H.set_convection(20.0, 10.0)
+    out = {}
+    for k in (1, 2, 3, 4, kcycle.KAPPA_W):
+        u.zero_()
+        H.solve(u, f, kappa=k, nu1=2, nu2=2, tol=w.tol, maxit=3000)
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, rr, st = H.solve(u, f, kappa=k, nu1=2, nu2=2, tol=w.tol, maxit=3000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        key = "W" if k == kcycle.KAPPA_W else str(k)
+        out[key] = {"cycles": it[0], "status": st[0], "ms": round(dt * 1e3, 2), "unknowns_per_s": round(n * n / dt)}
+        print(f"[bench] convection kappa={key}: {it[0]} cycles, {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    H.close()
     return out
 
 

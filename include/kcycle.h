@@ -210,6 +210,23 @@ kc_status kc_grad_params_noalloc(const kc_problem* probs, int32_t count, const d
                                  const int64_t* ldl, const double* const* d_u, const int64_t* ldu, void* hip_stream,
                                  double* dtheta, double* deps);
 
+/* convection-diffusion (the nonsymmetric problem the conclusions propose):
+ * switches every instance i to -div(D grad u) + b_i . grad u with the Section 4
+ * diffusion and constant velocity b_i = (bx[i], by[i]) (host arrays of count
+ * entries), the convection by first-order upwind differences; every level
+ * takes the same operator at its own mesh width (rediscretisation, not
+ * Galerkin).  Needs n_coarsest = 1 for every instance (else KC_ERR_ARG, nothing
+ * changed); afterwards the zebra smoother is refused (KC_ERR_ARG) and kc_pcg
+ * and kc_grad_params return KC_ERR_STATE (the operator is not symmetric).
+ * bx = by = 0 gives the diffusion operator with rediscretised coarse levels.
+ * Synchronises. */
+kc_status kc_set_convection(kc_hier* h, const double* bx, const double* by);
+
+/* host-only: the h^2-scaled 3x3 stencils of every level of one problem with
+ * convection (bx, by), as kc_set_convection builds them; no GPU needed */
+kc_status kc_convection_stencils(const kc_problem* p, double bx, double by, int32_t max_levels, int32_t* nlevels,
+                                 double* stencils);
+
 /* host-only: the h^2-scaled 3x3 stencils of every level of one problem,
  * s[9*l + 3*(b+1) + (a+1)] for offset (a, b) in (x, y); no GPU needed */
 kc_status kc_level_stencils(const kc_problem* p, int32_t max_levels, int32_t* nlevels, double* stencils);

@@ -56,6 +56,25 @@ void fine_stencil(double theta, double eps, double s[9])
     std::memcpy(s, t, sizeof t);
 }
 
+// convection-diffusion -div(D grad u) + b . grad u on an n x n grid: the
+// diffusion stencil plus first-order upwind convection (backward along a
+// positive velocity component, forward along a negative one), h^2-scaled: the
+// centre gains h |bx| + h |by|, the upwind neighbours lose h max(+-b, 0).  Coarse
+// levels take the same operator at their own mesh width (rediscretisation):
+// Galerkin stencils of the upwind operator lose the M-matrix property on
+// coarse levels and the cycle diverges.
+void convection_stencil(int n, double theta, double eps, double bx, double by, double s[9])
+{
+    fine_stencil(theta, eps, s);
+    const double h = 1.0 / (double)(n + 1);
+    const double cx = h * bx, cy = h * by;
+    s[4] = s[4] + (std::fabs(cx) + std::fabs(cy));
+    s[3] = s[3] - std::fmax(cx, 0.0);
+    s[5] = s[5] - std::fmax(-cx, 0.0);
+    s[1] = s[1] - std::fmax(cy, 0.0);
+    s[7] = s[7] - std::fmax(-cy, 0.0);
+}
+
 void fine_stencil_derivs(double theta, double eps, double dth[9], double deps[9])
 {
     const double C = std::cos(theta), S = std::sin(theta);
@@ -279,6 +298,8 @@ struct Launch {
 
 struct HostInst {
     kc_problem p;
+    bool conv = false;            // convection-diffusion operator (kc_set_convection)
+    double bx = 0.0, by = 0.0;
     InstLayout il;
     int cut = 0;
     double s[MAXL][9];
@@ -358,6 +379,13 @@ struct kc_hier {
     std::string last_driver;
     std::vector<int32_t> last_iters;           // per instance, last kc_solve / kc_pcg
 };
+
+static bool any_convection(const kc_hier* h)
+{
+    for (const HostInst& hi : h->hi)
+        if (hi.conv) return true;
+    return false;
+}
 
 namespace {
 
@@ -1060,6 +1088,7 @@ kc_status prepare_call(kc_hier* h, const kc_cycle_params* c)
     kc_status s = check_cycle(c);
     if (s != KC_OK) return s;
     if (c->smoother == 1) {
+        if (any_convection(h)) return fail(KC_ERR_ARG, "convection-diffusion runs with damped Jacobi only");
         for (int i = 0; i < h->count; ++i)
             if (h->hi[i].il.n[0] > 16383) return fail(KC_ERR_ARG, "the zebra smoother takes n <= 16383");
         if (h->ex.mode == 0 && h->sub_lds_z > max_lds_bytes() - 8192)
@@ -1291,6 +1320,20 @@ kc_status kc_level_stencils(const kc_problem* p, int32_t max_levels, int32_t* nl
     return KC_OK;
 }
 
+kc_status kc_convection_stencils(const kc_problem* p, double bx, double by, int32_t max_levels, int32_t* nlevels,
+                                 double* stencils)
+{
+    if (!p || !nlevels) return fail(KC_ERR_ARG, "null argument");
+    if (!std::isfinite(bx) || !std::isfinite(by)) return fail(KC_ERR_ARG, "bx, by must be finite");
+    int L;
+    kc_status s = check_problem(*p, L);
+    if (s != KC_OK) return s;
+    *nlevels = L;
+    for (int d = 0; d < L && d < max_levels; ++d)
+        if (stencils) convection_stencil(((p->n + 1) >> d) - 1, p->theta, p->eps, bx, by, stencils + 9 * d);
+    return KC_OK;
+}
+
 // prec: the hierarchy's precision, or -1 for host-only planning
 static kc_status validate_exec(const kc_exec* e, int prec)
 {
@@ -1313,6 +1356,18 @@ static kc_status validate_exec(const kc_exec* e, int prec)
     return KC_OK;
 }
 
+// level stencils of one instance: Galerkin coarse operators of the diffusion
+// problem, or the rediscretised convection-diffusion operator
+static void level_stencils_of(HostInst& hi)
+{
+    if (hi.conv) {
+        for (int d = 0; d < hi.il.L; ++d) convection_stencil(hi.il.n[d], hi.p.theta, hi.p.eps, hi.bx, hi.by, hi.s[d]);
+        return;
+    }
+    fine_stencil(hi.p.theta, hi.p.eps, hi.s[0]);
+    for (int d = 1; d < hi.il.L; ++d) galerkin(hi.s[d - 1], hi.s[d]);
+}
+
 static void build_host(kc_hier* h, const kc_problem* probs)
 {
     h->hi.assign(h->count, HostInst());
@@ -1320,10 +1375,34 @@ static void build_host(kc_hier* h, const kc_problem* probs)
         HostInst& hi = h->hi[i];
         hi.p = probs[i];
         hi.il = h->lay.il[i];
-        fine_stencil(hi.p.theta, hi.p.eps, hi.s[0]);
-        for (int d = 1; d < hi.il.L; ++d) galerkin(hi.s[d - 1], hi.s[d]);
+        level_stencils_of(hi);
     }
 }
+
+// coarsest factors and line-solve tables of instance i, copied into the workspace
+static kc_status upload_factors(kc_hier* h, int i)
+{
+    HostInst& hi = h->hi[i];
+    std::vector<double> c64;
+    std::vector<float> c32;
+    if (!coarse_cholesky<double>(hi.p.n_coarsest, hi.s[hi.il.L - 1], c64) ||
+        !coarse_cholesky<float>(hi.p.n_coarsest, hi.s[hi.il.L - 1], c32))
+        return fail(KC_ERR_ARG, "coarsest matrix is not positive definite");
+    std::vector<double> z64;
+    std::vector<float> z32;
+    for (int d = 0; d < hi.il.L; ++d) {
+        line_tables<double>(hi.il.n[d], hi.s[d], z64);
+        line_tables<float>(hi.il.n[d], hi.s[d], z32);
+    }
+    if (hipMemcpyAsync(h->ws + hi.il.chol64, c64.data(), c64.size() * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->ws + hi.il.chol32, c32.data(), c32.size() * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->ws + hi.il.zt64, z64.data(), z64.size() * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->ws + hi.il.zt32, z32.data(), z32.size() * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return fail(KC_ERR_HIP, "upload of the coarsest factor or the line-solve tables failed");
+    return KC_OK;
+}
+
 
 kc_status kc_schedule_counts(const kc_problem* probs, int32_t count, const kc_exec* exec, const kc_cycle_params* c,
                              int64_t* grid_launches, int64_t* subtree_launches, int64_t* subtree_stages)
@@ -1409,29 +1488,9 @@ kc_status kc_create(const kc_problem* probs, int32_t count, kc_precision prec, c
     h->d_hist = (double*)(h->ws + h->lay.hist);
     if ((s = enter(h)) != KC_OK) return cleanup(s);
     build_host(h, probs);
-    // coarsest Cholesky factors
-    for (int i = 0; i < count; ++i) {
-        HostInst& hi = h->hi[i];
-        std::vector<double> c64;
-        std::vector<float> c32;
-        if (!coarse_cholesky<double>(hi.p.n_coarsest, hi.s[hi.il.L - 1], c64) ||
-            !coarse_cholesky<float>(hi.p.n_coarsest, hi.s[hi.il.L - 1], c32))
-            return cleanup(fail(KC_ERR_ARG, "coarsest matrix is not positive definite"));
-        if (hipMemcpyAsync(h->ws + hi.il.chol64, c64.data(), c64.size() * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-            hipMemcpyAsync(h->ws + hi.il.chol32, c32.data(), c32.size() * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-            hipStreamSynchronize(h->stream) != hipSuccess)
-            return cleanup(fail(KC_ERR_HIP, "upload of the coarsest factor failed"));
-        std::vector<double> z64;
-        std::vector<float> z32;
-        for (int d = 0; d < hi.il.L; ++d) {
-            line_tables<double>(hi.il.n[d], hi.s[d], z64);
-            line_tables<float>(hi.il.n[d], hi.s[d], z32);
-        }
-        if (hipMemcpyAsync(h->ws + hi.il.zt64, z64.data(), z64.size() * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-            hipMemcpyAsync(h->ws + hi.il.zt32, z32.data(), z32.size() * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-            hipStreamSynchronize(h->stream) != hipSuccess)
-            return cleanup(fail(KC_ERR_HIP, "upload of the line-solve tables failed"));
-    }
+    // coarsest Cholesky factors and line-solve tables
+    for (int i = 0; i < count; ++i)
+        if ((s = upload_factors(h, i)) != KC_OK) return cleanup(s);
     if ((s = plan_exec(h)) != KC_OK) return cleanup(s);
     fill_inst_static(h);
     set_omega(h, 0.8);
@@ -1480,6 +1539,33 @@ kc_status kc_set_exec(kc_hier* h, const kc_exec* exec)
     if ((s = upload_inst(h)) != KC_OK) return s;
     HIPCHK(hipStreamSynchronize(h->stream));
     return KC_OK;
+}
+
+kc_status kc_set_convection(kc_hier* h, const double* bx, const double* by)
+{
+    if (!h || !bx || !by) return fail(KC_ERR_ARG, "null argument");
+    for (int i = 0; i < h->count; ++i) {
+        if (!std::isfinite(bx[i]) || !std::isfinite(by[i])) return fail(KC_ERR_ARG, "bx, by must be finite");
+        if (h->hi[i].p.n_coarsest != 1)
+            return fail(KC_ERR_ARG, "convection-diffusion needs a 1 x 1 coarsest level (n_coarsest = 1)");
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    drop_graphs(h);
+    kc_status s;
+    if ((s = enter(h)) != KC_OK) return s;
+    for (int i = 0; i < h->count; ++i) {
+        HostInst& hi = h->hi[i];
+        hi.conv = true;
+        hi.bx = bx[i];
+        hi.by = by[i];
+        level_stencils_of(hi);
+        if ((s = upload_factors(h, i)) != KC_OK) return s;
+    }
+    fill_inst_static(h);
+    set_omega(h, h->omega_set);
+    if ((s = upload_inst(h)) != KC_OK) return s;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return leave(h);
 }
 
 // level-0 binding of the cycle arrays for each driver
@@ -1598,6 +1684,7 @@ kc_status kc_pcg(kc_hier* h, double* const* d_u, const int64_t* ldu, const doubl
     kc_status s;
     if ((s = check_ptrs(h, d_u, ldu, "u")) != KC_OK || (s = check_ptrs(h, d_f, ldf, "f")) != KC_OK) return s;
     if (maxit < 0 || !(tol >= 0.0)) return fail(KC_ERR_ARG, "maxit must be >= 0 and tol >= 0");
+    if (any_convection(h)) return fail(KC_ERR_STATE, "CG needs a symmetric operator (convection is set)");
     if ((s = prepare_call(h, c)) != KC_OK) return s;
     if ((s = enter(h)) != KC_OK) return s;
     const bool f32 = h->prec == KC_F32_CYCLE;
@@ -1661,6 +1748,7 @@ kc_status kc_grad_params(kc_hier* h, const double* const* d_lam, const int64_t* 
 {
     if (!h) return fail(KC_ERR_ARG, "null hierarchy");
     if (!dtheta || !deps) return fail(KC_ERR_ARG, "null outputs");
+    if (any_convection(h)) return fail(KC_ERR_STATE, "the parameter gradients are those of the diffusion operator");
     kc_status s;
     if ((s = check_ptrs(h, d_lam, ldl, "lam")) != KC_OK || (s = check_ptrs(h, d_u, ldu, "u")) != KC_OK) return s;
     if ((s = enter(h)) != KC_OK) return s;

@@ -83,6 +83,8 @@ def lib():
         L.kc_grad_params.argtypes = arr + [P(dbl), P(dbl)]
         L.kc_grad_params_noalloc.argtypes = [P(Problem), i32, P(vp), P(i64), P(vp), P(i64), vp, P(dbl), P(dbl)]
         L.kc_level_stencils.argtypes = [P(Problem), i32, P(i32), P(dbl)]
+        L.kc_convection_stencils.argtypes = [P(Problem), dbl, dbl, i32, P(i32), P(dbl)]
+        L.kc_set_convection.argtypes = [vp, P(dbl), P(dbl)]
         L.kc_schedule_counts.argtypes = [P(Problem), i32, P(Exec), P(CycleParams), P(i64), P(i64), P(i64)]
         L.kc_stats.argtypes = [vp, C.c_char_p, sz]
         L.kc_profile_iteration.argtypes = [vp, i32, P(CycleParams), i32, C.c_char_p, sz]
@@ -94,7 +96,8 @@ def lib():
         L.kc_last_error.restype = C.c_char_p
         for name in ("kc_workspace_bytes", "kc_create", "kc_destroy", "kc_set_exec", "kc_cycle", "kc_solve",
                      "kc_pcg", "kc_apply_A", "kc_residual_history", "kc_grad_params", "kc_level_stencils", "kc_schedule_counts",
-                     "kc_stats", "kc_time_stage", "kc_time_cycles", "kc_profile_iteration", "kc_grad_params_noalloc"):
+                     "kc_stats", "kc_time_stage", "kc_time_cycles", "kc_profile_iteration", "kc_grad_params_noalloc",
+                     "kc_convection_stencils", "kc_set_convection"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -162,6 +165,16 @@ def level_stencils(n: int, theta: float, eps: float, n_coarsest: int = 1) -> np.
     nl = C.c_int32()
     buf = np.zeros(16 * 9)
     _check(lib().kc_level_stencils(C.byref(p), 16, C.byref(nl), buf.ctypes.data_as(C.POINTER(C.c_double))))
+    return buf[: 9 * nl.value].reshape(nl.value, 3, 3).copy()
+
+
+def convection_stencils(n: int, theta: float, eps: float, bx: float, by: float) -> np.ndarray:
+    """h^2-scaled stencils of every level of the convection-diffusion problem (host, no GPU)."""
+    p = Problem(n, 1, theta, eps)
+    nl = C.c_int32()
+    buf = np.zeros(16 * 9)
+    _check(lib().kc_convection_stencils(C.byref(p), float(bx), float(by), 16, C.byref(nl),
+                                        buf.ctypes.data_as(C.POINTER(C.c_double))))
     return buf[: 9 * nl.value].reshape(nl.value, 3, 3).copy()
 
 
@@ -321,6 +334,15 @@ class Hierarchy:
         de = (C.c_double * self.count)()
         _check(lib().kc_grad_params(self._h, pl, ll, pu, lu, dth, de))
         return list(dth), list(de)
+
+    def set_convection(self, bx, by):
+        """Switch every instance to -div(D grad u) + b . grad u (upwind convection,
+        rediscretised levels); bx, by: one value for all instances or one per instance."""
+        bxs = [float(bx)] * self.count if np.isscalar(bx) else [float(x) for x in bx]
+        bys = [float(by)] * self.count if np.isscalar(by) else [float(x) for x in by]
+        if len(bxs) != self.count or len(bys) != self.count:
+            raise ValueError(f"expected {self.count} velocities")
+        _check(lib().kc_set_convection(self._h, (C.c_double * self.count)(*bxs), (C.c_double * self.count)(*bys)))
 
     def set_exec(self, **kw):
         e = exec_options(**kw)

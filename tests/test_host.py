@@ -241,3 +241,12 @@ def test_autograd_gradient_return_for_number_parameters():
     assert float(th.grad) == 2.0 and ep.grad.tolist() == [3.0, 3.0]
     ep2 = torch.tensor([1e-3, 2e-3], dtype=torch.float64)   # a tensor that needs no gradient
     Stub.apply(f, th.detach(), ep2).sum().backward()
+
+
+@pytest.mark.parametrize("n,theta,eps,bx,by", [(1023, math.pi / 6, 1e-2, 20.0, 10.0), (63, 0.0, 1.0, -40.0, 15.0),
+                                               (255, 2.0, 1e-4, 3.0, -8.0), (7, 1.1, 0.05, 0.0, 0.0)])
+def test_convection_stencils_match_oracle_bitwise(n, theta, eps, bx, by):
+    s = K.convection_stencils(n, theta, eps, bx, by)
+    H = O.Hierarchy(n, theta, eps, convection=(bx, by))
+    assert s.shape == H.stencils.shape
+    assert np.array_equal(s, H.stencils)
