@@ -139,6 +139,27 @@ kc_status kc_create(const kc_problem* probs, int32_t count, kc_precision prec, c
 
 kc_status kc_destroy(kc_hier* h);
 
+/* semi-coarsening (Section 4, fifth and sixth solvers): hierarchies whose
+ * levels keep the n points of a line (x) and halve the lines (y), level l
+ * holding (n + 1) / 2^(l-1) - 1 lines down to a single line; linear
+ * interpolation P along y, full weighting R = P^T / 2 along y, Galerkin
+ * stencils R A P in units of the fine h^2; relaxation by x-line zebra (the
+ * cycle parameters must give smoother = 1; every relaxation runs the lines of
+ * even index, then odd, each solved exactly); the single coarsest line is
+ * solved exactly by the same line elimination.  Every instance must have the
+ * same n <= 16383 and n_coarsest = 1 (unused).  Levels run one kernel per
+ * operation (exec.mode is set to 1; kc_set_exec refuses 0).  The other calls
+ * (kc_cycle, kc_solve, kc_pcg, FP32 hierarchies, kc_apply_A, kc_grad_params)
+ * work on these hierarchies as on the standard ones; kc_set_convection
+ * returns KC_ERR_STATE. */
+kc_status kc_workspace_bytes_semi(const kc_problem* probs, int32_t count, kc_precision prec, size_t* bytes);
+kc_status kc_create_semi(const kc_problem* probs, int32_t count, kc_precision prec, const kc_exec* exec,
+                         void* d_workspace, size_t bytes, void* hip_stream, kc_hier** out);
+
+/* host-only: the stencils of every semi-coarsened level of one problem (units
+ * of the fine h^2), s[9*l + 3*(b+1) + (a+1)]; no GPU needed */
+kc_status kc_semi_stencils(const kc_problem* p, int32_t max_levels, int32_t* nlevels, double* stencils);
+
 /* change execution options (drops captured graphs) */
 kc_status kc_set_exec(kc_hier* h, const kc_exec* exec);
 

@@ -26,7 +26,8 @@ struct LevelDev {
     void* A;
     void* B;
     void* F;
-    int32_t n;
+    int32_t n;               // lines (rows) of the level
+    int32_t nx;              // points per line (columns): n, or the fine n on semi-coarsened levels
     int32_t lda, ldb, ldf;   // leading dimensions of A, B and F
     double fscale;           // F is multiplied by fscale when loaded (h^2 for a user f, else 1)
 };
@@ -141,6 +142,8 @@ struct StageArgs {
     int32_t src, dst;         // buffer selectors for unfused kernels (0 = A, 1 = B)
     int32_t flags;            // fused kernels' shape: bit 0 = 16 x 16 tiles; bit 4 = 32 x 32 tiles; bit 5 = 8 x 8
                               // tiles; bit 1 = streaming strips, rows 16 << bits 2-3; none = 64 x 32 tiles
+    int32_t semi;             // one-kernel-per-operation launch on semi-coarsened (rectangular) levels:
+                              // transfers along y only
 };
 
 // arguments of a persistent coarse-kernel launch

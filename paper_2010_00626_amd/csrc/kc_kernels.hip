@@ -535,6 +535,107 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// semi-coarsened levels (Section 4, fifth and sixth solvers): level d has n
+// lines (rows) of nx points, x is never coarsened, and every stencil is in units
+// of the fine level's h^2 (F of every level carries the same h^2 scale).  One
+// kernel per operation on 64 x 32 tiles of (nx, n):
+//   residual      r = F - S v (the nine products south row first, west to east);
+//   restriction   F_c(J, i) = 1/4 r(2J, i) + 1/2 r(2J+1, i) + 1/4 r(2J+2, i), i.e. R = P^T / 2;
+//   prolongation  e(2J+1, i) = v_c(J, i), e(2J, i) = 1/2 v_c(J-1, i) + 1/2 v_c(J, i)
+//                 (linear interpolation along y, zero beyond the last lines);
+//   zero, add, copy as in the square case.  Relaxation is the x-line zebra kernel.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline T sload(const T* p, int ld, int ny, int nx, int j, int i)
+{
+    const T v = p[(size_t)min(max(j, 0), ny - 1) * ld + min(max(i, 0), nx - 1)];
+    return ((unsigned)j < (unsigned)ny && (unsigned)i < (unsigned)nx) ? v : T(0);
+}
+
+template <typename T, int kind>
+__global__ void __launch_bounds__(GRID_THREADS) k_semi(StageArgs a)
+{
+    const int b = blockIdx.x;
+    const int inst = find_inst(a.tile_off, a.count, b);
+    if (a.st[inst].done) return;
+    const InstDev& I = a.inst[inst];
+    const int d = a.depth;
+    const LevelDev& Lv = I.lev[d];
+    const int ny = Lv.n, nx = Lv.nx;
+    const int blk = b - a.tile_off[inst];
+    const int tiles_x = (nx + TX - 1) / TX;
+    const int x0 = (blk % tiles_x) * TX, y0 = (blk / tiles_x) * TY;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int i = x0 + tx;
+    const int lds_ = a.src ? Lv.ldb : Lv.lda;
+    const int ldd_ = a.dst ? Lv.ldb : Lv.lda;
+
+    if constexpr (kind == GK_RESTRICT || kind == GK_ZERO) {
+        // coarse lines J whose centre line 2J+1 lies in this tile
+        const LevelDev& Lc = I.lev[d + 1];
+        const int nyc = Lc.n;
+        const T* r = buf<T>(Lv, a.src);
+        for (int k = ty; k < TY / 2; k += GRID_THREADS / 64) {
+            const int J = (y0 >> 1) + k;
+            if (J >= nyc || i >= nx) continue;
+            if constexpr (kind == GK_ZERO) {
+                ((T*)Lc.A)[(size_t)J * Lc.lda + i] = T(0);
+            } else {
+                T acc = T(0);
+                acc += T(0.25) * r[(size_t)(2 * J) * lds_ + i];
+                acc += T(0.5) * r[(size_t)(2 * J + 1) * lds_ + i];
+                acc += T(0.25) * r[(size_t)(2 * J + 2) * lds_ + i];
+                ((T*)Lc.F)[(size_t)J * Lc.ldf + i] = acc;
+            }
+        }
+        return;
+    }
+    Sten<T> s;
+    s.load(P<T>::s(I, d));
+    const T fs = (T)Lv.fscale;
+    for (int k = ty; k < TY; k += GRID_THREADS / 64) {
+        const int j = y0 + k;
+        if (j >= ny || i >= nx) continue;
+        const size_t gs = (size_t)j * lds_ + i, gd = (size_t)j * ldd_ + i;
+        if constexpr (kind == GK_RESID) {
+            const T* x = buf<T>(Lv, a.src);
+            T acc = T(0);
+            acc += s.c[0] * sload(x, lds_, ny, nx, j - 1, i - 1);
+            acc += s.c[1] * sload(x, lds_, ny, nx, j - 1, i);
+            acc += s.c[2] * sload(x, lds_, ny, nx, j - 1, i + 1);
+            acc += s.c[3] * sload(x, lds_, ny, nx, j, i - 1);
+            acc += s.c[4] * sload(x, lds_, ny, nx, j, i);
+            acc += s.c[5] * sload(x, lds_, ny, nx, j, i + 1);
+            acc += s.c[6] * sload(x, lds_, ny, nx, j + 1, i - 1);
+            acc += s.c[7] * sload(x, lds_, ny, nx, j + 1, i);
+            acc += s.c[8] * sload(x, lds_, ny, nx, j + 1, i + 1);
+            buf<T>(Lv, a.dst)[gd] = fs * ((const T*)Lv.F)[(size_t)j * Lv.ldf + i] - acc;
+        } else if constexpr (kind == GK_PROLONG) {
+            const LevelDev& Lc = I.lev[d + 1];
+            const T* vc = buf<T>(Lc, a.src);
+            const int ldc = a.src ? Lc.ldb : Lc.lda, nyc = Lc.n;
+            T acc = T(0);
+            if (j & 1) {
+                acc += T(1) * vc[(size_t)(j >> 1) * ldc + i];
+            } else {
+                const int Ja = (j >> 1) - 1, Jb = j >> 1;
+                const T va = vc[(size_t)max(Ja, 0) * ldc + i], vb = vc[(size_t)min(Jb, nyc - 1) * ldc + i];
+                acc += T(0.5) * (Ja >= 0 ? va : T(0));
+                acc += T(0.5) * (Jb < nyc ? vb : T(0));
+            }
+            buf<T>(Lv, a.dst)[gd] = acc;
+        } else if constexpr (kind == GK_ADD) {
+            T* v = buf<T>(Lv, a.src);
+            v[gs] = v[gs] + buf<T>(Lv, a.dst)[gd];
+        } else if constexpr (kind == GK_COPY) {
+            buf<T>(Lv, a.dst)[gd] = buf<T>(Lv, a.src)[gs];
+        } else if constexpr (kind == GK_ZERO_SELF) {
+            ((T*)Lv.A)[(size_t)j * Lv.lda + i] = T(0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // zebra line relaxation on the levels run one kernel per operation: every line of the launch's
 // colour (lines 2 m + colour) solves its tridiagonal system exactly with its
 // neighbouring lines' current values, in place.  Forward pass:
@@ -573,7 +674,7 @@ template <typename T, int DIR>
 struct ZLine {
     gp<T> V;
     gp<const T> F, rpv, mul;
-    int n, ldv, ldf, line;
+    int n, nl, ldv, ldf, line;   // points per line, lines of the level
     T fs, lo, cm0, cm1, cm2, cp0, cp1, cp2;
     bool hm, hp;
     int Lm, Lp;
@@ -854,10 +955,10 @@ __global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
     const InstDev& I = a.inst[inst];
     const int d = a.depth;
     const LevelDev& Lv = I.lev[d];
-    const int n = Lv.n;
-    // the launch's threshold (flags) picks the mapping for this instance; the
-    // block table was sized the same way
-    const bool waves = a.flags > 0 && n >= a.flags;
+    const int n = Lv.n, nx = Lv.nx;   // lines and points per line (equal except on semi-coarsened levels)
+    // the launch's threshold (flags) picks the mapping for this instance from the
+    // line length; the block table was sized the same way
+    const bool waves = a.flags > 0 && nx >= a.flags;
     int blk = b - a.tile_off[inst];
     int line;
     if (waves) {
@@ -882,12 +983,13 @@ __global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
     z.ldf = Lv.ldf;
     z.F = glob<T>((const void*)Lv.F);
     z.fs = (T)Lv.fscale;
-    z.n = n;
+    z.n = nx;
+    z.nl = n;
     z.line = line;
     Sten<T> s;
     s.load(P<T>::s(I, d));
-    z.rpv = glob<T>((const void*)(ZT<T>::t(I, d) + (size_t)DIR * 2 * n));
-    z.mul = z.rpv + n;
+    z.rpv = glob<T>((const void*)(ZT<T>::t(I, d) + (size_t)DIR * 2 * nx));
+    z.mul = z.rpv + nx;
     z.lo = DIR == 0 ? s.c[3] : s.c[1];
     // off-line coefficients at q - 1, q, q + 1 of the previous line (m) and the next line (p), in summation order
     z.cm0 = s.c[0];
@@ -897,7 +999,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
     z.cp1 = DIR == 0 ? s.c[7] : s.c[5];
     z.cp2 = s.c[8];
     z.hm = line > 0;
-    z.hp = line + 1 < n;
+    z.hp = line + 1 < n;   // n lines
     z.Lm = z.hm ? line - 1 : line;   // clamped; values masked when absent
     z.Lp = z.hp ? line + 1 : line;
     if (waves) {
@@ -2919,6 +3021,23 @@ static hipError_t launch_unfused(GridKernel k, const StageArgs& a, int nb, hipSt
     return hipGetLastError();
 }
 
+template <typename T>
+static hipError_t launch_semi(GridKernel k, const StageArgs& a, int nb, hipStream_t s)
+{
+    const dim3 g(nb), b(GRID_THREADS);
+    switch (k) {
+    case GK_RESID: k_semi<T, GK_RESID><<<g, b, 0, s>>>(a); break;
+    case GK_RESTRICT: k_semi<T, GK_RESTRICT><<<g, b, 0, s>>>(a); break;
+    case GK_ZERO: k_semi<T, GK_ZERO><<<g, b, 0, s>>>(a); break;
+    case GK_PROLONG: k_semi<T, GK_PROLONG><<<g, b, 0, s>>>(a); break;
+    case GK_ADD: k_semi<T, GK_ADD><<<g, b, 0, s>>>(a); break;
+    case GK_COPY: k_semi<T, GK_COPY><<<g, b, 0, s>>>(a); break;
+    case GK_ZERO_SELF: k_semi<T, GK_ZERO_SELF><<<g, b, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <bool F32>
 static hipError_t launch_driver(GridKernel k, const StageArgs& a, int nb, hipStream_t s)
 {
@@ -3001,7 +3120,10 @@ hipError_t launch_grid(GridKernel k, bool f32, const StageArgs& a, int32_t nb, h
         break;
     case GK_SWEEP: case GK_RESID: case GK_RESTRICT: case GK_ZERO: case GK_PROLONG: case GK_ADD: case GK_COPY:
     case GK_NORM: case GK_ZERO_SELF:
-        e = f32 ? launch_unfused<float>(k, a, nb, s) : launch_unfused<double>(k, a, nb, s);
+        if (a.semi && k != GK_NORM && k != GK_SWEEP)
+            e = f32 ? launch_semi<float>(k, a, nb, s) : launch_semi<double>(k, a, nb, s);
+        else
+            e = f32 ? launch_unfused<float>(k, a, nb, s) : launch_unfused<double>(k, a, nb, s);
         break;
     default:
         e = f32 ? launch_driver<true>(k, a, nb, s) : launch_driver<false>(k, a, nb, s);

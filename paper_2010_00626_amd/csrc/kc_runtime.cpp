@@ -136,6 +136,47 @@ void galerkin(const double sf[9], double sc[9])
         }
 }
 
+// Galerkin stencil of the next semi-coarsened level (Section 4, fifth and sixth
+// solvers), s_c = R s P with P linear interpolation along y and R = P^T / 2,
+// every stencil in units of the fine level's h^2 (x is never coarsened).  It is
+// read off by applying P, then s, then R to a coarse unit vector on a grid of 5
+// columns and 5 coarse (11 fine) lines, with the same loop orders as the
+// definition, so each entry is rounded as the definition rounds it.
+void semi_galerkin(const double sf[9], double sc[9])
+{
+    constexpr int NX = 5, NYC = 5, NYF = 11;
+    double e[NX * NYF], ae[NX * NYF];
+    for (int j = 0; j < NYF; ++j)          // e = P e_c (gather along y)
+        for (int i = 0; i < NX; ++i) {
+            double acc = 0.0;
+            for (int J = (j - 1) / 2 - 1; J <= j / 2; ++J) {
+                const int dy = j - (2 * J + 1);
+                if (dy < -1 || dy > 1) continue;
+                const double v = (J < 0 || J >= NYC) ? 0.0 : ((J == 2 && i == 2) ? 1.0 : 0.0);
+                acc += w1(dy) * v;
+            }
+            e[j * NX + i] = acc;
+        }
+    for (int j = 0; j < NYF; ++j)          // ae = s e
+        for (int i = 0; i < NX; ++i) {
+            double acc = 0.0;
+            for (int b = -1; b <= 1; ++b)
+                for (int a = -1; a <= 1; ++a) {
+                    const int jj = j + b, ii = i + a;
+                    const double x = (jj < 0 || jj >= NYF || ii < 0 || ii >= NX) ? 0.0 : e[jj * NX + ii];
+                    acc += sf[3 * (b + 1) + (a + 1)] * x;
+                }
+            ae[j * NX + i] = acc * 1.0;
+        }
+    for (int b0 = -1; b0 <= 1; ++b0)      // s_c = R ae around coarse line 2, column 2
+        for (int a0 = -1; a0 <= 1; ++a0) {
+            const int J = 2 + b0, i = 2 + a0;
+            double acc = 0.0;
+            for (int b = -1; b <= 1; ++b) acc += (w1(b) / 2.0) * ae[(2 * J + 1 + b) * NX + i];
+            sc[3 * (b0 + 1) + (a0 + 1)] = acc;
+        }
+}
+
 // lower Cholesky factor (row-major) of the coarsest matrix of stencil s on an
 // nc x nc grid, in the arithmetic type R; the h^2 scaling of the system is a
 // power of four, so this factor is the unscaled one times a power of two
@@ -188,6 +229,8 @@ kc_status check_problem(const kc_problem& p, int& L)
 struct InstLayout {
     int L = 0;
     int n[MAXL] = {}, ld[MAXL] = {};
+    int nx[MAXL] = {};           // points per line: n, or the fine n on semi-coarsened levels
+    bool semi = false;           // levels coarsened along y only
     size_t A[MAXL] = {}, B[MAXL] = {}, F[MAXL] = {};   // cycle arrays by level (A, F of level 0 unused in F64)
     size_t chol64 = 0, chol32 = 0, ops = 0;
     size_t r = 0, z = 0, p = 0, q = 0;
@@ -214,13 +257,28 @@ int zebra_blocks(int n, int wave_n)
     const int lines = (n + 1) / 2;
     return (wave_n > 0 && n >= wave_n) ? (lines + GRID_THREADS / 32 - 1) / (GRID_THREADS / 32) : (lines + 63) / 64;
 }
+// the same for a level of `lines` lines of nx points (the mapping follows the line length)
+int zebra_blocks_lines(int lines, int nx, int wave_n)
+{
+    const int per_colour = (lines + 1) / 2;
+    return (wave_n > 0 && nx >= wave_n) ? (per_colour + GRID_THREADS / 32 - 1) / (GRID_THREADS / 32)
+                                        : (per_colour + 63) / 64;
+}
+int tiles_rect(int nx, int ny) { return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY); }
 // streaming blocks: STRIP_BLOCK_W columns x R rows, R = 16 << code
 int strip_rows_code(int n) { return n >= 4095 ? 2 : (n >= 2047 ? 1 : 0); }
 int tiles_stream(int n, int code) { return ((n + STRIP_BLOCK_W - 1) / STRIP_BLOCK_W) * ((n + (16 << code) - 1) / (16 << code)); }
 
-kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Layout& lay)
+// semi: levels coarsened along y only down to one line (every instance the same n)
+kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Layout& lay, bool semi = false)
 {
     if (!probs || count < 1) return fail(KC_ERR_ARG, "need at least one problem");
+    if (semi)
+        for (int i = 0; i < count; ++i) {
+            if (probs[i].n != probs[0].n) return fail(KC_ERR_ARG, "semi-coarsened instances must share n");
+            if (probs[i].n_coarsest != 1) return fail(KC_ERR_ARG, "semi-coarsening: n_coarsest must be 1 (unused)");
+            if (probs[i].n > 16383) return fail(KC_ERR_ARG, "semi-coarsening (x-line zebra) takes n <= 16383");
+        }
     if (prec != KC_F64 && prec != KC_F32_CYCLE) return fail(KC_ERR_ARG, "unknown precision");
     const size_t T = (prec == KC_F64) ? 8 : 4;
     size_t off = 0;
@@ -249,9 +307,15 @@ kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Lay
     for (int i = 0; i < count; ++i) {
         InstLayout& il = lay.il[i];
         check_problem(probs[i], il.L);
+        il.semi = semi;
+        if (semi) {   // down to a single line
+            il.L = 1;
+            while (((probs[i].n + 1) >> (il.L - 1)) > 2) ++il.L;
+        }
         for (int d = 0; d < il.L; ++d) {
             il.n[d] = ((probs[i].n + 1) >> d) - 1;
-            il.ld[d] = ld_of(il.n[d]);
+            il.nx[d] = semi ? probs[i].n : il.n[d];
+            il.ld[d] = ld_of(il.nx[d]);
             const size_t bytes = (size_t)il.n[d] * il.ld[d] * T;
             il.B[d] = take(bytes);
             if (d > 0 || prec == KC_F32_CYCLE) {
@@ -266,7 +330,7 @@ kc_status make_layout(const kc_problem* probs, int count, kc_precision prec, Lay
         size_t zt = 0;
         for (int d = 0; d < il.L; ++d) {
             il.zoff[d] = zt;
-            zt += 4 * (size_t)il.n[d];
+            zt += 4 * (size_t)il.nx[d];
         }
         il.zt64 = take(sizeof(double) * zt);
         il.zt32 = take(sizeof(float) * zt);
@@ -344,6 +408,7 @@ void gen_sub_call(const HostInst& h, int d, int k, bool zg, int reg_n, std::vect
 struct kc_hier {
     int count = 0;
     kc_precision prec = KC_F64;
+    bool semi = false;   // levels coarsened along y only (x-line zebra, one kernel per operation)
     kc_exec ex{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -411,6 +476,7 @@ StageArgs base_args(kc_hier* h, int table)
     a.partial = h->d_partial;
     a.hist = h->d_hist;
     a.count = h->count;
+    a.semi = h->semi ? 1 : 0;
     return a;
 }
 
@@ -521,6 +587,17 @@ void cycle_fused(kc_hier* h, const kc_cycle_params& c, int kappa, bool zg, int f
 void gen_paper(kc_hier* h, int d, int k, const kc_cycle_params& c, bool f32, int cur[], std::vector<Launch>& out)
 {
     const bool hybrid = h->ex.mode == 0;
+    if (h->semi && d == h->max_L - 1) {
+        // semi-coarsening: the coarsest level is one x-line without neighbours, solved exactly
+        // by one zebra relaxation of its only line (colour 0; the input does not enter)
+        Launch L = grid(h, GK_ZEBRA, f32, tt_zeb(d), d);
+        L.sa.src = cur[d];
+        L.sa.dst = 0;
+        L.sa.nu = 0;
+        L.sa.flags = h->ex.zebra_wave_n;
+        out.push_back(L);
+        return;
+    }
     if (!hybrid && nlist(h, lt_coarse(d)) > 0) {
         Launch L{};
         L.type = L_COARSEST;
@@ -550,7 +627,7 @@ void gen_paper(kc_hier* h, int d, int k, const kc_cycle_params& c, bool f32, int
                 Launch L = grid(h, GK_ZEBRA, f32, tt_zeb(d), d);
                 L.sa.src = cur[d];
                 L.sa.dst = color;
-                L.sa.nu = r & 1;
+                L.sa.nu = h->semi ? 0 : (r & 1);   // semi-coarsening relaxes x-lines only
                 L.sa.flags = h->ex.zebra_wave_n;   // per instance: two lines per wave at n >= this
                 out.push_back(L);
             }
@@ -641,6 +718,11 @@ kc_status build_tables(kc_hier* h, const std::vector<char>* active)
             // one-kernel-per-operation stages: levels above the instance's cut (all of them in
             // the paper-structured mode, where the cut is L)
             const bool lvl = d < L - 1 && hi.cut > d;
+            if (h->semi) {   // rectangular levels; the coarsest line is solved by the zebra kernel
+                h->tiles[tt_lvl(d)][i + 1] = lvl ? tiles_rect(hi.il.nx[d], hi.il.n[d]) : 0;
+                h->tiles[tt_zeb(d)][i + 1] = d < L ? zebra_blocks_lines(hi.il.n[d], hi.il.nx[d], h->ex.zebra_wave_n) : 0;
+                continue;
+            }
             h->tiles[tt_lvl(d)][i + 1] = lvl ? tiles_of(hi.il.n[d]) : 0;
             h->tiles[tt_zeb(d)][i + 1] = lvl ? zebra_blocks(hi.il.n[d], h->ex.zebra_wave_n) : 0;
             if (hi.cut == d && d < L) h->lists[lt_sub(d)].push_back(i);
@@ -809,6 +891,7 @@ void fill_inst_static(kc_hier* h)
             }
             LevelDev& Lv = I.lev[d];
             Lv.n = hi.il.n[d];
+            Lv.nx = hi.il.nx[d];
             Lv.lda = Lv.ldb = Lv.ldf = hi.il.ld[d];
             const bool own = d > 0 || !f64;   // FP64 level 0 binds the caller's arrays per call
             Lv.A = own ? (void*)(h->ws + hi.il.A[d]) : nullptr;
@@ -1087,6 +1170,8 @@ kc_status prepare_call(kc_hier* h, const kc_cycle_params* c)
 {
     kc_status s = check_cycle(c);
     if (s != KC_OK) return s;
+    if (h->semi && c->smoother != 1)
+        return fail(KC_ERR_ARG, "a semi-coarsened hierarchy relaxes by x-line zebra: smoother must be 1");
     if (c->smoother == 1) {
         if (any_convection(h)) return fail(KC_ERR_ARG, "convection-diffusion runs with damped Jacobi only");
         for (int i = 0; i < h->count; ++i)
@@ -1302,6 +1387,35 @@ kc_status kc_workspace_bytes(const kc_problem* probs, int32_t count, kc_precisio
     return KC_OK;
 }
 
+kc_status kc_workspace_bytes_semi(const kc_problem* probs, int32_t count, kc_precision prec, size_t* bytes)
+{
+    if (!bytes) return fail(KC_ERR_ARG, "null bytes");
+    Layout lay;
+    kc_status s = make_layout(probs, count, prec, lay, true);
+    if (s != KC_OK) return s;
+    *bytes = lay.total;
+    return KC_OK;
+}
+
+kc_status kc_semi_stencils(const kc_problem* p, int32_t max_levels, int32_t* nlevels, double* stencils)
+{
+    if (!p || !nlevels) return fail(KC_ERR_ARG, "null argument");
+    Layout lay;
+    kc_status s = make_layout(p, 1, KC_F64, lay, true);
+    if (s != KC_OK) return s;
+    const int L = lay.il[0].L;
+    *nlevels = L;
+    double cur[9];
+    fine_stencil(p->theta, p->eps, cur);
+    for (int d = 0; d < L && d < max_levels; ++d) {
+        if (stencils) std::memcpy(stencils + 9 * d, cur, sizeof cur);
+        double nxt[9];
+        semi_galerkin(cur, nxt);
+        std::memcpy(cur, nxt, sizeof cur);
+    }
+    return KC_OK;
+}
+
 kc_status kc_level_stencils(const kc_problem* p, int32_t max_levels, int32_t* nlevels, double* stencils)
 {
     if (!p || !nlevels) return fail(KC_ERR_ARG, "null argument");
@@ -1365,7 +1479,10 @@ static void level_stencils_of(HostInst& hi)
         return;
     }
     fine_stencil(hi.p.theta, hi.p.eps, hi.s[0]);
-    for (int d = 1; d < hi.il.L; ++d) galerkin(hi.s[d - 1], hi.s[d]);
+    for (int d = 1; d < hi.il.L; ++d) {
+        if (hi.il.semi) semi_galerkin(hi.s[d - 1], hi.s[d]);
+        else galerkin(hi.s[d - 1], hi.s[d]);
+    }
 }
 
 static void build_host(kc_hier* h, const kc_problem* probs)
@@ -1391,8 +1508,8 @@ static kc_status upload_factors(kc_hier* h, int i)
     std::vector<double> z64;
     std::vector<float> z32;
     for (int d = 0; d < hi.il.L; ++d) {
-        line_tables<double>(hi.il.n[d], hi.s[d], z64);
-        line_tables<float>(hi.il.n[d], hi.s[d], z32);
+        line_tables<double>(hi.il.nx[d], hi.s[d], z64);
+        line_tables<float>(hi.il.nx[d], hi.s[d], z32);
     }
     if (hipMemcpyAsync(h->ws + hi.il.chol64, c64.data(), c64.size() * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
         hipMemcpyAsync(h->ws + hi.il.chol32, c32.data(), c32.size() * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
@@ -1444,19 +1561,21 @@ kc_status kc_schedule_counts(const kc_problem* probs, int32_t count, const kc_ex
     return KC_OK;
 }
 
-kc_status kc_create(const kc_problem* probs, int32_t count, kc_precision prec, const kc_exec* exec, void* d_workspace,
-                    size_t bytes, void* hip_stream, kc_hier** out)
+static kc_status create_impl(const kc_problem* probs, int32_t count, kc_precision prec, const kc_exec* exec,
+                             void* d_workspace, size_t bytes, void* hip_stream, kc_hier** out, bool semi)
 {
     if (!out) return fail(KC_ERR_ARG, "null out");
     *out = nullptr;
     kc_hier* h = new kc_hier();
     h->count = count;
     h->prec = prec;
+    h->semi = semi;
     kc_exec_default(&h->ex);
     if (exec) h->ex = *exec;
+    if (semi) h->ex.mode = 1;   // one kernel per operation on the rectangular levels
     kc_status s = validate_exec(&h->ex, (int)prec);
     if (s != KC_OK) { delete h; return s; }
-    s = make_layout(probs, count, prec, h->lay);
+    s = make_layout(probs, count, prec, h->lay, semi);
     if (s != KC_OK) { delete h; return s; }
     if (!d_workspace || bytes < h->lay.total) { delete h; return fail(KC_ERR_WORKSPACE, "workspace missing or smaller than kc_workspace_bytes"); }
     if (((uintptr_t)d_workspace) % ALIGN != 0) { delete h; return fail(KC_ERR_WORKSPACE, "workspace must be 256-byte aligned"); }
@@ -1503,6 +1622,18 @@ kc_status kc_create(const kc_problem* probs, int32_t count, kc_precision prec, c
     return KC_OK;
 }
 
+kc_status kc_create(const kc_problem* probs, int32_t count, kc_precision prec, const kc_exec* exec, void* d_workspace,
+                    size_t bytes, void* hip_stream, kc_hier** out)
+{
+    return create_impl(probs, count, prec, exec, d_workspace, bytes, hip_stream, out, false);
+}
+
+kc_status kc_create_semi(const kc_problem* probs, int32_t count, kc_precision prec, const kc_exec* exec,
+                         void* d_workspace, size_t bytes, void* hip_stream, kc_hier** out)
+{
+    return create_impl(probs, count, prec, exec, d_workspace, bytes, hip_stream, out, true);
+}
+
 kc_status kc_destroy(kc_hier* h)
 {
     if (!h) return KC_OK;
@@ -1525,6 +1656,7 @@ kc_status kc_set_exec(kc_hier* h, const kc_exec* exec)
     if (!h || !exec) return fail(KC_ERR_ARG, "null argument");
     kc_status s = validate_exec(exec, (int)h->prec);
     if (s != KC_OK) return s;
+    if (h->semi && exec->mode != 1) return fail(KC_ERR_ARG, "a semi-coarsened hierarchy runs one kernel per operation (mode 1)");
     HIPCHK(hipStreamSynchronize(h->stream));
     drop_graphs(h);
     kc_exec old = h->ex;
@@ -1544,6 +1676,7 @@ kc_status kc_set_exec(kc_hier* h, const kc_exec* exec)
 kc_status kc_set_convection(kc_hier* h, const double* bx, const double* by)
 {
     if (!h || !bx || !by) return fail(KC_ERR_ARG, "null argument");
+    if (h->semi) return fail(KC_ERR_STATE, "convection-diffusion needs full coarsening");
     for (int i = 0; i < h->count; ++i) {
         if (!std::isfinite(bx[i]) || !std::isfinite(by[i])) return fail(KC_ERR_ARG, "bx, by must be finite");
         if (h->hi[i].p.n_coarsest != 1)

@@ -72,6 +72,9 @@ def lib():
         L.kc_exec_default.restype = None
         L.kc_workspace_bytes.argtypes = [P(Problem), i32, i32, P(sz)]
         L.kc_create.argtypes = [P(Problem), i32, i32, P(Exec), vp, sz, vp, P(vp)]
+        L.kc_workspace_bytes_semi.argtypes = [P(Problem), i32, i32, P(sz)]
+        L.kc_create_semi.argtypes = [P(Problem), i32, i32, P(Exec), vp, sz, vp, P(vp)]
+        L.kc_semi_stencils.argtypes = [P(Problem), i32, P(i32), P(dbl)]
         L.kc_destroy.argtypes = [vp]
         L.kc_set_exec.argtypes = [vp, P(Exec)]
         arr = [vp, P(vp), P(i64), P(vp), P(i64)]
@@ -97,7 +100,8 @@ def lib():
         for name in ("kc_workspace_bytes", "kc_create", "kc_destroy", "kc_set_exec", "kc_cycle", "kc_solve",
                      "kc_pcg", "kc_apply_A", "kc_residual_history", "kc_grad_params", "kc_level_stencils", "kc_schedule_counts",
                      "kc_stats", "kc_time_stage", "kc_time_cycles", "kc_profile_iteration", "kc_grad_params_noalloc",
-                     "kc_convection_stencils", "kc_set_convection"):
+                     "kc_convection_stencils", "kc_set_convection", "kc_workspace_bytes_semi", "kc_create_semi",
+                     "kc_semi_stencils"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -152,11 +156,21 @@ def _precision(p) -> int:
     return {"f64": KC_F64, "f32": KC_F32_CYCLE, "f32_cycle": KC_F32_CYCLE}.get(p, p) if isinstance(p, str) else int(p)
 
 
-def workspace_bytes(problems, precision="f64") -> int:
+def workspace_bytes(problems, precision="f64", coarsening="full") -> int:
     arr, n = _problems(problems)
     out = C.c_size_t()
-    _check(lib().kc_workspace_bytes(arr, n, _precision(precision), C.byref(out)))
+    fn = lib().kc_workspace_bytes_semi if coarsening == "semi" else lib().kc_workspace_bytes
+    _check(fn(arr, n, _precision(precision), C.byref(out)))
     return out.value
+
+
+def semi_stencils(n: int, theta: float, eps: float) -> np.ndarray:
+    """Stencils of every semi-coarsened level (units of the fine h^2; host computation, no GPU)."""
+    p = Problem(n, 1, theta, eps)
+    nl = C.c_int32()
+    buf = np.zeros(16 * 9)
+    _check(lib().kc_semi_stencils(C.byref(p), 16, C.byref(nl), buf.ctypes.data_as(C.POINTER(C.c_double))))
+    return buf[: 9 * nl.value].reshape(nl.value, 3, 3).copy()
 
 
 def level_stencils(n: int, theta: float, eps: float, n_coarsest: int = 1) -> np.ndarray:
@@ -236,7 +250,7 @@ class Hierarchy:
     precision: "f64" or "f32" (FP32 cycles, FP64 refinement / CG).
     """
 
-    def __init__(self, problems: Iterable, precision="f64", exec=None, device=None, stream=None):
+    def __init__(self, problems: Iterable, precision="f64", exec=None, device=None, stream=None, coarsening="full"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: the kappa-cycle library runs on the GPU only")
@@ -245,7 +259,10 @@ class Hierarchy:
         self._probs, self.count = _problems(problems)
         self.sizes = [self._probs[i].n for i in range(self.count)]
         self.precision = _precision(precision)
-        nbytes = workspace_bytes(list(self._probs), self.precision)
+        if coarsening not in ("full", "semi"):
+            raise ValueError("coarsening must be 'full' or 'semi' (x-line zebra, coarsening along y)")
+        self.coarsening = coarsening
+        nbytes = workspace_bytes(list(self._probs), self.precision, coarsening)
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws.data_ptr()
         aligned = (base + 255) // 256 * 256
@@ -255,8 +272,9 @@ class Hierarchy:
         handle = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
         self._e = exec if isinstance(exec, Exec) else exec_options(**(exec or {}))
         h = C.c_void_p()
-        _check(lib().kc_create(self._probs, self.count, self.precision, C.byref(self._e), C.c_void_p(aligned),
-                               nbytes, handle, C.byref(h)))
+        create = lib().kc_create_semi if coarsening == "semi" else lib().kc_create
+        _check(create(self._probs, self.count, self.precision, C.byref(self._e), C.c_void_p(aligned),
+                      nbytes, handle, C.byref(h)))
         self._h = h
 
     # ---- helpers ----

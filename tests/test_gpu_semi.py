@@ -1,0 +1,137 @@
+"""GPU parity of the semi-coarsening solvers (Section 4, fifth and sixth:
+x-line zebra relaxation, coarsening along y only, Galerkin operators, the
+single coarsest line solved exactly) against the oracle: single cycles and
+stand-alone solves bit for bit with identical cycle counts, for both line
+mappings of the zebra kernel and every kappa; PCG with identical iteration
+counts and iterates within 1e-11; FP32 cycles reaching the FP64 tolerance on
+the true residual; batches of instances with different angles."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2010_00626_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def K():
+    from paper_2010_00626_amd import kcycle
+    return kcycle
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def banner(msg):
+    print(f"[gpu-semi] {msg}", flush=True)
+
+
+@pytest.mark.parametrize("n,kappa,wave_n", [(1, 1, 63), (3, 2, 63), (15, 1, 63), (63, 2, 63), (63, 3, 0),
+                                            (127, 2 ** 31 - 1, 63), (255, 3, 0), (255, 1, 63), (511, 4, 63)])
+def test_semi_cycle_bitwise(n, kappa, wave_n):
+    banner(f"cycle n={n} kappa={kappa} zebra_wave_n={wave_n}")
+    rng = np.random.default_rng(3 * n + kappa)
+    th, ep = math.pi / 4, 1e-3
+    v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
+    H = K().Hierarchy([(n, th, ep)], exec=dict(zebra_wave_n=wave_n), coarsening="semi")
+    v = dev(v0)
+    H.cycle(v, dev(f), kappa=kappa, nu1=2, nu2=2, smoother="zebra")
+    Ho = O.Hierarchy(n, th, ep, coarsening="semi")
+    ref = Ho.cycle(v0, f, kappa=min(kappa, 64), nu1=2, nu2=2)[0]
+    assert np.array_equal(host(v), ref)
+    H.cycle(v, dev(f), kappa=kappa, nu1=2, nu2=2, smoother="zebra")   # replay
+    assert np.array_equal(host(v), Ho.cycle(ref, f, kappa=min(kappa, 64), nu1=2, nu2=2)[0])
+    H.close()
+
+
+@pytest.mark.parametrize("kappa,theta", [(1, 0.05), (2, math.pi / 4), (3, 1.2), (2 ** 31 - 1, math.pi / 4)])
+def test_semi_solve_bitwise(kappa, theta):
+    n, ep = 255, 1e-5
+    banner(f"solve n={n} kappa={kappa} theta={theta}")
+    f = inputs.uniform_rhs(np.random.default_rng(kappa), n)
+    Ho = O.Hierarchy(n, theta, ep, coarsening="semi")
+    u_ref, rc, it_ref, hist = Ho.solve(f, kappa=min(kappa, 64), nu1=2, nu2=2, tol=1e-8, maxit=3000)
+    assert rc == O.OK
+    assert np.all(np.abs(np.asarray(hist) - 1e-8) > 1e-12 * 1e-8)
+    H = K().Hierarchy([(n, theta, ep)], coarsening="semi")
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    it, rr, st = H.solve(u, dev(f), kappa=kappa, nu1=2, nu2=2, tol=1e-8, maxit=3000, smoother="zebra")
+    assert st == [0] and it[0] == it_ref
+    assert np.allclose(H.residual_history(0), hist, rtol=1e-14, atol=0.0)
+    assert np.array_equal(host(u), u_ref)
+    H.close()
+
+
+@pytest.mark.parametrize("kappa", [1, 2, 3])
+def test_semi_pcg_and_fp32(kappa):
+    n, th, ep = 255, 3 * math.pi / 8, 1e-5
+    banner(f"pcg n={n} kappa={kappa}")
+    f = inputs.gaussian_sum_rhs(5, n)
+    Ho = O.Hierarchy(n, th, ep, coarsening="semi")
+    u_ref, rc, it_ref, hist = Ho.pcg(f, kappa=kappa, nu1=2, nu2=2, tol=1e-8, maxit=300)
+    assert rc == O.OK
+    H = K().Hierarchy([(n, th, ep)], coarsening="semi")
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    it, rr, st = H.pcg(u, dev(f), kappa=kappa, nu1=2, nu2=2, tol=1e-8, maxit=300, smoother="zebra")
+    assert st == [0] and it[0] == it_ref
+    assert np.allclose(H.residual_history(0), hist[:it[0] + 1], rtol=1e-14, atol=0.0)
+    assert relmax(host(u), u_ref) <= 1e-11
+    H.close()
+    H32 = K().Hierarchy([(n, th, ep)], "f32", coarsening="semi")
+    u.zero_()
+    it, rr, st = H32.pcg(u, dev(f), kappa=kappa, nu1=2, nu2=2, tol=1e-8, maxit=300, smoother="zebra")
+    up_ref, rc, itp, _ = Ho.pcg(f, kappa=kappa, nu1=2, nu2=2, tol=1e-8, maxit=300, precond_f32=True)
+    assert st == [0] and abs(it[0] - itp) <= 1
+    assert np.linalg.norm(f - Ho.apply(host(u))) / np.linalg.norm(f) < 1e-8
+    u.zero_()
+    it, rr, st = H32.solve(u, dev(f), kappa=kappa, nu1=2, nu2=2, tol=1e-8, maxit=3000, smoother="zebra")
+    u_ir, rc, it_ir, _ = Ho.ir_solve(f, kappa=kappa, nu1=2, nu2=2, tol=1e-8, maxit=3000)
+    assert st == [0] and rc == O.OK and abs(it[0] - it_ir) <= 1
+    assert np.linalg.norm(f - Ho.apply(host(u))) / np.linalg.norm(f) < 1e-8
+    H32.close()
+
+
+def test_semi_batch_and_refusals():
+    banner("batch of angles, refusals")
+    KK = K()
+    n = 127
+    specs = [(n, 0.02, 1e-4), (n, math.pi / 2, 1e-2), (n, 0.8, 1.0)]
+    rng = np.random.default_rng(8)
+    fs = [inputs.uniform_rhs(rng, n) for _ in specs]
+    H = KK.Hierarchy(specs, coarsening="semi")
+    us = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for _ in specs]
+    iters, relres, status = H.solve(us, [dev(f) for f in fs], kappa=2, nu1=2, nu2=2, tol=1e-9, maxit=3000,
+                                    smoother="zebra")
+    assert status == [0] * len(specs)
+    for k, (s, f) in enumerate(zip(specs, fs)):
+        u_ref, rc, it_ref, _ = O.Hierarchy(*s, coarsening="semi").solve(f, kappa=2, nu1=2, nu2=2, tol=1e-9,
+                                                                         maxit=3000)
+        assert iters[k] == it_ref and np.array_equal(host(us[k]), u_ref), k
+    with pytest.raises(KK.KCycleError):
+        H.solve(us, [dev(f) for f in fs], kappa=2, smoother="jacobi")
+    with pytest.raises(KK.KCycleError):
+        H.set_exec(mode="fused")
+    with pytest.raises(KK.KCycleError):
+        H.set_convection(1.0, 1.0)
+    H.close()
+    with pytest.raises(KK.KCycleError):
+        KK.Hierarchy([(127, 0.3, 1e-3), (63, 0.3, 1e-3)], coarsening="semi")

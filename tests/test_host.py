@@ -250,3 +250,25 @@ def test_convection_stencils_match_oracle_bitwise(n, theta, eps, bx, by):
     H = O.Hierarchy(n, theta, eps, convection=(bx, by))
     assert s.shape == H.stencils.shape
     assert np.array_equal(s, H.stencils)
+
+
+@pytest.mark.parametrize("n,theta,eps", [(1023, math.pi / 4, 1e-5), (63, 0.0, 1e-3), (255, 1.3, 0.2), (1, 0.5, 1.0)])
+def test_semi_stencils_match_oracle_bitwise(n, theta, eps):
+    s = K.semi_stencils(n, theta, eps)
+    H = O.Hierarchy(n, theta, eps, coarsening="semi")
+    assert s.shape == H.stencils.shape
+    assert np.array_equal(s, H.stencils)
+
+
+def test_semi_workspace_and_arguments():
+    """Semi-coarsened layouts hold n-point lines on every level (more bytes than
+    full coarsening) and need one n for the whole batch and n_coarsest = 1."""
+    full = K.workspace_bytes([(1023, 0.3, 1e-3)], "f64")
+    semi = K.workspace_bytes([(1023, 0.3, 1e-3)], "f64", coarsening="semi")
+    assert semi > full
+    with pytest.raises(K.KCycleError):
+        K.workspace_bytes([(255, 0.3, 1e-3), (127, 0.3, 1e-3)], "f64", coarsening="semi")
+    with pytest.raises(K.KCycleError):
+        K.workspace_bytes([(255, 0.3, 1e-3, 3)], "f64", coarsening="semi")
+    with pytest.raises(K.KCycleError):
+        K.workspace_bytes([(32767, 0.3, 1e-3)], "f64", coarsening="semi")
