@@ -61,8 +61,13 @@ def main(argv=None):
     ap.add_argument("--nmax", type=int, default=13)
     ap.add_argument("--modes", default="paper,fused")
     ap.add_argument("--nu", type=int, default=4)
+    ap.add_argument("--from-json", default="", help="refit the measurements of an earlier run's output (no GPU)")
     args = ap.parse_args(argv)
     kappas = [1, 2, 3, 4, kcycle.KAPPA_W]
+    stored = None
+    if args.from_json:
+        with open(args.from_json) as fh:
+            stored = json.load(fh)
     out = {"units": "alpha in us per call, beta in ns per operation unit", "nu": args.nu,
            "calls": "grid launches + persistent-kernel stages (the paper's launch count in the paper mode)",
            "regimes": {"cache": f"n <= {CACHE_LEVELS} levels (FP64 hierarchy inside the 256 MB Infinity Cache)",
@@ -73,7 +78,12 @@ def main(argv=None):
             key = "W" if k == kcycle.KAPPA_W else str(k)
             for nl in range(args.nmin, args.nmax + 1):
                 t0 = time.perf_counter()
-                ms, grid, stages, reps = measure(mode, k, nl, args.nu)
+                if stored is not None:
+                    m = stored["modes"][mode]["measurements"][f"{key},{nl}"]
+                    ms, calls, stages, reps = m["ms"], m["calls"], m["persistent_stages"], m["reps"]
+                    grid = calls - stages
+                else:
+                    ms, grid, stages, reps = measure(mode, k, nl, args.nu)
                 calls = n_calls(grid, stages)
                 if mode == "paper":
                     expect = model.n_gpu_calls_paper(k, nl, args.nu) + (args.nu % 2)
@@ -89,18 +99,21 @@ def main(argv=None):
             sub = [r for r in rows if sel(r[0][1])]
             if len(sub) < 3:
                 continue
-            fit = model.fit(sub)
-            errs = {f"{k[0]},{k[1]}": round(100.0 * e, 2) for k, e in fit.rel_errors.items() if k[1] >= 8}
-            tps = {}
-            if mode == "paper" and fit.alpha > 0 and fit.beta > 0:
-                for k in (1, 2, 3, 4, math.inf):
-                    ntp = model.paper_turning_point(fit.alpha, fit.beta, k, 5 + args.nu)
-                    tps["W" if math.isinf(k) else str(k)] = {"n_tp": round(ntp, 2), "N_tp": round((2 ** ntp - 1) ** 2)}
-            res[regime] = {"alpha_us": fit.alpha * 1e3, "beta_ns": fit.beta * 1e6,
-                           "alpha_over_beta": fit.alpha / fit.beta if fit.beta else None,
-                           "rel_errors_percent_n8plus": errs,
-                           "max_abs_err_percent_n8plus": max((abs(v) for v in errs.values()), default=None),
-                           "turning_points": tps}
+            for rel in (False, True):
+                fit = model.fit(sub, relative=rel)
+                errs = {f"{k[0]},{k[1]}": round(100.0 * e, 2) for k, e in fit.rel_errors.items() if k[1] >= 8}
+                tps = {}
+                if mode == "paper" and fit.alpha > 0 and fit.beta > 0:
+                    for k in (1, 2, 3, 4, math.inf):
+                        ntp = model.paper_turning_point(fit.alpha, fit.beta, k, 5 + args.nu)
+                        tps["W" if math.isinf(k) else str(k)] = {"n_tp": round(ntp, 2),
+                                                                 "N_tp": round((2 ** ntp - 1) ** 2)}
+                res[regime + ("_relative" if rel else "")] = {
+                    "alpha_us": fit.alpha * 1e3, "beta_ns": fit.beta * 1e6,
+                    "alpha_over_beta": fit.alpha / fit.beta if fit.beta else None,
+                    "rel_errors_percent_n8plus": errs,
+                    "max_abs_err_percent_n8plus": max((abs(v) for v in errs.values()), default=None),
+                    "turning_points": tps}
         out["modes"][mode] = res
     print(json.dumps(out))
 

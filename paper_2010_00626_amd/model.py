@@ -86,17 +86,26 @@ class Fit:
         return predict(self.alpha, self.beta, calls, ops)
 
 
-def fit(samples: Iterable[tuple]) -> Fit:
+def fit(samples: Iterable[tuple], relative: bool = False) -> Fit:
     """Least squares for (alpha, beta) over samples (key, calls, ops, time),
     both constrained to be non-negative (a per-call cost and a per-operation
-    cost cannot be negative; with few samples the unconstrained fit can be)."""
+    cost cannot be negative; with few samples the unconstrained fit can be).
+    relative=True minimises the relative errors (each row divided by its
+    time), the quantity Table 2 reports, instead of the absolute ones, which
+    the largest runs dominate."""
     rows = list(samples)
     M = np.array([[r[1], r[2]] for r in rows], dtype=np.float64)
     t = np.array([r[3] for r in rows], dtype=np.float64)
+    if relative:
+        M = M / t[:, None]
+        t = np.ones_like(t)
     (alpha, beta), *_ = np.linalg.lstsq(M, t, rcond=None)
     if alpha < 0 or beta < 0:
         from scipy.optimize import nnls
         (alpha, beta), _ = nnls(M, t)
+    rows_t = np.array([r[3] for r in rows], dtype=np.float64)
+    if relative:
+        M = M * rows_t[:, None]
     errs = {r[0]: (predict(alpha, beta, r[1], r[2]) - r[3]) / r[3] for r in rows}
     return Fit(float(alpha), float(beta), errs)
 

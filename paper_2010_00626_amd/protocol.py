@@ -9,6 +9,9 @@ until the L2 norm of the error has dropped by 1e8; FP64 throughout.
   one relaxation per direction before and after the coarse correction):
   eps = 1e-5 and angles 10, 30, 45, 60, 80 degrees, stand-alone and MGCG, at a
   chosen number of levels (the paper uses 14).
+* Tables 7 and 8 (x-line zebra relaxation, two relaxations before and after
+  the coarse correction, coarsening along y only, Galerkin operators): the
+  same angles and eps, stand-alone and MGCG, at a chosen number of levels.
 
 Stand-alone: with f = 0 the exact solution is 0, so the error after k cycles
 is v_k itself.  Cycles run in chunks (one graph launch of `chunk` cycles, timed
@@ -26,7 +29,7 @@ chunks); MGCG total = wall time of one run of exactly k iterations (setup and
 host polling included, as the paper's totals include theirs).
 
 Usage: python -m paper_2010_00626_amd.protocol [--tables] [--sweep 9,13] [--zebra-levels 12] [--zebra-exec JSON]
-       [--maxc 40000]
+       [--semi-levels 12] [--angles 10,30,45,60,80] [--solvers standalone,mgcg] [--maxc 40000]
 Prints one JSON object per result line and a summary object at the end.
 """
 from __future__ import annotations
@@ -114,17 +117,18 @@ def mgcg(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, kmax: int = 4000, s
 
 
 def run(levels: int, theta: float, eps: float, kappas, which: str, seed: int, maxc: int,
-        smoother: str = "jacobi", exec_opts: dict | None = None) -> list:
+        smoother: str = "jacobi", exec_opts: dict | None = None, coarsening: str = "full") -> list:
     import torch
     n = 2 ** levels - 1
     v0 = torch.from_numpy(inputs.uniform_rhs(np.random.default_rng(seed), n)).to("cuda")
-    H = kcycle.Hierarchy([(n, theta, eps)], "f64", exec=exec_opts)
+    H = kcycle.Hierarchy([(n, theta, eps)], "f64", exec=exec_opts, coarsening=coarsening)
     out = []
     for k in kappas:
         t0 = time.perf_counter()
         r = (standalone(H, v0, k, maxc=maxc, smoother=smoother) if which == "standalone"
              else mgcg(H, v0, k, smoother=smoother))
-        r.update({"solver": which, "smoother": smoother, "exec": exec_opts or {}, "levels": levels, "n": n,
+        r.update({"solver": which, "smoother": smoother, "coarsening": coarsening, "exec": exec_opts or {},
+                  "levels": levels, "n": n,
                   "theta": theta, "eps": eps,
                   "kappa": _key(k),
                   "unknowns_per_s": (n * n / (r["total_ms"] * 1e-3)) if r.get("total_ms") else None,
@@ -147,8 +151,11 @@ def main(argv=None):
     ap.add_argument("--zebra-kappas", default="1,2,3,4,W")
     ap.add_argument("--zebra-exec", default="{}",
                     help='execution options of the zebra runs as JSON, e.g. \'{"mode": "paper"}\' (default: fused)')
+    ap.add_argument("--semi-levels", type=int, default=0,
+                    help="Tables 7 and 8 (x-line zebra, coarsening along y) at this many levels")
+    ap.add_argument("--solvers", default="standalone,mgcg", help="solvers of the zebra and semi tables")
     a = ap.parse_args(argv)
-    res = {"tables": [], "sweep": [], "zebra": []}
+    res = {"tables": [], "sweep": [], "zebra": [], "semi": []}
     if a.tables:
         for which in ("standalone", "mgcg"):
             res["tables"] += run(12, math.pi / 4, 1e-4, KAPPAS, which, a.seed, a.maxc)
@@ -158,9 +165,15 @@ def main(argv=None):
     if a.zebra_levels:
         zk = [kcycle.KAPPA_W if x == "W" else int(x) for x in a.zebra_kappas.split(",")]
         for deg in [float(x) for x in a.angles.split(",")]:
-            for which in ("standalone", "mgcg"):
+            for which in a.solvers.split(","):
                 res["zebra"] += run(a.zebra_levels, math.radians(deg), 1e-5, zk, which, a.seed, a.maxc, "zebra",
                                     json.loads(a.zebra_exec))
+    if a.semi_levels:
+        zk = [kcycle.KAPPA_W if x == "W" else int(x) for x in a.zebra_kappas.split(",")]
+        for deg in [float(x) for x in a.angles.split(",")]:
+            for which in a.solvers.split(","):
+                res["semi"] += run(a.semi_levels, math.radians(deg), 1e-5, zk, which, a.seed, a.maxc, "zebra",
+                                   None, "semi")
     print(json.dumps({"summary": res}))
 
 

@@ -69,6 +69,21 @@ def run(args) -> None:
     del x, y
     torch.cuda.empty_cache()
 
+    if args.size:
+        # the fine-level fused kernels alone on an n x n FP64 problem far beyond the Infinity
+        # Cache: `cycles` launches each of the pre-part and the post-part at nu = 2
+        n = args.size
+        H = kcycle.Hierarchy([(n, math.pi / 4, 1e-4)], "f64", exec=json.loads(args.exec) if args.exec else None)
+        f = torch.zeros((n, n), dtype=torch.float64, device="cuda").uniform_(-1, 1)
+        u = torch.zeros_like(f)
+        H.solve(u, f, kappa=1, tol=0.0, maxit=1)   # binds the arrays
+        out = {}
+        for name, which in (("pre", 0), ("post", 1)):
+            ms, b = H.time_stage(which, kappa=1, nu1=2, nu2=2, reps=args.cycles)
+            out[name] = {"ms": ms, "algorithmic_bytes": b}
+        torch.cuda.synchronize()
+        print(json.dumps(out), flush=True)
+        return
     w = inputs.config2()
     inst = w.instances[0]
     n = inst.n
@@ -159,6 +174,7 @@ def main(argv=None):
     r.add_argument("--kappa", default="2")
     r.add_argument("--exec", default="", help="JSON execution options")
     r.add_argument("--cycles", type=int, default=20)
+    r.add_argument("--size", type=int, default=0, help="fine-level kernels alone on an n x n FP64 grid (e.g. 8191)")
     s = sub.add_parser("summarise")
     s.add_argument("dir_fetch")
     s.add_argument("dir_write")
