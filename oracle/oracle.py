@@ -20,6 +20,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# a separately built copy (e.g. with sanitizers) may be named by KC_ORACLE_LIB
+_LIB_PATH = os.environ.get("KC_ORACLE_LIB") or _LIB_PATH
 
 OP_CALL, OP_SOLVE, OP_RELAX, OP_RESID, OP_RESTR, OP_ZERO, OP_PROL, OP_ADD = range(1, 9)
 OK, NOT_CONVERGED, DIVERGED, BREAKDOWN = 0, 1, 2, 3
@@ -31,7 +33,10 @@ KIND_KAPPA, KIND_GAMMA, KIND_F = 0, 1, 2
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no fused multiply-add)."""
     src = os.path.join(_HERE, "kc_oracle.c")
-    deps = [src, os.path.join(_HERE, "kc_oracle.h"), os.path.join(_HERE, "kc_oracle_levels.inc")]
+    deps = [src, os.path.join(_HERE, "kc_oracle.h"), os.path.join(_HERE, "kc_oracle_levels.inc"),
+            os.path.join(_HERE, "kc_oracle_semi.inc")]
+    if os.environ.get("KC_ORACLE_LIB"):
+        return _LIB_PATH
     if not force and os.path.exists(_LIB_PATH):
         if os.path.getmtime(_LIB_PATH) >= max(os.path.getmtime(d) for d in deps):
             return _LIB_PATH

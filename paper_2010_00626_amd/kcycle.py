@@ -15,7 +15,7 @@ from typing import Iterable, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libkcycle.so")
+LIB_PATH = os.environ.get("KC_LIBRARY") or os.path.join(_HERE, "libkcycle.so")   # KC_LIBRARY: another build of it
 
 KC_OK, KC_NOT_CONVERGED, KC_DIVERGED, KC_BREAKDOWN = 0, 1, 2, 3
 KC_ERR_ARG, KC_ERR_HIP, KC_ERR_WORKSPACE, KC_ERR_NONFINITE, KC_ERR_STATE = -1, -2, -3, -4, -5
