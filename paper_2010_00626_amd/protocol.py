@@ -65,7 +65,11 @@ def standalone(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, chunk: int = 
         ms = H.time_cycles(v, f, kappa=kappa, nu1=nu, nu2=nu, omega=omega, reps=chunk - 1,
                            smoother=smoother)   # chunk cycles in all
         per_cycle.append(ms)
-        if float(torch.linalg.vector_norm(v)) / e0 < TARGET:
+        err = float(torch.linalg.vector_norm(v)) / e0
+        if (done // chunk) % 16 == 0:   # progress of long runs
+            print(f"[protocol] kappa={_key(kappa)}: {done + chunk} cycles, error {err:.3e}, {ms:.3f} ms per cycle",
+                  file=sys.stderr, flush=True)
+        if err < TARGET:
             v.copy_(start)
             for j in range(chunk):
                 H.cycle(v, f, kappa=kappa, nu1=nu, nu2=nu, omega=omega, smoother=smoother)
@@ -93,6 +97,8 @@ def mgcg(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, kmax: int = 4000, s
             u.zero_()
             H.pcg(u, b, kappa=kappa, nu1=nu, nu2=nu, omega=omega, tol=0.0, maxit=k, smoother=smoother)
             cache[k] = float(torch.linalg.vector_norm(u - v0)) / e0
+            print(f"[protocol] mgcg kappa={_key(kappa)}: {k} iterations, error {cache[k]:.3e}", file=sys.stderr,
+                  flush=True)
         return cache[k]
 
     hi = 8
@@ -154,6 +160,8 @@ def main(argv=None):
     ap.add_argument("--semi-levels", type=int, default=0,
                     help="Tables 7 and 8 (x-line zebra, coarsening along y) at this many levels")
     ap.add_argument("--solvers", default="standalone,mgcg", help="solvers of the zebra and semi tables")
+    ap.add_argument("--standalone-kappas", default="", help="kappas of the stand-alone zebra/semi runs (default: --zebra-kappas)")
+    ap.add_argument("--mgcg-kappas", default="", help="kappas of the MGCG zebra/semi runs (default: --zebra-kappas)")
     a = ap.parse_args(argv)
     res = {"tables": [], "sweep": [], "zebra": [], "semi": []}
     if a.tables:
@@ -162,18 +170,20 @@ def main(argv=None):
     for lv in [int(x) for x in a.sweep.split(",") if x]:
         for e in [float(x) for x in a.eps.split(",")]:
             res["sweep"] += run(lv, math.pi / 4, e, KAPPAS, "standalone", a.seed, a.maxc)
+    def kappas_of(which: str) -> list:
+        spec = {"standalone": a.standalone_kappas, "mgcg": a.mgcg_kappas}[which] or a.zebra_kappas
+        return [kcycle.KAPPA_W if x == "W" else int(x) for x in spec.split(",")]
+
     if a.zebra_levels:
-        zk = [kcycle.KAPPA_W if x == "W" else int(x) for x in a.zebra_kappas.split(",")]
         for deg in [float(x) for x in a.angles.split(",")]:
             for which in a.solvers.split(","):
-                res["zebra"] += run(a.zebra_levels, math.radians(deg), 1e-5, zk, which, a.seed, a.maxc, "zebra",
-                                    json.loads(a.zebra_exec))
+                res["zebra"] += run(a.zebra_levels, math.radians(deg), 1e-5, kappas_of(which), which, a.seed, a.maxc,
+                                    "zebra", json.loads(a.zebra_exec))
     if a.semi_levels:
-        zk = [kcycle.KAPPA_W if x == "W" else int(x) for x in a.zebra_kappas.split(",")]
         for deg in [float(x) for x in a.angles.split(",")]:
             for which in a.solvers.split(","):
-                res["semi"] += run(a.semi_levels, math.radians(deg), 1e-5, zk, which, a.seed, a.maxc, "zebra",
-                                   None, "semi")
+                res["semi"] += run(a.semi_levels, math.radians(deg), 1e-5, kappas_of(which), which, a.seed, a.maxc,
+                                   "zebra", None, "semi")
     print(json.dumps({"summary": res}))
 
 
