@@ -16,9 +16,10 @@
 //
 // Grid-wide kernels work on tiles (8 x 8 to 64 x 32) or row strips of one
 // level of every instance in a batch (blockIdx -> instance by a prefix table).
-// Reductions are deterministic: one partial per block, summed in a fixed order
-// by a finalize kernel (one workgroup per instance), which also applies the
-// solver's decision (stop test, CG scalars) to the instance's state.  Calls
+// Reductions are deterministic Dot2 sums: one (value, error) partial per block,
+// merged in a fixed order by a finalize kernel (one workgroup per instance),
+// which also applies the solver's decision (stop test, CG scalars) to the
+// instance's state.  Calls
 // below a cutover level run in a persistent kernel, one workgroup per instance
 // with the levels in LDS.
 #include <math.h>
