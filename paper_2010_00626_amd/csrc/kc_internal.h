@@ -162,6 +162,20 @@ struct SubArgs {
     int32_t wave_n;           // levels with n <= wave_n are run by one wave
     int32_t smoother;         // 0 damped Jacobi, 1 alternating zebra line relaxation
     double* hist;
+    // single-instance launch on an internal level (the library's own arrays): what the
+    // kernel would otherwise read from the instance table before it can issue its loads
+    // (op lists of the two calls, the top level's arrays, the coarsest factor); ops1 is
+    // null when the kernel reads them from the table
+    const uint32_t* ops1;
+    const uint32_t* ops2;
+    int32_t n1, n2;           // op counts of the first and the second call (0: none)
+    int32_t n0;               // size of the top level
+    int32_t sub_lds;          // LDS elements of the instance's levels
+    const void* F0;           // top level's right-hand side and current estimate
+    void* A0;
+    int32_t ldf0, lda0;
+    double fs0;               // fscale of F0
+    const void* chol0;        // coarsest factor in the hierarchy's precision
 };
 
 // kernel launchers (kc_kernels.hip)

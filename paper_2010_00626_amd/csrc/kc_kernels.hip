@@ -1848,6 +1848,22 @@ __device__ __forceinline__ T sten_win(const T (&s)[9], const T (&w)[U + 2][3], i
     return acc;
 }
 
+// the U stencil sums of a window at once, coefficient by coefficient: each
+// sum takes the same operations in the same order as sten_win, and the U
+// independent sums are interleaved so that their latencies overlap
+template <typename T, int U>
+__device__ __forceinline__ void sten_win_all(const T (&s)[9], const T (&w)[U + 2][3], T (&acc)[U])
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = T(0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[u] += s[3 * b + e] * w[u + b][e];
+}
+
 // y = x + w (F - S x) (Jacobi), or y = w F on a zero guess
 template <typename T, int N, int NB>
 __device__ __noinline__ void ph_sweep(clds<T> __restrict__ x, lds<T> __restrict__ y, clds<T> __restrict__ F,
@@ -1869,10 +1885,12 @@ __device__ __noinline__ void ph_sweep(clds<T> __restrict__ x, lds<T> __restrict_
         for (int k = 0; k < 9; ++k) s[k] = sc[k];
         T w[U + 2][3];
         load_rows<T, N, U>(x, j0, cc, w);
+        T acc[U];
+        sten_win_all<T, U>(s, w, acc);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const T f = F[(min(j0 + u, N - 1) + 1) * P + cc + 1];
-            val[u] = w[u + 1][1] + om * (f - sten_win<T, U>(s, w, u));
+            val[u] = w[u + 1][1] + om * (f - acc[u]);
         }
     }
     if (c < N) {
@@ -1898,9 +1916,10 @@ __device__ __noinline__ void ph_resid(clds<T> __restrict__ x, lds<T> __restrict_
     for (int k = 0; k < 9; ++k) s[k] = sc[k];
     T w[U + 2][3];
     load_rows<T, N, U>(x, j0, cc, w);
-    T val[U];
+    T val[U], acc[U];
+    sten_win_all<T, U>(s, w, acc);
 #pragma unroll
-    for (int u = 0; u < U; ++u) val[u] = F[(min(j0 + u, N - 1) + 1) * P + cc + 1] - sten_win<T, U>(s, w, u);
+    for (int u = 0; u < U; ++u) val[u] = F[(min(j0 + u, N - 1) + 1) * P + cc + 1] - acc[u];
     if (c < N) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -2185,6 +2204,23 @@ __device__ __forceinline__ T wsten(const T (&s)[9], const WRow<T>& S, const WRow
     return acc;
 }
 
+// the stencil sums of all U rows of a lane at once (each as wsten, the rows interleaved)
+template <typename T, int U>
+__device__ __forceinline__ void wsten_all(const T (&s)[9], const WRow<T> (&r)[U + 2], T (&acc)[U])
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = T(0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] += s[3 * b] * r[u + b].w;
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] += s[3 * b + 1] * r[u + b].c;
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] += s[3 * b + 2] * r[u + b].e;
+    }
+}
+
 template <int N> __device__ __forceinline__ bool wvalid(int u)
 {
     const int lane = threadIdx.x & 63;
@@ -2211,9 +2247,10 @@ __device__ __forceinline__ void wsweep(T (&v)[WL<N>::U], const T (&f)[WL<N>::U],
     } else {
         WRow<T> r[U + 2];
         wwin<T, N>(v, r);
+        T acc[U];
+        wsten_all<T, U>(s, r, acc);
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            nv[u] = wvalid<N>(u) ? r[u + 1].c + om * (f[u] - wsten(s, r[u], r[u + 1], r[u + 2])) : T(0);
+        for (int u = 0; u < U; ++u) nv[u] = wvalid<N>(u) ? r[u + 1].c + om * (f[u] - acc[u]) : T(0);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) v[u] = nv[u];
@@ -2248,28 +2285,17 @@ __device__ __forceinline__ void wcycle(T (&v)[WL<N>::U], const T (&f)[WL<N>::U],
         {
             WRow<T> w[U + 2];
             wwin<T, N>(v, w);
+            T acc[U];
+            wsten_all<T, U>(s, w, acc);
 #pragma unroll
-            for (int u = 0; u < U; ++u) r[u] = wvalid<N>(u) ? f[u] - wsten(s, w[u], w[u + 1], w[u + 2]) : T(0);
+            for (int u = 0; u < U; ++u) r[u] = wvalid<N>(u) ? f[u] - acc[u] : T(0);
         }
         T fw[U];
         {
             WRow<T> w[U + 2];
             wwin<T, N>(r, w);
-            const T qq = T(0.25), hh = T(0.5);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                T acc = T(0);
-                acc += qq * w[u].w;
-                acc += hh * w[u].c;
-                acc += qq * w[u].e;
-                acc += hh * w[u + 1].w;
-                acc += T(1) * w[u + 1].c;
-                acc += hh * w[u + 1].e;
-                acc += qq * w[u + 2].w;
-                acc += hh * w[u + 2].c;
-                acc += qq * w[u + 2].e;
-                fw[u] = acc;
-            }
+            const T fwc[9] = {T(0.25), T(0.5), T(0.25), T(0.5), T(1), T(0.5), T(0.25), T(0.5), T(0.25)};
+            wsten_all<T, U>(fwc, w, fw);   // full weighting: the same nine-term order, the rows interleaved
         }
         T fc[1], vc[1];
         {
@@ -2585,21 +2611,33 @@ __global__ void __launch_bounds__(THREADS) k_subtree(SubArgs a)
     const int d0 = a.depth, L = I.L;
 
     // the top level's F (and A) are loaded into registers first, so that they are in
-    // flight while the tables are staged; the load count is exact for the level size
+    // flight while the tables are staged; the load count is exact for the level size.
+    // A single-instance launch on an internal level carries the table entries these
+    // loads need (a.ops1 set), so that no load waits for another
+    const bool fast = a.ops1 != nullptr;
     const LevelDev& Lv = I.lev[d0];
-    const int n = Lv.n;
-    const T fs = (T)Lv.fscale;
-    const gp<const T> Fg = glob<T>((const void*)Lv.F);
-    const gp<T> Ag = glob<T>(Lv.A);
+    const int n = fast ? a.n0 : Lv.n;
+    const T fs = (T)(fast ? a.fs0 : Lv.fscale);
+    const gp<const T> Fg = glob<T>(fast ? a.F0 : (const void*)Lv.F);
+    const gp<T> Ag = glob<T>(fast ? a.A0 : Lv.A);
+    const int ldf = fast ? a.ldf0 : Lv.ldf, lda = fast ? a.lda0 : Lv.lda;
+    const int sub_lds = fast ? a.sub_lds : I.sub_lds;
+    const T* const chol = fast ? (const T*)a.chol0 : P<T>::chol(I);
     const bool zero = a.pair || a.zg;
     const int k1 = min(a.kappa, MAXL + 1), k2 = min(max(a.kappa - 1, 1), MAXL + 1);
     // zebra calls use op lists without register calls
     const int32_t* const obeg = ZEB ? I.zops_beg : I.ops_beg;
     const int32_t* const olen = ZEB ? I.zops_len : I.ops_len;
-    const int n1 = olen[k1 - 1], n2 = (a.pair && a.kappa > 1) ? olen[k2 - 1] : 0;
+    const int n1 = fast ? a.n1 : olen[k1 - 1];
+    const int n2 = fast ? a.n2 : ((a.pair && a.kappa > 1) ? olen[k2 - 1] : 0);
     auto stage = [&]() {   // parameters, op lists and a small coarsest factor into LDS; LDS levels zeroed
-        for (int t = threadIdx.x; t < n1 + n2; t += blockDim.x)
-            pp.ops[t] = (t < n1) ? I.ops[obeg[k1 - 1] + t] : I.ops[obeg[k2 - 1] + (t - n1)];
+        if (fast) {
+            for (int t = threadIdx.x; t < n1 + n2; t += blockDim.x)
+                pp.ops[t] = (t < n1) ? a.ops1[t] : a.ops2[t - n1];
+        } else {
+            for (int t = threadIdx.x; t < n1 + n2; t += blockDim.x)
+                pp.ops[t] = (t < n1) ? I.ops[obeg[k1 - 1] + t] : I.ops[obeg[k2 - 1] + (t - n1)];
+        }
         for (int t = threadIdx.x; t < MAXL * 9; t += blockDim.x) {
             const int d = t / 9;
             pp.s[d][t % 9] = (d < L) ? P<T>::s(I, d)[t % 9] : T(0);
@@ -2615,8 +2653,8 @@ __global__ void __launch_bounds__(THREADS) k_subtree(SubArgs a)
             pp.nops[1] = n2;
         }
         if (I.nc2 * I.nc2 <= SubParams<T>::CH)
-            for (int t = threadIdx.x; t < I.nc2 * I.nc2; t += blockDim.x) pp.chol[t] = P<T>::chol(I)[t];
-        for (int p = threadIdx.x; p < I.sub_lds; p += blockDim.x) sm[p] = T(0);
+            for (int t = threadIdx.x; t < I.nc2 * I.nc2; t += blockDim.x) pp.chol[t] = chol[t];
+        for (int p = threadIdx.x; p < sub_lds; p += blockDim.x) sm[p] = T(0);
         if constexpr (ZEB) {   // line-solve tables of the relaxed levels, after the level arrays
             for (int dd = d0; dd < L - 1; ++dd) {
                 const int nn = I.lev[dd].n, lgd = 32 - __clz(nn);
@@ -2630,13 +2668,13 @@ __global__ void __launch_bounds__(THREADS) k_subtree(SubArgs a)
     T* const lev = sm + I.lds_off[d0];
     bool live = false;
     switch (n) {
-    case 1: live = top_level_in<T, THREADS, 1>(Fg, Ag, Lv.ldf, Lv.lda, fs, zero, done, lev, stage); break;
-    case 3: live = top_level_in<T, THREADS, 3>(Fg, Ag, Lv.ldf, Lv.lda, fs, zero, done, lev, stage); break;
-    case 7: live = top_level_in<T, THREADS, 7>(Fg, Ag, Lv.ldf, Lv.lda, fs, zero, done, lev, stage); break;
-    case 15: live = top_level_in<T, THREADS, 15>(Fg, Ag, Lv.ldf, Lv.lda, fs, zero, done, lev, stage); break;
-    case 31: live = top_level_in<T, THREADS, 31>(Fg, Ag, Lv.ldf, Lv.lda, fs, zero, done, lev, stage); break;
+    case 1: live = top_level_in<T, THREADS, 1>(Fg, Ag, ldf, lda, fs, zero, done, lev, stage); break;
+    case 3: live = top_level_in<T, THREADS, 3>(Fg, Ag, ldf, lda, fs, zero, done, lev, stage); break;
+    case 7: live = top_level_in<T, THREADS, 7>(Fg, Ag, ldf, lda, fs, zero, done, lev, stage); break;
+    case 15: live = top_level_in<T, THREADS, 15>(Fg, Ag, ldf, lda, fs, zero, done, lev, stage); break;
+    case 31: live = top_level_in<T, THREADS, 31>(Fg, Ag, ldf, lda, fs, zero, done, lev, stage); break;
     default:
-        if constexpr (THREADS >= 512) live = top_level_in<T, THREADS, 63>(Fg, Ag, Lv.ldf, Lv.lda, fs, zero, done, lev, stage);
+        if constexpr (THREADS >= 512) live = top_level_in<T, THREADS, 63>(Fg, Ag, ldf, lda, fs, zero, done, lev, stage);
         break;
     }
     if (!live) return;   // the whole workgroup leaves together
@@ -2682,7 +2720,7 @@ __global__ void __launch_bounds__(THREADS) k_subtree(SubArgs a)
     const T* vr = S.bufp(off0, lg0, (S.cur >> d0) & 1);
     for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
         const int j = p / n, i = p - j * n;
-        Ag[(size_t)j * Lv.lda + i] = vr[(j + 1) * Pst + (i + 1)];
+        Ag[(size_t)j * lda + i] = vr[(j + 1) * Pst + (i + 1)];
     }
 }
 

@@ -522,6 +522,30 @@ Launch sub(kc_hier* h, bool f32, int depth, int kappa, bool pair, int nu1, int n
     L.ba.hist = h->d_hist;
     L.threads = h->ex.coarse_threads;
     L.lds = smoother == 1 ? h->sub_lds_z : h->sub_lds;
+    if (L.ba.count == 1 && depth > 0 && h->h_inst && h->ws) {
+        // one instance on an internal level: its tables are fixed for the plan, so the
+        // launch carries them and the kernel issues every load in one round
+        const int i = L.ba.first;
+        const HostInst& hi = h->hi[i];
+        const InstDev& I = h->h_inst[i];
+        const int k1 = std::min(kappa, KMAX), k2 = std::min(std::max(kappa - 1, 1), KMAX);
+        const int* ob = obeg(hi, smoother);
+        const int* ol = olen(hi, smoother);
+        const uint32_t* ops = (const uint32_t*)(h->ws + hi.il.ops);
+        L.ba.ops1 = ops + ob[k1 - 1];
+        L.ba.n1 = ol[k1 - 1];
+        L.ba.ops2 = ops + ob[k2 - 1];
+        L.ba.n2 = (pair && kappa > 1) ? ol[k2 - 1] : 0;
+        const LevelDev& Lv = I.lev[depth];
+        L.ba.n0 = Lv.n;
+        L.ba.sub_lds = I.sub_lds;
+        L.ba.F0 = Lv.F;
+        L.ba.A0 = Lv.A;
+        L.ba.ldf0 = Lv.ldf;
+        L.ba.lda0 = Lv.lda;
+        L.ba.fs0 = Lv.fscale;
+        L.ba.chol0 = f32 ? (const void*)I.chol32 : (const void*)I.chol64;
+    }
     return L;
 }
 
