@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--sweep-reps", type=int, default=3, help="timed solves per (kappa, precision) in the sweep")
+    ap.add_argument("--sweep-reps", type=int, default=5, help="timed solves per (kappa, precision) in the sweep (median)")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=40, help="oracle cycles timed for the CPU baseline")
@@ -219,6 +219,17 @@ def main():
                     flops_per_launch=dom["flops_per_launch"],
                     note="1023^2 levels stay in the 256 MB Infinity Cache; coarse levels are latency-bound on one CU "
                          "per instance (the persistent kernel)")
+    # per level (depth 0 = 1023^2): launches, time and algorithmic GB/s of one iteration
+    per_level = {}
+    for nm, depth, ms, nbytes in prof["sequence"]:
+        e = per_level.setdefault(str(depth), {"launches": 0, "ms": 0.0, "bytes": 0.0})
+        e["launches"] += 1
+        e["ms"] += ms
+        e["bytes"] += nbytes
+    for e in per_level.values():
+        e["GB_s"] = round(e["bytes"] / (e["ms"] * 1e-3) / 1e9, 1) if e["ms"] > 0 else None
+        e["ms"] = round(e["ms"], 4)
+        del e["bytes"]
     fine = {"kernel": "fine-level pre-smoothing", "avg_us": round(ms_pre * 1e3, 2),
             "GB_s": round(bytes_pre / (ms_pre * 1e-3) / 1e9, 1), "bytes_per_launch": bytes_pre}
 
@@ -267,7 +278,7 @@ def main():
                    "kappa": "W" if best_k == kcycle.KAPPA_W else best_k, "precision": best_p,
                    "exec": tuned.get((best_p, best_k)),
                    "cycles": its[0], "unknowns": N},
-        "roofline": roofline, "iteration_ms": round(it_ms, 4), "fine_level": fine,
+        "roofline": roofline, "iteration_ms": round(it_ms, 4), "fine_level": fine, "per_level": per_level,
         "kernels": dict(list(kernels.items())[:8]),
         "per_kappa": per, "model": model_info,
         "extras": extras, "cpu_baseline": cpu,

@@ -294,7 +294,7 @@ kc_status kc_time_cycles(kc_hier* h, double* const* d_v, const int64_t* ldv, con
  * per kernel (compiler names, as a profiler lists them), the launches per
  * iteration, total and average ms, and the algorithmic bytes and flops per
  * launch (each input read once, each output written once); the sequence of
- * launches with depth and ms.  Synchronises. */
+ * launches as [kernel, depth, ms, algorithmic bytes].  Synchronises. */
 kc_status kc_profile_iteration(kc_hier* h, int32_t driver, const kc_cycle_params* c, int32_t reps, char* out,
                                size_t cap);
 

@@ -2082,9 +2082,9 @@ kc_status kc_profile_iteration(kc_hier* h, int32_t driver, const kc_cycle_params
         A.bytes += b;
         A.flops += f;
         total += t_main[k] / reps;
-        char buf[160];
-        std::snprintf(buf, sizeof buf, "%s[\"%s\", %d, %.5f]", seq.empty() ? "" : ", ", nm.c_str(),
-                      L.type == L_GRID ? L.sa.depth : L.ba.depth, t_main[k] / reps);
+        char buf[192];
+        std::snprintf(buf, sizeof buf, "%s[\"%s\", %d, %.5f, %.1f]", seq.empty() ? "" : ", ", nm.c_str(),
+                      L.type == L_GRID ? L.sa.depth : L.ba.depth, t_main[k] / reps, b);
         seq += buf;
         if (L.type == L_GRID && L.sa.fin != FIN_NONE) {
             if (!agg.count("k_finalize")) order.push_back("k_finalize");

@@ -423,6 +423,8 @@ def test_profile_iteration_covers_every_launch(prec, driver):
     assert any(k["name"].startswith("k_subtree") for k in ks)
     assert all(k["bytes_per_launch"] > 0 for k in ks if k["name"].startswith(("k_pre", "k_post")))
     assert all(k["flops_per_launch"] > 0 for k in ks if k["name"].startswith("k_subtree"))
+    seq = prof["sequence"]   # [kernel, depth, ms, algorithmic bytes] per launch
+    assert len(seq) == launches and all(len(e) == 4 and e[2] > 0 and e[3] >= 0 for e in seq)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
