@@ -8,7 +8,8 @@
 namespace kc {
 
 constexpr int MAXL = 16;          // levels per instance
-constexpr int NTABLES = 1 + 3 * MAXL;   // block tables: whole fine level, fused grid per depth, per level, zebra per level
+constexpr int NTABLES = 1 + 4 * MAXL;   // block tables: whole fine level, fused grid per depth, per level, zebra per level,
+                                        // fused post-smoothing per depth (where its strips differ from the pre-smoothing's)
 constexpr int ZLDS_TABLE = 480;   // persistent-kernel LDS elements for the zebra tables of levels 1 .. 63 (4 n each)
 constexpr int TX = 64;            // grid-kernel tile width  (one wave64 row)
 constexpr int TY = 32;            // grid-kernel tile height

@@ -267,6 +267,9 @@ int zebra_blocks_lines(int lines, int nx, int wave_n)
 int tiles_rect(int nx, int ny) { return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY); }
 // streaming blocks: STRIP_BLOCK_W columns x R rows, R = 16 << code
 int strip_rows_code(int n) { return n >= 4095 ? 2 : (n >= 2047 ? 1 : 0); }
+// the post-smoothing strips: 32 rows from 2047^2 up (measured faster than 64 at 4095^2 - 16383^2,
+// where the pre-smoothing is faster with taller strips)
+int strip_rows_code_post(int n) { return n >= 2047 ? 1 : 0; }
 int tiles_stream(int n, int code) { return ((n + STRIP_BLOCK_W - 1) / STRIP_BLOCK_W) * ((n + (16 << code) - 1) / (16 << code)); }
 
 // semi: levels coarsened along y only down to one line (every instance the same n)
@@ -432,6 +435,7 @@ struct kc_hier {
     std::vector<std::vector<int32_t>> lists;   // host copies of the instance lists
     int max_cut = 0, max_L = 0;
     int shape[MAXL] = {};                      // StageArgs::flags of the fused grid kernels at depth d
+    int shape_post[MAXL] = {};                 // the same for the post-smoothing kernel
     bool compacted = false;                    // the tables cover only the instances still iterating
     int last_compactions = 0;                  // table compactions during the last driver call
     int sub_lds = 0;
@@ -459,6 +463,7 @@ int tt_all0() { return 0; }
 int tt_cut(int d) { return 1 + d; }          // instances with cut > d
 int tt_lvl(int d) { return 1 + MAXL + d; }   // instances with L - 1 > d and cut > d (one kernel per operation)
 int tt_zeb(int d) { return 1 + 2 * MAXL + d; }   // zebra line groups of those instances
+int tt_cut_post(int d) { return 1 + 3 * MAXL + d; }   // fused post-smoothing strips where they differ from tt_cut
 int lt_sub(int d) { return d; }              // instances with cut == d
 int lt_coarse(int d) { return MAXL + d; }    // instances with L - 1 == d
 
@@ -495,8 +500,9 @@ Launch grid(kc_hier* h, GridKernel gk, bool f32, int table, int depth)
 // fused PRE/POST launch at depth d, in the tile shape chosen for that depth
 Launch fused_grid(kc_hier* h, GridKernel gk, bool f32, int d)
 {
-    Launch L = grid(h, gk, f32, tt_cut(d), d);
-    L.sa.flags = h->shape[d];
+    const bool own = gk == GK_POST && h->shape_post[d] != h->shape[d];   // post strips of their own height
+    Launch L = grid(h, gk, f32, own ? tt_cut_post(d) : tt_cut(d), d);
+    L.sa.flags = gk == GK_POST ? h->shape_post[d] : h->shape[d];
     return L;
 }
 
@@ -739,6 +745,8 @@ kc_status build_tables(kc_hier* h, const std::vector<char>* active)
                            : (sh & 16) ? tiles_mid(hi.il.n[d])
                                        : tiles_of(hi.il.n[d]);
             h->tiles[tt_cut(d)][i + 1] = (d < L && hi.cut > d) ? tc : 0;
+            const int shp = h->shape_post[d];
+            h->tiles[tt_cut_post(d)][i + 1] = (d < L && hi.cut > d && shp != sh) ? tiles_stream(hi.il.n[d], (shp >> 2) & 3) : 0;
             // one-kernel-per-operation stages: levels above the instance's cut (all of them in
             // the paper-structured mode, where the cut is L)
             const bool lvl = d < L - 1 && hi.cut > d;
@@ -854,6 +862,7 @@ kc_status plan_exec(kc_hier* h)
         else if (maxn > 0 && maxn <= h->ex.small_tile_n) f = 1;
         else if (maxn > 0 && maxn <= h->ex.mid_tile_n) f = 16;
         h->shape[d] = f;
+        h->shape_post[d] = (f & 2) ? (2 | (strip_rows_code_post(maxn) << 2)) : f;
     }
     kc_status st = build_tables(h, nullptr);
     if (st != KC_OK) return st;

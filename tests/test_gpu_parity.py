@@ -1028,3 +1028,22 @@ def test_zebra_rejects_oversized_leading_dimension():
     rc = KK.lib().kc_solve(H._h, pv, ok_ld, pf, big_ld, C.byref(cz), 1e-8, 5, it, rr, st)
     assert rc == KK.KC_ERR_ARG
     H.close()
+
+
+def test_stream_kernels_8191_cycle_bitwise():
+    """One FP64 V-cycle at 8191^2 (beyond the Infinity Cache): the streaming
+    pre-smoothing strips of 64 rows and post-smoothing strips of 32 rows
+    (separate block tables) give the oracle's bits."""
+    n = 8191
+    banner(f"streaming kernels one cycle n={n}")
+    rng = np.random.default_rng(81)
+    v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
+    H = K().Hierarchy([(n, math.pi / 4, 1e-4)])
+    v = dev(v0)
+    H.cycle(v, dev(f), kappa=1, nu1=2, nu2=2)
+    got = host(v)
+    H.close()
+    del v
+    torch.cuda.empty_cache()
+    ref = O.Hierarchy(n, math.pi / 4, 1e-4).cycle(v0, f, kappa=1, nu1=2, nu2=2)[0]
+    assert np.array_equal(got, ref)
