@@ -1522,11 +1522,19 @@ __device__ inline bool get_strip(const StageArgs& a, Strip& t)
     const int b = blockIdx.x;
     const int i = find_inst(a.tile_off, a.count, b);
     t.inst = i;
-    t.blk = b - a.tile_off[i];
+    t.blk = b - a.tile_off[i];   // the block's partial-sum slot
     const int n = a.inst[i].lev[a.depth].n;
     const int nbx = (n + STRIP_BLOCK_W - 1) / STRIP_BLOCK_W;
-    t.x0 = ((t.blk % nbx) * SWAVES + (int)(threadIdx.x >> 6)) * SW;
-    t.y0 = (t.blk / nbx) * R;
+    // workgroups go round-robin over the eight XCDs: give each XCD a contiguous run of
+    // strips (whole bands of rows), so that the halo rows and columns neighbouring strips
+    // share are read through one L2
+    int blk = t.blk;
+    {
+        const int nb = a.tile_off[i + 1] - a.tile_off[i];
+        if ((a.tile_off[i] & 7) == 0 && (nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    }
+    t.x0 = ((blk % nbx) * SWAVES + (int)(threadIdx.x >> 6)) * SW;
+    t.y0 = (blk / nbx) * R;
     t.live = t.x0 < n;
     return a.st[i].done == 0;
 }
