@@ -6,10 +6,17 @@
  * multigrid cycles").  Only the tests, the smoke check and the benchmark's
  * CPU-baseline leg may load it.  It shares no code with the GPU library.
  *
- * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared (no contracted
- * multiply-add: every product and sum is rounded on its own; the one fused
- * multiply-add is the explicit fma() that extracts a product's exact rounding
- * error in the norms and dot products).
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared (the compiler
+ * contracts nothing; every fused multiply-add is an explicit fma() call).
+ * Arithmetic reading: inside the cycle every product that is added to or
+ * subtracted from a running value is one fused multiply-add (FMAR below):
+ * the nine-point and off-line stencil sums, the Jacobi update
+ * v + omega/S_0 (f - A v) and both recurrences of the line elimination.
+ * Products by the transfer weights (1, 1/2, 1/4) are exact, so full
+ * weighting and prolongation keep plain products and sums; the dense
+ * coarsest solve, the setup (Galerkin stencils, factors) and the Krylov
+ * vector updates round every product and sum on its own.  The norms and
+ * dot products use fma() to extract a product's exact rounding error.
  *
  * What each part follows:
  *   - fine operator: the nine-point stencil table of Section 4;
@@ -48,27 +55,35 @@ static void tr_push(or_tr* t, int op, int level, int counter)
 
 #define REAL double
 #define SFX(x) x##_d
+#define FMAR fma
 #include "kc_oracle_levels.inc"
 #undef REAL
 #undef SFX
+#undef FMAR
 
 #define REAL float
 #define SFX(x) x##_s
+#define FMAR fmaf
 #include "kc_oracle_levels.inc"
 #undef REAL
 #undef SFX
+#undef FMAR
 
 #define REAL double
 #define SFX(x) x##_d
+#define FMAR fma
 #include "kc_oracle_semi.inc"
 #undef REAL
 #undef SFX
+#undef FMAR
 
 #define REAL float
 #define SFX(x) x##_s
+#define FMAR fmaf
 #include "kc_oracle_semi.inc"
 #undef REAL
 #undef SFX
+#undef FMAR
 
 struct or_hier {
     lv_d d;          /* FP64 hierarchy (semi-coarsening: the fine level only) */
