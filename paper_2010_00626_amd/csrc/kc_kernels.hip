@@ -1458,11 +1458,29 @@ __device__ inline void chol_solve_padded(int n, const T* Lc, const T* F, T* v, i
 // x0 - H + l) and it walks down the strip's R rows plus the halo rows.  Every
 // stage keeps the last three rows it produced in registers (a row window) and
 // produces one row per step, one row behind the stage feeding it, so each
-// input row is read from memory once; east / west neighbours come from lane
-// shuffles.  No LDS and no barriers: loads, arithmetic and stores of the many
-// resident waves overlap.  Arithmetic per point is the tile kernels' (same
-// expressions, same order), so results are identical.
+// input row is read from memory once; east / west neighbours come from DPP
+// whole-wave shifts (the lanes at the wave's edges are halo, whose values are
+// never stored: each stage's valid lanes shrink by one per side).  No LDS and
+// no barriers: loads, arithmetic and stores of the many resident waves
+// overlap.  Arithmetic per point is the tile kernels' (same expressions, same
+// order), so results are identical.
 // ---------------------------------------------------------------------------
+// DPP lane moves (a VALU operand modifier, no LDS round trip); lanes whose source
+// lies outside the row or wave read 0.  A double moves as its two 32-bit halves.
+template <int CTRL> __device__ __forceinline__ float dpp(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL> __device__ __forceinline__ double dpp(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+constexpr int DPP_WAVE_SHR1 = 0x138;   // wave_shr:1 -> value of lane - 1 (0 in lane 0)
+constexpr int DPP_WAVE_SHL1 = 0x130;   // wave_shl:1 -> value of lane + 1 (0 in lane 63)
+
 constexpr int SW = 54;        // output columns per wave (pre-smoothing with nu <= 3 fits 64 lanes)
 constexpr int SWAVES = 4;     // strips per block, side by side
 static_assert(SW * SWAVES == STRIP_BLOCK_W, "strip geometry");
@@ -1473,7 +1491,7 @@ template <typename T> struct Row3 {
 
 template <typename T> __device__ __forceinline__ Row3<T> row3(T v)
 {
-    return Row3<T>{__shfl_up(v, 1, 64), v, __shfl_down(v, 1, 64)};
+    return Row3<T>{dpp<DPP_WAVE_SHR1>(v), v, dpp<DPP_WAVE_SHL1>(v)};
 }
 
 // fixed-order nine-point sum (south row first, west to east), as Sten::apply
@@ -1730,7 +1748,7 @@ __global__ void __launch_bounds__(256) k_post_s(StageArgs a)
     // column), cb (the next one, from the east lane); row Js + 2 is prefetched raw
     int Jn = ((i0 - 1) >> 1) + 2;
     T ca0 = cmask(Jn - 2, craw(Jn - 2)), ca1 = cmask(Jn - 1, craw(Jn - 1));
-    T cb0 = __shfl_down(ca0, 1, 64), cb1 = __shfl_down(ca1, 1, 64);
+    T cb0 = dpp<DPP_WAVE_SHL1>(ca0), cb1 = dpp<DPP_WAVE_SHL1>(ca1);
     T cr2 = craw(Jn);
 
     for (int g = 0; g < NG; ++g) {
@@ -1747,7 +1765,7 @@ __global__ void __launch_bounds__(256) k_post_s(StageArgs a)
                 ca0 = ca1;
                 cb0 = cb1;
                 ca1 = cmask(Jn, cr2);
-                cb1 = __shfl_down(ca1, 1, 64);
+                cb1 = dpp<DPP_WAVE_SHL1>(ca1);
                 ++Jn;
                 cr2 = craw(Jn);
             }
@@ -2157,18 +2175,6 @@ static_assert(zlds_off(7) == ZLDS_TABLE, "zebra table block");
 // ---------------------------------------------------------------------------
 constexpr int DPP_WEST = 0x111;   // row_shr:1 -> value of lane - 1 (0 at a row start)
 constexpr int DPP_EAST = 0x101;   // row_shl:1 -> value of lane + 1 (0 at a row end)
-
-template <int CTRL> __device__ __forceinline__ float dpp(float x)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
-}
-template <int CTRL> __device__ __forceinline__ double dpp(double x)
-{
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
 
 template <int N> struct WL {
     static constexpr int B = N + 1, U = (N == 15) ? 4 : 1, LOGB = (N == 15) ? 4 : (N == 7) ? 3 : (N == 3) ? 2 : 1;
