@@ -46,6 +46,11 @@ template <> struct P<float> {
     static __device__ const float* chol(const InstDev& I) { return I.chol32; }
 };
 
+// a * b + c with one rounding: every product of a stencil sum, the Jacobi update
+// and both steps of the line elimination (the oracle calls fma() at the same places)
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T> struct Sten {
     T c[9];
     __device__ void load(const T* s)
@@ -57,15 +62,15 @@ template <typename T> struct Sten {
     __device__ __forceinline__ T apply(const T* x, int st) const
     {
         T acc = T(0);
-        acc += c[0] * x[-st - 1];
-        acc += c[1] * x[-st];
-        acc += c[2] * x[-st + 1];
-        acc += c[3] * x[-1];
-        acc += c[4] * x[0];
-        acc += c[5] * x[1];
-        acc += c[6] * x[st - 1];
-        acc += c[7] * x[st];
-        acc += c[8] * x[st + 1];
+        acc = fmadd(c[0], x[-st - 1], acc);
+        acc = fmadd(c[1], x[-st], acc);
+        acc = fmadd(c[2], x[-st + 1], acc);
+        acc = fmadd(c[3], x[-1], acc);
+        acc = fmadd(c[4], x[0], acc);
+        acc = fmadd(c[5], x[1], acc);
+        acc = fmadd(c[6], x[st - 1], acc);
+        acc = fmadd(c[7], x[st], acc);
+        acc = fmadd(c[8], x[st + 1], acc);
         return acc;
     }
 };
@@ -106,15 +111,15 @@ template <typename T>
 __device__ inline T gapply(const Sten<T>& s, const T* x, int ld, int n, int j, int i)
 {
     T acc = T(0);
-    acc += s.c[0] * gload(x, ld, n, j - 1, i - 1);
-    acc += s.c[1] * gload(x, ld, n, j - 1, i);
-    acc += s.c[2] * gload(x, ld, n, j - 1, i + 1);
-    acc += s.c[3] * gload(x, ld, n, j, i - 1);
-    acc += s.c[4] * gload(x, ld, n, j, i);
-    acc += s.c[5] * gload(x, ld, n, j, i + 1);
-    acc += s.c[6] * gload(x, ld, n, j + 1, i - 1);
-    acc += s.c[7] * gload(x, ld, n, j + 1, i);
-    acc += s.c[8] * gload(x, ld, n, j + 1, i + 1);
+    acc = fmadd(s.c[0], gload(x, ld, n, j - 1, i - 1), acc);
+    acc = fmadd(s.c[1], gload(x, ld, n, j - 1, i), acc);
+    acc = fmadd(s.c[2], gload(x, ld, n, j - 1, i + 1), acc);
+    acc = fmadd(s.c[3], gload(x, ld, n, j, i - 1), acc);
+    acc = fmadd(s.c[4], gload(x, ld, n, j, i), acc);
+    acc = fmadd(s.c[5], gload(x, ld, n, j, i + 1), acc);
+    acc = fmadd(s.c[6], gload(x, ld, n, j + 1, i - 1), acc);
+    acc = fmadd(s.c[7], gload(x, ld, n, j + 1, i), acc);
+    acc = fmadd(s.c[8], gload(x, ld, n, j + 1, i + 1), acc);
     return acc;
 }
 
@@ -122,15 +127,15 @@ template <typename T>
 __device__ inline T gapply(const Sten<T>& s, gp<const T> x, int ld, int n, int j, int i)
 {
     T acc = T(0);
-    acc += s.c[0] * gload(x, ld, n, j - 1, i - 1);
-    acc += s.c[1] * gload(x, ld, n, j - 1, i);
-    acc += s.c[2] * gload(x, ld, n, j - 1, i + 1);
-    acc += s.c[3] * gload(x, ld, n, j, i - 1);
-    acc += s.c[4] * gload(x, ld, n, j, i);
-    acc += s.c[5] * gload(x, ld, n, j, i + 1);
-    acc += s.c[6] * gload(x, ld, n, j + 1, i - 1);
-    acc += s.c[7] * gload(x, ld, n, j + 1, i);
-    acc += s.c[8] * gload(x, ld, n, j + 1, i + 1);
+    acc = fmadd(s.c[0], gload(x, ld, n, j - 1, i - 1), acc);
+    acc = fmadd(s.c[1], gload(x, ld, n, j - 1, i), acc);
+    acc = fmadd(s.c[2], gload(x, ld, n, j - 1, i + 1), acc);
+    acc = fmadd(s.c[3], gload(x, ld, n, j, i - 1), acc);
+    acc = fmadd(s.c[4], gload(x, ld, n, j, i), acc);
+    acc = fmadd(s.c[5], gload(x, ld, n, j, i + 1), acc);
+    acc = fmadd(s.c[6], gload(x, ld, n, j + 1, i - 1), acc);
+    acc = fmadd(s.c[7], gload(x, ld, n, j + 1, i), acc);
+    acc = fmadd(s.c[8], gload(x, ld, n, j + 1, i + 1), acc);
     return acc;
 }
 
@@ -488,7 +493,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_unfused(StageArgs a)
             if (!in) break;
             const T* x = buf<T>(Lv, a.src);
             const T acc = gapply(s, x, lds_, n, j, i);
-            buf<T>(Lv, a.dst)[gd] = x[gs] + w * (fs * F[gf] - acc);
+            buf<T>(Lv, a.dst)[gd] = fmadd(w, fs * F[gf] - acc, x[gs]);
             break;
         }
         case GK_RESID: {
@@ -601,15 +606,15 @@ __global__ void __launch_bounds__(GRID_THREADS) k_semi(StageArgs a)
         if constexpr (kind == GK_RESID) {
             const T* x = buf<T>(Lv, a.src);
             T acc = T(0);
-            acc += s.c[0] * sload(x, lds_, ny, nx, j - 1, i - 1);
-            acc += s.c[1] * sload(x, lds_, ny, nx, j - 1, i);
-            acc += s.c[2] * sload(x, lds_, ny, nx, j - 1, i + 1);
-            acc += s.c[3] * sload(x, lds_, ny, nx, j, i - 1);
-            acc += s.c[4] * sload(x, lds_, ny, nx, j, i);
-            acc += s.c[5] * sload(x, lds_, ny, nx, j, i + 1);
-            acc += s.c[6] * sload(x, lds_, ny, nx, j + 1, i - 1);
-            acc += s.c[7] * sload(x, lds_, ny, nx, j + 1, i);
-            acc += s.c[8] * sload(x, lds_, ny, nx, j + 1, i + 1);
+            acc = fmadd(s.c[0], sload(x, lds_, ny, nx, j - 1, i - 1), acc);
+            acc = fmadd(s.c[1], sload(x, lds_, ny, nx, j - 1, i), acc);
+            acc = fmadd(s.c[2], sload(x, lds_, ny, nx, j - 1, i + 1), acc);
+            acc = fmadd(s.c[3], sload(x, lds_, ny, nx, j, i - 1), acc);
+            acc = fmadd(s.c[4], sload(x, lds_, ny, nx, j, i), acc);
+            acc = fmadd(s.c[5], sload(x, lds_, ny, nx, j, i + 1), acc);
+            acc = fmadd(s.c[6], sload(x, lds_, ny, nx, j + 1, i - 1), acc);
+            acc = fmadd(s.c[7], sload(x, lds_, ny, nx, j + 1, i), acc);
+            acc = fmadd(s.c[8], sload(x, lds_, ny, nx, j + 1, i + 1), acc);
             buf<T>(Lv, a.dst)[gd] = fs * ((const T*)Lv.F)[(size_t)j * Lv.ldf + i] - acc;
         } else if constexpr (kind == GK_PROLONG) {
             const LevelDev& Lc = I.lev[d + 1];
@@ -707,12 +712,12 @@ __device__ __forceinline__ void zebra_lanes(const ZLine<T, DIR>& z)
 #pragma unroll
         for (int k = 0; k < ZK; ++k) {
             T acc = T(0);
-            acc += z.cm0 * m0;
-            acc += z.cm1 * m1;
-            acc += z.cm2 * mn[k];
-            acc += z.cp0 * p0;
-            acc += z.cp1 * p1;
-            acc += z.cp2 * pn[k];
+            acc = fmadd(z.cm0, m0, acc);
+            acc = fmadd(z.cm1, m1, acc);
+            acc = fmadd(z.cm2, mn[k], acc);
+            acc = fmadd(z.cp0, p0, acc);
+            acc = fmadd(z.cp1, p1, acc);
+            acc = fmadd(z.cp2, pn[k], acc);
             dq[k] = z.fs * fv[k] - acc;
             m0 = m1;
             m1 = mn[k];
@@ -723,7 +728,7 @@ __device__ __forceinline__ void zebra_lanes(const ZLine<T, DIR>& z)
         for (int k = 0; k < ZK; ++k) {
             const int q = q0 + k;
             if (q < n) {
-                const T y = (q == 0) ? dq[k] * rv[k] : (dq[k] - z.lo * prev) * rv[k];
+                const T y = (q == 0) ? dq[k] * rv[k] : fmadd(-z.lo, prev, dq[k]) * rv[k];
                 z.V[z.vi(z.line, q)] = y;
                 prev = y;
             }
@@ -742,7 +747,7 @@ __device__ __forceinline__ void zebra_lanes(const ZLine<T, DIR>& z)
         for (int k = 0; k < ZK; ++k) {
             const int q = q1 - k;
             if (q >= 0) {
-                const T x = yv[k] - mv[k] * next;
+                const T x = fmadd(-mv[k], next, yv[k]);
                 z.V[z.vi(z.line, q)] = x;
                 next = x;
             }
@@ -780,12 +785,12 @@ struct ZFwd {
     __device__ __forceinline__ T dq(const ZLine<T, DIR>& z) const
     {
         T acc = T(0);
-        acc += z.cm0 * (km0 ? m0 : T(0));
-        acc += z.cm1 * (km1 ? m1 : T(0));
-        acc += z.cm2 * (km2 ? m2 : T(0));
-        acc += z.cp0 * (kp0 ? p0 : T(0));
-        acc += z.cp1 * (kp1 ? p1 : T(0));
-        acc += z.cp2 * (kp2 ? p2 : T(0));
+        acc = fmadd(z.cm0, (km0 ? m0 : T(0)), acc);
+        acc = fmadd(z.cm1, (km1 ? m1 : T(0)), acc);
+        acc = fmadd(z.cm2, (km2 ? m2 : T(0)), acc);
+        acc = fmadd(z.cp0, (kp0 ? p0 : T(0)), acc);
+        acc = fmadd(z.cp1, (kp1 ? p1 : T(0)), acc);
+        acc = fmadd(z.cp2, (kp2 ? p2 : T(0)), acc);
         return z.fs * f - acc;
     }
 };
@@ -843,7 +848,7 @@ __device__ __forceinline__ void zebra_wave(const ZLine<T, DIR>& z, ZSlots<T>& sl
 #pragma unroll
                 for (int j = 0; j < SB; ++j) {
                     const int k = kb + j;
-                    const T t = (k == 0 && first) ? dk[j] : dk[j] - z.lo * prev;   // y_0 = d_0 r_0
+                    const T t = (k == 0 && first) ? dk[j] : fmadd(-z.lo, prev, dk[j]);   // y_0 = d_0 r_0
                     const T y = t * rk[j];
                     sl.res[h][k] = y;
                     if constexpr (decltype(partial)::value) prev = (k < cnt) ? y : prev;
@@ -915,7 +920,7 @@ __device__ __forceinline__ void zebra_wave(const ZLine<T, DIR>& z, ZSlots<T>& sl
 #pragma unroll
                 for (int j = SB - 1; j >= 0; --j) {
                     const int k = kb + j;
-                    const T x = yk[j] - uk[j] * next;
+                    const T x = fmadd(-uk[j], next, yk[j]);
                     sl.res[h][k] = x;
                     if constexpr (decltype(partial)::value) next = (k <= top) ? x : next;
                     else next = x;
@@ -1055,19 +1060,19 @@ __device__ __forceinline__ void band_pass(const T* src, T* dst, const T* sf, con
         for (int u = 0; u < U; ++u) {
             const int r = min(r0 + u, R1 - 1);
             T acc = T(0);
-            acc += s.c[0] * win[u][0];
-            acc += s.c[1] * win[u][1];
-            acc += s.c[2] * win[u][2];
-            acc += s.c[3] * win[u + 1][0];
-            acc += s.c[4] * win[u + 1][1];
-            acc += s.c[5] * win[u + 1][2];
-            acc += s.c[6] * win[u + 2][0];
-            acc += s.c[7] * win[u + 2][1];
-            acc += s.c[8] * win[u + 2][2];
+            acc = fmadd(s.c[0], win[u][0], acc);
+            acc = fmadd(s.c[1], win[u][1], acc);
+            acc = fmadd(s.c[2], win[u][2], acc);
+            acc = fmadd(s.c[3], win[u + 1][0], acc);
+            acc = fmadd(s.c[4], win[u + 1][1], acc);
+            acc = fmadd(s.c[5], win[u + 1][2], acc);
+            acc = fmadd(s.c[6], win[u + 2][0], acc);
+            acc = fmadd(s.c[7], win[u + 2][1], acc);
+            acc = fmadd(s.c[8], win[u + 2][2], acc);
             const bool in = colin && (unsigned)(ry0 + r) < (unsigned)n;
             const T fr = sf[r * RW + c];
             if (MODE == 2) val[u] = in ? fr - acc : T(0);
-            else val[u] = in ? win[u + 1][1] + w * (fr - acc) : T(0);
+            else val[u] = in ? fmadd(w, fr - acc, win[u + 1][1]) : T(0);
         }
     }
 #pragma unroll
@@ -1170,7 +1175,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_pre(StageArgs a)
                 T val = T(0);
                 if (inside(ry0 + rj, rx0 + ri, n)) {
                     if (k == 1 && zg) val = w * sf[q];
-                    else val = src[q] + w * (sf[q] - s.apply(&src[q], RW));
+                    else val = fmadd(w, sf[q] - s.apply(&src[q], RW), src[q]);
                 }
                 dst[q] = val;
             }
@@ -1299,7 +1304,7 @@ __global__ void __launch_bounds__(GRID_THREADS) k_post(StageArgs a)
                 const int rj = k + p / ww, ri = k + (p % ww);
                 const int q = rj * RW + ri;
                 T val = T(0);
-                if (inside(ry0 + rj, rx0 + ri, n)) val = src[q] + w * (sf[q] - s.apply(&src[q], RW));
+                if (inside(ry0 + rj, rx0 + ri, n)) val = fmadd(w, sf[q] - s.apply(&src[q], RW), src[q]);
                 dst[q] = val;
             }
             __syncthreads();
@@ -1499,15 +1504,15 @@ template <typename T>
 __device__ __forceinline__ T sten3(const Sten<T>& s, const Row3<T>& S, const Row3<T>& C, const Row3<T>& N)
 {
     T acc = T(0);
-    acc += s.c[0] * S.w;
-    acc += s.c[1] * S.c;
-    acc += s.c[2] * S.e;
-    acc += s.c[3] * C.w;
-    acc += s.c[4] * C.c;
-    acc += s.c[5] * C.e;
-    acc += s.c[6] * N.w;
-    acc += s.c[7] * N.c;
-    acc += s.c[8] * N.e;
+    acc = fmadd(s.c[0], S.w, acc);
+    acc = fmadd(s.c[1], S.c, acc);
+    acc = fmadd(s.c[2], S.e, acc);
+    acc = fmadd(s.c[3], C.w, acc);
+    acc = fmadd(s.c[4], C.c, acc);
+    acc = fmadd(s.c[5], C.e, acc);
+    acc = fmadd(s.c[6], N.w, acc);
+    acc = fmadd(s.c[7], N.c, acc);
+    acc = fmadd(s.c[8], N.e, acc);
     return acc;
 }
 
@@ -1644,7 +1649,7 @@ __global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
                     val = in ? w * S1.f : T(0);
                 } else {
                     const T res = S1.f - sten3(s, S0.x, S1.x, S2.x);
-                    val = in ? S1.x.c + w * res : T(0);
+                    val = in ? fmadd(w, res, S1.x.c) : T(0);
                     if (k == 1 && stop && own && r >= ylo && r < yhi) {
                         const double rd = (double)res;
                         nrm.add_sq(rd);
@@ -1782,7 +1787,7 @@ __global__ void __launch_bounds__(256) k_post_s(StageArgs a)
                 const int r = i - k;
                 const bool rin = (unsigned)r < (unsigned)n && (unsigned)x < (unsigned)n;
                 const RowF<T>& S1 = Y[k - 1][1];
-                const T val = rin ? S1.x.c + w * (S1.f - sten3(s, Y[k - 1][0].x, S1.x, Y[k - 1][2].x)) : T(0);
+                const T val = rin ? fmadd(w, S1.f - sten3(s, Y[k - 1][0].x, S1.x, Y[k - 1][2].x), S1.x.c) : T(0);
                 const T fk = S1.f;
                 Y[k][0] = Y[k][1];
                 Y[k][1] = Y[k][2];
@@ -1862,15 +1867,15 @@ template <typename T, int U>
 __device__ __forceinline__ T sten_win(const T (&s)[9], const T (&w)[U + 2][3], int k)
 {
     T acc = T(0);
-    acc += s[0] * w[k][0];
-    acc += s[1] * w[k][1];
-    acc += s[2] * w[k][2];
-    acc += s[3] * w[k + 1][0];
-    acc += s[4] * w[k + 1][1];
-    acc += s[5] * w[k + 1][2];
-    acc += s[6] * w[k + 2][0];
-    acc += s[7] * w[k + 2][1];
-    acc += s[8] * w[k + 2][2];
+    acc = fmadd(s[0], w[k][0], acc);
+    acc = fmadd(s[1], w[k][1], acc);
+    acc = fmadd(s[2], w[k][2], acc);
+    acc = fmadd(s[3], w[k + 1][0], acc);
+    acc = fmadd(s[4], w[k + 1][1], acc);
+    acc = fmadd(s[5], w[k + 1][2], acc);
+    acc = fmadd(s[6], w[k + 2][0], acc);
+    acc = fmadd(s[7], w[k + 2][1], acc);
+    acc = fmadd(s[8], w[k + 2][2], acc);
     return acc;
 }
 
@@ -1887,7 +1892,7 @@ __device__ __forceinline__ void sten_win_all(const T (&s)[9], const T (&w)[U + 2
 #pragma unroll
         for (int e = 0; e < 3; ++e)
 #pragma unroll
-            for (int u = 0; u < U; ++u) acc[u] += s[3 * b + e] * w[u + b][e];
+            for (int u = 0; u < U; ++u) acc[u] = fmadd(s[3 * b + e], w[u + b][e], acc[u]);
 }
 
 // y = x + w (F - S x) (Jacobi), or y = w F on a zero guess
@@ -1916,7 +1921,7 @@ __device__ __noinline__ void ph_sweep(clds<T> __restrict__ x, lds<T> __restrict_
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const T f = F[(min(j0 + u, N - 1) + 1) * P + cc + 1];
-            val[u] = w[u + 1][1] + om * (f - acc[u]);
+            val[u] = fmadd(om, f - acc[u], w[u + 1][1]);
         }
     }
     if (c < N) {
@@ -2106,14 +2111,14 @@ __device__ __forceinline__ void zebra_lds_line(lds<T> x, clds<T> F, clds<T> sc, 
             const int q = q0 + k;
             if (q < N) {
                 T acc = T(0);
-                acc += cm0 * m0;
-                acc += cm1 * m1;
-                acc += cm2 * mn[k];
-                acc += cp0 * p0;
-                acc += cp1 * p1;
-                acc += cp2 * pn[k];
+                acc = fmadd(cm0, m0, acc);
+                acc = fmadd(cm1, m1, acc);
+                acc = fmadd(cm2, mn[k], acc);
+                acc = fmadd(cp0, p0, acc);
+                acc = fmadd(cp1, p1, acc);
+                acc = fmadd(cp2, pn[k], acc);
                 const T dq = fv[k] - acc;
-                const T y = (q == 0) ? dq * rv[k] : (dq - lo * prev) * rv[k];
+                const T y = (q == 0) ? dq * rv[k] : fmadd(-lo, prev, dq) * rv[k];
                 x[at(line, q)] = y;
                 prev = y;
                 m0 = m1;
@@ -2139,7 +2144,7 @@ __device__ __forceinline__ void zebra_lds_line(lds<T> x, clds<T> F, clds<T> sc, 
         for (int k = 0; k < ZK; ++k) {
             const int q = q1 - k;
             if (q >= 0) {
-                const T v = yv[k] - uv[k] * next;
+                const T v = fmadd(-uv[k], next, yv[k]);
                 x[at(line, q)] = v;
                 next = v;
             }
@@ -2206,15 +2211,15 @@ template <typename T>
 __device__ __forceinline__ T wsten(const T (&s)[9], const WRow<T>& S, const WRow<T>& C, const WRow<T>& N)
 {
     T acc = T(0);
-    acc += s[0] * S.w;
-    acc += s[1] * S.c;
-    acc += s[2] * S.e;
-    acc += s[3] * C.w;
-    acc += s[4] * C.c;
-    acc += s[5] * C.e;
-    acc += s[6] * N.w;
-    acc += s[7] * N.c;
-    acc += s[8] * N.e;
+    acc = fmadd(s[0], S.w, acc);
+    acc = fmadd(s[1], S.c, acc);
+    acc = fmadd(s[2], S.e, acc);
+    acc = fmadd(s[3], C.w, acc);
+    acc = fmadd(s[4], C.c, acc);
+    acc = fmadd(s[5], C.e, acc);
+    acc = fmadd(s[6], N.w, acc);
+    acc = fmadd(s[7], N.c, acc);
+    acc = fmadd(s[8], N.e, acc);
     return acc;
 }
 
@@ -2227,11 +2232,11 @@ __device__ __forceinline__ void wsten_all(const T (&s)[9], const WRow<T> (&r)[U 
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] += s[3 * b] * r[u + b].w;
+        for (int u = 0; u < U; ++u) acc[u] = fmadd(s[3 * b], r[u + b].w, acc[u]);
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] += s[3 * b + 1] * r[u + b].c;
+        for (int u = 0; u < U; ++u) acc[u] = fmadd(s[3 * b + 1], r[u + b].c, acc[u]);
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] += s[3 * b + 2] * r[u + b].e;
+        for (int u = 0; u < U; ++u) acc[u] = fmadd(s[3 * b + 2], r[u + b].e, acc[u]);
     }
 }
 
@@ -2264,7 +2269,7 @@ __device__ __forceinline__ void wsweep(T (&v)[WL<N>::U], const T (&f)[WL<N>::U],
         T acc[U];
         wsten_all<T, U>(s, r, acc);
 #pragma unroll
-        for (int u = 0; u < U; ++u) nv[u] = wvalid<N>(u) ? r[u + 1].c + om * (f[u] - acc[u]) : T(0);
+        for (int u = 0; u < U; ++u) nv[u] = wvalid<N>(u) ? fmadd(om, f[u] - acc[u], r[u + 1].c) : T(0);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) v[u] = nv[u];
@@ -2784,15 +2789,15 @@ struct DWin {
     __device__ __forceinline__ double apply(const Sten<double>& s, int r) const
     {
         double acc = 0.0;
-        acc += s.c[0] * v[r][0];
-        acc += s.c[1] * v[r][1];
-        acc += s.c[2] * v[r][2];
-        acc += s.c[3] * v[r + 1][0];
-        acc += s.c[4] * v[r + 1][1];
-        acc += s.c[5] * v[r + 1][2];
-        acc += s.c[6] * v[r + 2][0];
-        acc += s.c[7] * v[r + 2][1];
-        acc += s.c[8] * v[r + 2][2];
+        acc = fmadd(s.c[0], v[r][0], acc);
+        acc = fmadd(s.c[1], v[r][1], acc);
+        acc = fmadd(s.c[2], v[r][2], acc);
+        acc = fmadd(s.c[3], v[r + 1][0], acc);
+        acc = fmadd(s.c[4], v[r + 1][1], acc);
+        acc = fmadd(s.c[5], v[r + 1][2], acc);
+        acc = fmadd(s.c[6], v[r + 2][0], acc);
+        acc = fmadd(s.c[7], v[r + 2][1], acc);
+        acc = fmadd(s.c[8], v[r + 2][2], acc);
         return acc;
     }
 };
@@ -2995,8 +3000,7 @@ static void pre_shape(const StageArgs& a, int nb, hipStream_t s)
     if (a.flags & 2) {
         switch ((a.flags >> 2) & 3) {
         case 0: k_pre_s<T, NU, 16><<<nb, 256, 0, s>>>(a); break;
-        case 1: k_pre_s<T, NU, 32><<<nb, 256, 0, s>>>(a); break;
-        default: k_pre_s<T, NU, 64><<<nb, 256, 0, s>>>(a); break;
+        default: k_pre_s<T, NU, 32><<<nb, 256, 0, s>>>(a); break;
         }
     } else if (a.flags & 32) {
         k_pre<T, NU, 8, 8><<<nb, GRID_THREADS, 0, s>>>(a);
@@ -3015,8 +3019,7 @@ static void post_shape(const StageArgs& a, int nb, hipStream_t s)
     if (a.flags & 2) {
         switch ((a.flags >> 2) & 3) {
         case 0: k_post_s<T, NU, 16><<<nb, 256, 0, s>>>(a); break;
-        case 1: k_post_s<T, NU, 32><<<nb, 256, 0, s>>>(a); break;
-        default: k_post_s<T, NU, 64><<<nb, 256, 0, s>>>(a); break;
+        default: k_post_s<T, NU, 32><<<nb, 256, 0, s>>>(a); break;
         }
     } else if (a.flags & 32) {
         k_post<T, NU, 8, 8><<<nb, GRID_THREADS, 0, s>>>(a);

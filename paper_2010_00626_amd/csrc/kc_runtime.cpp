@@ -265,11 +265,10 @@ int zebra_blocks_lines(int lines, int nx, int wave_n)
                                         : (per_colour + 63) / 64;
 }
 int tiles_rect(int nx, int ny) { return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY); }
-// streaming blocks: STRIP_BLOCK_W columns x R rows, R = 16 << code
-int strip_rows_code(int n) { return n >= 4095 ? 2 : (n >= 2047 ? 1 : 0); }
-// the post-smoothing strips: 32 rows from 2047^2 up (measured faster than 64 at 4095^2 - 16383^2,
-// where the pre-smoothing is faster with taller strips)
-int strip_rows_code_post(int n) { return n >= 2047 ? 1 : 0; }
+// streaming blocks: STRIP_BLOCK_W columns x R rows, R = 16 << code; 32 rows from 2047^2 up for both
+// parts (measured faster than 16 or 64 at 8191^2 and 16383^2); the post-smoothing keeps a shape of its
+// own per depth (shape_post) so that the two parts can take different heights
+int strip_rows_code(int n) { return n >= 2047 ? 1 : 0; }
 int tiles_stream(int n, int code) { return ((n + STRIP_BLOCK_W - 1) / STRIP_BLOCK_W) * ((n + (16 << code) - 1) / (16 << code)); }
 
 // semi: levels coarsened along y only down to one line (every instance the same n)
@@ -862,7 +861,7 @@ kc_status plan_exec(kc_hier* h)
         else if (maxn > 0 && maxn <= h->ex.small_tile_n) f = 1;
         else if (maxn > 0 && maxn <= h->ex.mid_tile_n) f = 16;
         h->shape[d] = f;
-        h->shape_post[d] = (f & 2) ? (2 | (strip_rows_code_post(maxn) << 2)) : f;
+        h->shape_post[d] = f;
     }
     kc_status st = build_tables(h, nullptr);
     if (st != KC_OK) return st;
