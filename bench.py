@@ -307,6 +307,8 @@ def summary(out, f32_best):
         hb = ex["fine_kernels_hbm"]
         sm["fine_TB_s_nu2"] = {f"{name}_{n}": round(hb[f"by_nu_{n}"][f"{name}_nu2"]["GB_s"] / 1e3, 3)
                                for n in (8191, 16383) for name in ("pre", "post") if f"by_nu_{n}" in hb}
+        if "torch_streaming_8191" in hb:
+            sm["fine_TB_s_nu2"]["torch_axpy_8191"] = hb["torch_streaming_8191"]["axpy"]
     if "c5_adjoint" in ex:
         sm["c5_forward_backward_ms"] = ex["c5_adjoint"]["forward_backward_ms"]
     if "convection_c2" in ex:
@@ -386,7 +388,35 @@ def hbm_kernel(kcycle, torch):
         Hh.close()
         del Hh, fh, uh
         torch.cuda.empty_cache()
+    res["torch_streaming_8191"] = torch_streaming(torch, 8191)
     return res
+
+
+def torch_streaming(torch, n):
+    """What PyTorch's own elementwise kernels reach on n x n FP64 arrays of the same size
+    (copy: 1 read + 1 write, add and a + 0.5 b: 2 reads + 1 write), in TB/s: the practical
+    streaming rate of this GPU next to which the fused kernels' rates can be read."""
+    a = torch.zeros((n, n), dtype=torch.float64, device="cuda").uniform_(-1, 1)
+    b = torch.zeros_like(a).uniform_(-1, 1)
+    c = torch.zeros_like(a).uniform_(-1, 1)
+    nb = a.numel() * 8
+
+    def rate(fn, nbytes, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return round(nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e12, 3)
+
+    out = {"copy": rate(lambda: a.copy_(b), 2 * nb), "add": rate(lambda: torch.add(b, c, out=a), 3 * nb),
+           "axpy": rate(lambda: torch.add(b, c, alpha=0.5, out=a), 3 * nb)}
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
 
 
 def c4_batched(inputs, kcycle, autotune, torch):
@@ -568,7 +598,37 @@ def zebra_c2(inputs, kcycle, torch):
             print(f"[bench] zebra {mode} kappa={key}: {it[0]} cycles, {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
         H.close()
         out[mode] = res
+    out["cycle_4095"] = zebra_4095(inst, kcycle, torch)
     return out
+
+
+def zebra_4095(inst, kcycle, torch):
+    """One zebra cycle on a 4095^2 grid (the same theta and eps, fused mode with the calls
+    at 63^2 and below in the persistent kernel), ms per cycle per kappa, and the fine
+    level's line-kernel launches (one colour of one relaxation each) from the launch
+    profile of a kappa = 1 iteration: average time and algorithmic rate."""
+    n = 4095
+    H = kcycle.Hierarchy([(n, inst.theta, inst.eps)], "f64", exec=dict(mode="fused", coarse_cutover=63))
+    f = torch.zeros((n, n), dtype=torch.float64, device="cuda").uniform_(-1, 1)
+    u = torch.zeros_like(f)
+    res = {"ms_per_cycle": {}}
+    for k in (1, 2, 3, 4, kcycle.KAPPA_W):
+        key = "W" if k == kcycle.KAPPA_W else str(k)
+        res["ms_per_cycle"][key] = round(H.time_cycles(u, f, kappa=k, reps=5, smoother="zebra"), 3)
+    u.zero_()
+    H.solve(u, f, kappa=1, tol=0.0, maxit=2, smoother="zebra")
+    prof = H.profile_iteration("solve", kappa=1, reps=5, smoother="zebra")
+    fine = [e for e in prof["sequence"] if e[0].startswith("k_zebra") and e[1] == 0]
+    if fine:
+        ms = sum(e[2] for e in fine) / len(fine)
+        b = sum(e[3] for e in fine) / len(fine)
+        res["fine_colour"] = {"launches_per_cycle": len(fine), "avg_ms": round(ms, 4), "bytes": b,
+                              "GB_s": round(b / (ms * 1e-3) / 1e9, 1)}
+    print(f"[bench] zebra 4095^2: {res}", file=sys.stderr, flush=True)
+    H.close()
+    del f, u
+    torch.cuda.empty_cache()
+    return res
 
 
 def convection_c2(inputs, kcycle, torch):
