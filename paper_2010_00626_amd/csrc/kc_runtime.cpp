@@ -1270,9 +1270,11 @@ void record_counts(kc_hier* h, int drv, const kc_cycle_params& c)
 // per-launch profile of one driver iteration: kernel names as the compiler
 // emits them (so they match a profiler's), algorithmic bytes and flops
 // ---------------------------------------------------------------------------
-constexpr double FL_SWEEP = 20.0;     // 9 mul + 8 add + sub + mul + add per point
-constexpr double FL_RESID = 18.0;     // 9 mul + 8 add + sub
+constexpr double FL_SWEEP = 20.0;     // nine-term sum (9 mul + 8 add, as fused multiply-adds) + sub + multiply-add per point
+constexpr double FL_RESID = 18.0;     // nine-term sum + sub
 constexpr double FL_FW = 17.0;        // 9 mul + 8 add per coarse point
+constexpr double FL_ZEBRA_RHS = 13.0;   // six off-line products and sums + scaled f - sum
+constexpr double FL_ZEBRA_SOLVE = 5.0;  // forward multiply-add and product, backward multiply-add
 constexpr double FL_PROLONG = 3.0;    // average over injected, edge and centre points
 
 std::string launch_name(const kc_hier* h, const Launch& L)
@@ -1339,6 +1341,15 @@ void launch_work(const kc_hier* h, const Launch& L, double& bytes, double& flops
             const double nf = hi.il.n[d], nc = hi.il.n[d + 1];
             bytes += (3.0 * nf * nf + 2.0 * nc * nc) * T;   // read v, f, v_c; write v, f_c
             flops += nf * nf * (FL_PROLONG + FL_SWEEP * (L.sa.src + L.sa.nu) + FL_RESID) + nc * nc * FL_FW;
+            continue;
+        }
+        if (L.gk == GK_ZEBRA) {
+            // one colour: f of its lines and the other colour's lines read, its lines written
+            if (hi.cut <= d || d >= hi.il.L) continue;
+            const double nl = hi.il.n[d], np = hi.il.nx[d];
+            const double own = std::floor((nl + 1 - L.sa.dst) / 2);
+            bytes += (2.0 * own + (nl - own)) * np * T;
+            flops += own * np * (FL_ZEBRA_RHS + FL_ZEBRA_SOLVE);
             continue;
         }
         if (L.gk == GK_PRE || L.gk == GK_POST) {
