@@ -17,7 +17,7 @@ ARCH = os.environ.get("KC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
-    "-ffp-contract=off",                                   # one rounding per + and *
+    "-ffp-contract=off",                                   # fused multiply-adds only where written (fmadd)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]

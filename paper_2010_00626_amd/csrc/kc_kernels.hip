@@ -7,9 +7,11 @@
 // coarse operators), so every rounded result equals the unscaled one times a
 // power of two.
 //
-// Arithmetic order (shared by every kernel, one rounding per + and *, no
-// contraction): a stencil sum visits the south row, then the centre row, then
-// the north row, west to east in each; full weighting visits the 3x3
+// Arithmetic order (shared by every kernel; the compiler contracts nothing,
+// and each product of a stencil sum, the Jacobi update and both steps of the
+// line elimination is an explicit fused multiply-add, fmadd): a stencil sum
+// visits the south row, then the centre row, then the north row, west to east
+// in each, accumulating product by product; full weighting visits the 3x3
 // neighbourhood in the same order with weights w(a) w(b), w(0)=1, w(+-1)=1/2;
 // bilinear prolongation gathers the one, two or four coarse neighbours south
 // to north, west to east, and scales the sum by 1/2 or 1/4.

@@ -1032,8 +1032,7 @@ def test_zebra_rejects_oversized_leading_dimension():
 
 def test_stream_kernels_8191_cycle_bitwise():
     """One FP64 V-cycle at 8191^2 (beyond the Infinity Cache): the streaming
-    pre-smoothing strips of 64 rows and post-smoothing strips of 32 rows
-    (separate block tables) give the oracle's bits."""
+    pre- and post-smoothing strips of 32 rows give the oracle's bits."""
     n = 8191
     banner(f"streaming kernels one cycle n={n}")
     rng = np.random.default_rng(81)
