@@ -1463,9 +1463,10 @@ __device__ inline void chol_solve_padded(int n, const T* Lc, const T* F, T* v, i
 // streaming fused kernels for large levels.  A wave owns a strip of SW output
 // columns; its 64 lanes hold the strip plus a halo (lane l is column
 // x0 - H + l) and it walks down the strip's R rows plus the halo rows.  Every
-// stage keeps the last three rows it produced in registers (a row window) and
-// produces one row per step, one row behind the stage feeding it, so each
-// input row is read from memory once; east / west neighbours come from DPP
+// stage produces one row per step, one row behind the stage feeding it, and
+// keeps its nine-point sums in rolling form (the open sums of the two rows
+// its newest input row still enters), so each input row is read from memory
+// once and no stage holds a window of rows; east / west neighbours come from DPP
 // whole-wave shifts (the lanes at the wave's edges are halo, whose values are
 // never stored: each stage's valid lanes shrink by one per side).  No LDS and
 // no barriers: loads, arithmetic and stores of the many resident waves
@@ -1564,18 +1565,50 @@ __device__ inline bool get_strip(const StageArgs& a, Strip& t)
     return a.st[i].done == 0;
 }
 
-template <typename T> struct RowF {
-    Row3<T> x;   // values of the row around this lane's column
-    T f;         // right-hand side of the row at this lane's column
+// A stage's nine-point sums in rolling form: when the stage above delivers a
+// row X, X is the north row of the oldest open sum (which it completes), the
+// centre row of the next and the south row of a new one, so a stage keeps two
+// partial sums and one centre value instead of a window of three rows.  Each
+// sum takes the products in the stencil order (south row, centre row, north
+// row; west to east), as sten3 does, so every completed sum is sten3's.
+template <typename T> struct Roll {
+    T ac = T(0);   // row r: south and centre parts
+    T as = T(0);   // row r + 1: south part
+    T cc = T(0);   // row r's own value
 };
+
+// feeds row X (= row r + 1 of the stage above); returns row r's completed sum
+// and leaves row r's own value in `centre`
+template <typename T>
+__device__ __forceinline__ T roll(Roll<T>& q, const Sten<T>& s, const Row3<T>& X, T& centre)
+{
+    T acc = q.ac;
+    acc = fmadd(s.c[6], X.w, acc);
+    acc = fmadd(s.c[7], X.c, acc);
+    acc = fmadd(s.c[8], X.e, acc);
+    centre = q.cc;
+    T mid = q.as;
+    mid = fmadd(s.c[3], X.w, mid);
+    mid = fmadd(s.c[4], X.c, mid);
+    mid = fmadd(s.c[5], X.e, mid);
+    T low = T(0);
+    low = fmadd(s.c[0], X.w, low);
+    low = fmadd(s.c[1], X.c, low);
+    low = fmadd(s.c[2], X.e, low);
+    q.ac = mid;
+    q.as = low;
+    q.cc = X.c;
+    return acc;
+}
 
 // pre-smoothing: NU sweeps + residual + full weighting (+ input residual norm).
 // Step s reads input row i = y0 - H + s; sweep k produces row i - k, the
 // residual row i - NU - 1 and full weighting is centred on row i - NU - 2.
-// The loop body is unrolled over G = 6 steps (windows rotate with period 3,
-// row parity with period 2), so window rotation is register renaming; input
-// rows are loaded 3 steps ahead.  Steps past the strip compute rows that are
-// never stored.
+// Every stage keeps its sums in rolling form (Roll) and the right-hand sides
+// of the last NU + 2 rows sit in a ring.  The loop body is unrolled over G = 6
+// steps (the ring rotates and the row parity alternates at compile time);
+// input rows are loaded 3 steps ahead.  Steps past the strip compute rows that
+// are never stored.
 template <typename T, int NU, int R>
 __global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
 {
@@ -1607,12 +1640,11 @@ __global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
     const int i0 = t.y0 - H;
     Acc2 nrm;
 
-    const Row3<T> z3{T(0), T(0), T(0)};
-    RowF<T> V0{z3, T(0)}, V1 = V0, V2 = V0;          // input rows i-2, i-1, i
-    RowF<T> Y[NU + 1][3];                             // Y[k]: rows after k sweeps (k >= 1)
+    Roll<T> sw[NU + 1];   // sw[k]: sweep k (k >= 1); sw[0]: the residual
+    T fr[NU + 2];         // fr[j]: right-hand side of row i - j
 #pragma unroll
-    for (int k = 0; k <= NU; ++k) Y[k][0] = Y[k][1] = Y[k][2] = V0;
-    Row3<T> R0 = z3, R1 = z3, R2 = z3;                // residual rows
+    for (int j = 0; j < NU + 2; ++j) fr[j] = T(0);
+    T fwp = T(0);         // full weighting of the next odd row: its south part, then its centre part
 
     // raw rows from clamped (always valid) addresses, masked when they become current;
     // a zero guess reads no estimate (F, with its own leading dimension, stands in)
@@ -1635,57 +1667,70 @@ __global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
             const T rv = pv[u % 3], rf = pf[u % 3];
             load(i + 3, pv[u % 3], pf[u % 3]);
             const bool rin = col && (unsigned)i < (unsigned)n;
-            const T vi = (rin && !zg) ? rv : T(0), fi = rin ? fs * rf : T(0);
-            V0 = V1;
-            V1 = V2;
-            V2 = RowF<T>{row3(vi), fi};
+            const T vi = (rin && !zg) ? rv : T(0);
+#pragma unroll
+            for (int j = NU + 1; j > 0; --j) fr[j] = fr[j - 1];
+            fr[0] = rin ? fs * rf : T(0);
+            Row3<T> X = row3(vi);   // the newest row of the stage feeding the next one
+            T top = vi;             // its own value
 #pragma unroll
             for (int k = 1; k <= NU; ++k) {   // sweep k: row i - k
                 const int r = i - k;
-                const RowF<T>& S0 = (k == 1) ? V0 : Y[k - 1][0];
-                const RowF<T>& S1 = (k == 1) ? V1 : Y[k - 1][1];
-                const RowF<T>& S2 = (k == 1) ? V2 : Y[k - 1][2];
                 const bool in = (unsigned)r < (unsigned)n && (unsigned)x < (unsigned)n;
+                T centre;
+                const T acc = roll(sw[k], s, X, centre);
                 T val;
                 if (k == 1 && zg) {
-                    val = in ? w * S1.f : T(0);
+                    val = in ? w * fr[1] : T(0);
                 } else {
-                    const T res = S1.f - sten3(s, S0.x, S1.x, S2.x);
-                    val = in ? fmadd(w, res, S1.x.c) : T(0);
+                    const T res = fr[k] - acc;
+                    val = in ? fmadd(w, res, centre) : T(0);
                     if (k == 1 && stop && own && r >= ylo && r < yhi) {
                         const double rd = (double)res;
                         nrm.add_sq(rd);
                     }
                 }
-                const T fk = S1.f;
-                Y[k][0] = Y[k][1];
-                Y[k][1] = Y[k][2];
-                Y[k][2] = RowF<T>{row3(val), fk};
+                X = row3(val);
+                top = val;
             }
-            const RowF<T>& Q0 = (NU == 0) ? V0 : Y[NU][0];
-            const RowF<T>& Q1 = (NU == 0) ? V1 : Y[NU][1];
-            const RowF<T>& Q2 = (NU == 0) ? V2 : Y[NU][2];
-            {   // smoothed row i - NU (with no sweeps on a zero guess the window holds zeros)
+            {   // smoothed row i - NU (with no sweeps on a zero guess the input rows are zeros)
                 const int r = i - NU;
-                if (own && r >= ylo && r < yhi) B[(size_t)r * ldb + x] = Q2.x.c;
+                if (own && r >= ylo && r < yhi) B[(size_t)r * ldb + x] = top;
             }
+            Row3<T> Rr;
             {   // residual of row i - NU - 1
                 const int r = i - NU - 1;
                 const bool in = (unsigned)r < (unsigned)n && (unsigned)x < (unsigned)n;
-                const T res = Q1.f - sten3(s, Q0.x, Q1.x, Q2.x);
+                T centre;
+                const T res = fr[NU + 1] - roll(sw[0], s, X, centre);
                 if (NU == 0 && stop && !zg && own && r >= ylo && r < yhi) {
                     const double rd = (double)res;
                     nrm.add_sq(rd);
                 }
-                R0 = R1;
-                R1 = R2;
-                R2 = row3(in ? res : T(0));
+                Rr = row3(in ? res : T(0));
             }
-            {   // full weighting centred on fine row c = i - NU - 2 (odd rows)
-                const int c = i - NU - 2;
-                if (((c & 1) != 0) && fwc && c >= ylo && c < yhi) {
-                    const int J = (c - 1) >> 1;
-                    if (J < nc) Fc[(size_t)J * ldc + ((x - 1) >> 1)] = fw3(R0, R1, R2);
+            {   // full weighting: residual row j = i - NU - 1 (its parity is that of u: y0 and
+                // 2 H are even) is the centre row of the odd centre j, or the north row of
+                // centre j - 1 (stored) and the south row of centre j + 1
+                const T q = T(0.25), h = T(0.5);
+                if ((u & 1) != 0) {
+                    fwp += h * Rr.w;
+                    fwp += T(1) * Rr.c;
+                    fwp += h * Rr.e;
+                } else {
+                    T acc = fwp;
+                    acc += q * Rr.w;
+                    acc += h * Rr.c;
+                    acc += q * Rr.e;
+                    const int c = i - NU - 2;
+                    if (fwc && c >= ylo && c < yhi) {
+                        const int J = (c - 1) >> 1;
+                        if (J < nc) Fc[(size_t)J * ldc + ((x - 1) >> 1)] = acc;
+                    }
+                    fwp = T(0);
+                    fwp += q * Rr.w;
+                    fwp += h * Rr.c;
+                    fwp += q * Rr.e;
                 }
             }
         }
@@ -1700,9 +1745,10 @@ __global__ void __launch_bounds__(256) k_pre_s(StageArgs a)
 
 // post-smoothing: prolong-add + NU sweeps.  Step s reads row i = y0 - H + s,
 // corrects it with the bilinear interpolant of the coarse solution and sweep
-// k produces row i - k.  A lane loads the coarse value at column
-// (x - 1) / 2 of each coarse row once (every second step) and takes the value
-// at the next coarse column from its east neighbour lane.
+// k produces row i - k (sums in rolling form, right-hand sides in a ring).  A
+// lane loads the coarse value at column (x - 1) / 2 of each coarse row once
+// (every second step) and takes the value at the next coarse column from its
+// east neighbour lane.
 template <typename T, int NU, int R>
 __global__ void __launch_bounds__(256) k_post_s(StageArgs a)
 {
@@ -1734,10 +1780,10 @@ __global__ void __launch_bounds__(256) k_post_s(StageArgs a)
     const bool cin = t.live && (unsigned)Is < (unsigned)nc;
     const bool xodd = (x & 1) != 0;
 
-    const Row3<T> z3{T(0), T(0), T(0)};
-    RowF<T> Y[NU + 1][3];
+    Roll<T> sw[NU + 1];   // sw[k]: sweep k (k >= 1)
+    T fr[NU + 1];         // fr[j]: right-hand side of row i - j
 #pragma unroll
-    for (int k = 0; k <= NU; ++k) Y[k][0] = Y[k][1] = Y[k][2] = RowF<T>{z3, T(0)};
+    for (int j = 0; j < NU + 1; ++j) fr[j] = T(0);
 
     // raw rows from clamped (always valid) addresses, masked when they become current
     const size_t xc = (size_t)clampi(x, n), Ic = (size_t)clampi(Is, nc);
@@ -1765,7 +1811,10 @@ __global__ void __launch_bounds__(256) k_post_s(StageArgs a)
             const T rv = pv[u % 3], rf = pf[u % 3];
             load(i + 3, pv[u % 3], pf[u % 3]);
             const bool rin = col && (unsigned)i < (unsigned)n;
-            const T vi = rin ? rv : T(0), fi = rin ? fs * rf : T(0);
+            const T vi = rin ? rv : T(0);
+#pragma unroll
+            for (int j = NU; j > 0; --j) fr[j] = fr[j - 1];
+            fr[0] = rin ? fs * rf : T(0);
             // i0 = y0 - H with y0 even, so the parity of i is that of H + u (known at compile time);
             // an odd row starts a new coarse row pair (not at the first step: the pair is loaded)
             if (((H + u) & 1) != 0 && (u > 0 || g > 0)) {
@@ -1781,22 +1830,20 @@ __global__ void __launch_bounds__(256) k_post_s(StageArgs a)
             else e = xodd ? T(0.5) * (ca0 + ca1) : T(0.25) * (((ca0 + cb0) + ca1) + cb1);
             const bool in = col && (unsigned)i < (unsigned)n;
             const T uu = in ? vi + e : T(0);
-            Y[0][0] = Y[0][1];
-            Y[0][1] = Y[0][2];
-            Y[0][2] = RowF<T>{row3(uu), fi};
+            Row3<T> X = row3(uu);
+            T top = uu;
 #pragma unroll
             for (int k = 1; k <= NU; ++k) {
                 const int r = i - k;
-                const bool rin = (unsigned)r < (unsigned)n && (unsigned)x < (unsigned)n;
-                const RowF<T>& S1 = Y[k - 1][1];
-                const T val = rin ? fmadd(w, S1.f - sten3(s, Y[k - 1][0].x, S1.x, Y[k - 1][2].x), S1.x.c) : T(0);
-                const T fk = S1.f;
-                Y[k][0] = Y[k][1];
-                Y[k][1] = Y[k][2];
-                Y[k][2] = RowF<T>{row3(val), fk};
+                const bool rk = (unsigned)r < (unsigned)n && (unsigned)x < (unsigned)n;
+                T centre;
+                const T acc = roll(sw[k], s, X, centre);
+                const T val = rk ? fmadd(w, fr[k] - acc, centre) : T(0);
+                X = row3(val);
+                top = val;
             }
             const int r = i - NU;
-            if (own && r >= ylo && r < yhi) A[(size_t)r * lda + x] = Y[NU][2].x.c;
+            if (own && r >= ylo && r < yhi) A[(size_t)r * lda + x] = top;
         }
     }
 }
