@@ -1061,8 +1061,9 @@ void iteration(kc_hier* h, int drv, const kc_cycle_params& c, std::vector<Launch
 }
 
 // iterations captured in one graph: each graph launch costs a fixed gap on the stream (about
-// 20 us on MI355X), so runs of GRAPH_ITERS iterations go as one launch and the remainder as
-// single-iteration launches (exactly `times` iterations either way)
+// 6 us on MI355X), so runs of GRAPH_ITERS iterations go as one launch and the remainder as
+// single-iteration launches (exactly `times` iterations either way; an iteration's launches
+// take the same arguments every time, so four captured copies equal four replays of one)
 constexpr int GRAPH_ITERS = 4;
 
 // the graph of `reps` consecutive iterations (captured on first use, kept until the plan changes)
