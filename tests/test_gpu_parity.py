@@ -100,6 +100,27 @@ def test_one_cycle_bitwise(n, nc, kappa, nu1, nu2, mode, graph):
     assert np.array_equal(host(v), ref2)
 
 
+@pytest.mark.parametrize("reps", [3, 4, 5, 9])
+def test_multi_cycle_graphs_exact_count(reps):
+    """Runs of cycles are replayed as graphs of four cycles plus single-cycle
+    graphs for the remainder: time_cycles (one warm-up cycle, then reps timed
+    ones) must leave exactly 1 + reps oracle cycles in v, bit for bit."""
+    n, kappa = 127, 2
+    banner(f"multi-cycle graphs n={n} kappa={kappa} reps={reps}")
+    rng = np.random.default_rng(500 + reps)
+    th, ep = 0.6, 4e-3
+    v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
+    H = K().Hierarchy([(n, th, ep)])
+    v = dev(v0)
+    H.time_cycles(v, dev(f), kappa=kappa, reps=reps)
+    Ho = O.Hierarchy(n, th, ep)
+    ref = v0
+    for _ in range(1 + reps):
+        ref = Ho.cycle(ref, f, kappa=kappa)[0]
+    assert np.array_equal(host(v), ref)
+    H.close()
+
+
 @pytest.mark.parametrize("n,kappa,small", [(255, 3, 4095), (1023, 2, 255), (1023, 2 ** 31 - 1, 511)])
 def test_small_tile_option(n, kappa, small):
     """16 x 16 tiles on the small levels give the same bits as the oracle,
