@@ -165,7 +165,7 @@ def test_galerkin_levels_consistent_on_quadratics(theta, eps):
 
 @pytest.mark.parametrize("nc", [1, 3, 7])
 def test_coarsest_solve_dense(nc):
-    """A one-level hierarchy is the coarsest solve alone (Algorithm 3, line 1)."""
+    """A one-level hierarchy is the coarsest solve alone (Algorithm 3, the coarsest grid)."""
     theta, eps = 0.9, 3e-3
     H = O.Hierarchy(nc, theta, eps, n_coarsest=nc)
     assert H.levels == 1
