@@ -120,6 +120,10 @@ typedef struct {
     int32_t zebra_wave_n;   /* zebra line relaxation on levels with n >= this solves each line with half a wave (two
                                lines per wave, 32 points per chunk, many lines in flight); smaller levels use one
                                thread per line (0 = never; 0..16383; default 63); results do not depend on it */
+    int32_t zebra_quad_n;   /* of those levels, the ones with n >= this solve each line with a quarter wave (four
+                               lines per wave, 16 points per chunk: on the largest levels the line recurrences then
+                               share fewer LDS instructions per point; 0 = never; 0..16383; default 8191); results
+                               do not depend on it */
 } kc_exec;
 
 typedef struct kc_hier kc_hier;

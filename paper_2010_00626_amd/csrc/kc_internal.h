@@ -18,6 +18,7 @@ constexpr int TM = 32;            // mid-level tile side of the fused kernels
 constexpr int TT = 8;             // tiny tile side of the fused kernels (one point per thread and phase)
 constexpr int STRIP_BLOCK_W = 216; // columns of a streaming block (4 strips of 54)
 constexpr int GRID_THREADS = 256; // threads of the grid-wide kernels
+constexpr int ZEBRA_QUAD_LPW = 4; // lines per wave of the zebra line kernel on its largest levels
 constexpr int HIST_CAP = 8192;    // relres history entries kept per instance
 
 // one level of one instance; arrays are row-major with leading dimension ld.

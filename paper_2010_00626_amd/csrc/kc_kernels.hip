@@ -797,23 +797,24 @@ struct ZFwd {
     }
 };
 
-// a wave's LDS slots for one chunk of each of its two lines: the lanes' (d_q, r_q)
+// a wave's LDS slots for one chunk of each of its 64 / ZC lines: the lanes' (d_q, r_q)
 // or (y_q, u_q) pairs, read back one per step by the lane running that line's
 // recurrence, and the chunk's results, written by that lane and read by every
-// lane of the line
-constexpr int ZC = 32;   // points per chunk and line (two lines per wave)
-template <typename T>
+// lane of the line.  ZC (points per chunk and line) is 32 (two lines per wave) or
+// 16 (four lines per wave); the slots of a wave take the same bytes either way
+template <typename T, int ZC>
 struct ZSlots {
-    T pair[2][ZC][2];
-    T res[2][ZC];
+    T pair[64 / ZC][ZC][2];
+    T res[64 / ZC][ZC];
 };
 
-template <typename T, int DIR>
-__device__ __forceinline__ void zebra_wave(const ZLine<T, DIR>& z, ZSlots<T>& sl)
+template <typename T, int DIR, int ZC>
+__device__ __forceinline__ void zebra_wave(const ZLine<T, DIR>& z, ZSlots<T, ZC>& sl)
 {
+    static_assert(ZC == 32 || ZC == 16, "a line takes half or a quarter of a wave");
     constexpr int SB = 8;   // steps per block: the block's pairs are read one block ahead
-    const int n = z.n, lane = threadIdx.x & 63, h = lane >> 5, p = lane & (ZC - 1);
-    const bool runner = p == 0;   // lanes 0 and 32 run the recurrences of the two lines
+    const int n = z.n, lane = threadIdx.x & 63, h = lane / ZC, p = lane & (ZC - 1);
+    const bool runner = p == 0;   // the first lane of each line's group runs its recurrence
     ZFwd<T> cur;
     cur.load(z, p);
     T prev = T(0);
@@ -865,8 +866,8 @@ __device__ __forceinline__ void zebra_wave(const ZLine<T, DIR>& z, ZSlots<T>& sl
                 }
             }
         };
-        // two lanes run the recurrences: each instruction advances both lines, and the LDS
-        // returns 2 x 16 bytes per step
+        // the runner lanes run the recurrences: each instruction advances every line of the
+        // wave, and the LDS returns 16 bytes per line and step
         if (runner) {
             if (cnt == ZC) steps(std::false_type{});
             else steps(std::true_type{});
@@ -883,7 +884,7 @@ __device__ __forceinline__ void zebra_wave(const ZLine<T, DIR>& z, ZSlots<T>& sl
 
     // backward, chunks from the last one down; a lane owns the points it wrote above
     const int c_last = (n - 1) / ZC;
-    const T ylast = __shfl(prev, lane & ZC, 64);   // y_{n-1}, kept by the line's runner lane
+    const T ylast = __shfl(prev, lane & (64 - ZC), 64);   // y_{n-1}, kept by the line's runner lane
     T next = prev;   // x_{n-1} = y_{n-1} (runner lanes)
     T yv, uv;
     {
@@ -956,7 +957,7 @@ __device__ __forceinline__ void zebra_wave(const ZLine<T, DIR>& z, ZSlots<T>& sl
 template <typename T, int DIR>
 __global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
 {
-    __shared__ ZSlots<T> slots[GRID_THREADS / 64];
+    __shared__ ZSlots<T, 32> slots[GRID_THREADS / 64];
     const int b = blockIdx.x;
     const int inst = find_inst(a.tile_off, a.count, b);
     if (a.st[inst].done) return;
@@ -964,9 +965,12 @@ __global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
     const int d = a.depth;
     const LevelDev& Lv = I.lev[d];
     const int n = Lv.n, nx = Lv.nx;   // lines and points per line (equal except on semi-coarsened levels)
-    // the launch's threshold (flags) picks the mapping for this instance from the
-    // line length; the block table was sized the same way
-    const bool waves = a.flags > 0 && nx >= a.flags;
+    // the launch's thresholds (flags: bits 0-14 two lines per wave from this line length,
+    // bits 15-29 four lines per wave) pick the mapping for this instance from the line
+    // length; the block table was sized the same way
+    const int wave_n = a.flags & 0x7fff, quad_n = (a.flags >> 15) & 0x7fff;
+    const bool waves = wave_n > 0 && nx >= wave_n;
+    const bool quad = waves && quad_n > 0 && nx >= quad_n;
     int blk = b - a.tile_off[inst];
     int line;
     if (waves) {
@@ -974,11 +978,12 @@ __global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
         // eight XCDs), so y-lines sharing cache lines share an L2
         const int nb = a.tile_off[inst + 1] - a.tile_off[inst];
         if ((a.tile_off[inst] & 7) == 0 && (nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
-        // two lines per wave, lanes 0-31 and 32-63; a second line past the level's last one
-        // repeats the first (the same values go to the same addresses twice)
-        const int first = 2 * (blk * (GRID_THREADS / 32) + 2 * (int)(threadIdx.x >> 6)) + a.dst;
+        // lpw lines per wave, 64 / lpw lanes each; a line past the level's last one repeats
+        // the wave's first (the same values go to the same addresses again)
+        const int lpw = quad ? ZEBRA_QUAD_LPW : 2;
+        const int first = 2 * (blk * (GRID_THREADS / 64) * lpw + lpw * (int)(threadIdx.x >> 6)) + a.dst;
         if (first >= n) return;   // the whole wave
-        line = first + 2 * (int)((threadIdx.x >> 5) & 1);
+        line = first + 2 * (int)((threadIdx.x & 63) / (64 / lpw));
         if (line >= n) line = first;
     } else {
         if (threadIdx.x >= 64) return;
@@ -1010,8 +1015,12 @@ __global__ void __launch_bounds__(GRID_THREADS) k_zebra(StageArgs a)
     z.hp = line + 1 < n;   // n lines
     z.Lm = z.hm ? line - 1 : line;   // clamped; values masked when absent
     z.Lp = z.hp ? line + 1 : line;
-    if (waves) {
-        zebra_wave<T, DIR>(z, slots[threadIdx.x >> 6]);
+    if (quad) {
+        using QS = ZSlots<T, 64 / ZEBRA_QUAD_LPW>;
+        static_assert(sizeof(QS) == sizeof(ZSlots<T, 32>), "one slot array serves both mappings");
+        zebra_wave<T, DIR, 64 / ZEBRA_QUAD_LPW>(z, *reinterpret_cast<QS*>(&slots[threadIdx.x >> 6]));
+    } else if (waves) {
+        zebra_wave<T, DIR, 32>(z, slots[threadIdx.x >> 6]);
     } else {
         zebra_lanes<T, DIR>(z);
     }

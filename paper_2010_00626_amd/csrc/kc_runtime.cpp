@@ -250,20 +250,18 @@ int tiles_of(int n) { return ((n + TX - 1) / TX) * ((n + TY - 1) / TY); }
 int tiles_small(int n) { return ((n + TS - 1) / TS) * ((n + TS - 1) / TS); }
 int tiles_mid(int n) { return ((n + TM - 1) / TM) * ((n + TM - 1) / TM); }
 int tiles_tiny(int n) { return ((n + TT - 1) / TT) * ((n + TT - 1) / TT); }
-// zebra launches: the lines of one colour ((n + 1) / 2 at most), two per wave (eight per
-// workgroup) on levels with n >= wave_n > 0, else one per thread (64 per workgroup)
-int zebra_blocks(int n, int wave_n)
-{
-    const int lines = (n + 1) / 2;
-    return (wave_n > 0 && n >= wave_n) ? (lines + GRID_THREADS / 32 - 1) / (GRID_THREADS / 32) : (lines + 63) / 64;
-}
-// the same for a level of `lines` lines of nx points (the mapping follows the line length)
-int zebra_blocks_lines(int lines, int nx, int wave_n)
+// zebra launches: the lines of one colour, ZEBRA_QUAD_LPW or two per wave on levels whose lines
+// have nx >= quad_n > 0 or nx >= wave_n > 0 points, else one per thread (64 per workgroup);
+// k_zebra takes the same decision per instance from the thresholds packed by zebra_flags
+int zebra_blocks_lines(int lines, int nx, int wave_n, int quad_n)
 {
     const int per_colour = (lines + 1) / 2;
-    return (wave_n > 0 && nx >= wave_n) ? (per_colour + GRID_THREADS / 32 - 1) / (GRID_THREADS / 32)
-                                        : (per_colour + 63) / 64;
+    if (!(wave_n > 0 && nx >= wave_n)) return (per_colour + 63) / 64;
+    const int per_block = (GRID_THREADS / 64) * ((quad_n > 0 && nx >= quad_n) ? ZEBRA_QUAD_LPW : 2);
+    return (per_colour + per_block - 1) / per_block;
 }
+int zebra_blocks(int n, int wave_n, int quad_n) { return zebra_blocks_lines(n, n, wave_n, quad_n); }
+int zebra_flags(const kc_exec& e) { return e.zebra_wave_n | (e.zebra_quad_n << 15); }
 int tiles_rect(int nx, int ny) { return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY); }
 // streaming blocks: STRIP_BLOCK_W columns x R rows, R = 16 << code; 32 rows from 2047^2 up for both
 // parts (measured faster than 16 or 64 at 8191^2 and 16383^2); the post-smoothing keeps a shape of its
@@ -624,7 +622,7 @@ void gen_paper(kc_hier* h, int d, int k, const kc_cycle_params& c, bool f32, int
         L.sa.src = cur[d];
         L.sa.dst = 0;
         L.sa.nu = 0;
-        L.sa.flags = h->ex.zebra_wave_n;
+        L.sa.flags = zebra_flags(h->ex);
         out.push_back(L);
         return;
     }
@@ -658,7 +656,7 @@ void gen_paper(kc_hier* h, int d, int k, const kc_cycle_params& c, bool f32, int
                 L.sa.src = cur[d];
                 L.sa.dst = color;
                 L.sa.nu = h->semi ? 0 : (r & 1);   // semi-coarsening relaxes x-lines only
-                L.sa.flags = h->ex.zebra_wave_n;   // per instance: two lines per wave at n >= this
+                L.sa.flags = zebra_flags(h->ex);   // per instance: lines per wave from the line length
                 out.push_back(L);
             }
         } else {
@@ -752,11 +750,11 @@ kc_status build_tables(kc_hier* h, const std::vector<char>* active)
             const bool lvl = d < L - 1 && hi.cut > d;
             if (h->semi) {   // rectangular levels; the coarsest line is solved by the zebra kernel
                 h->tiles[tt_lvl(d)][i + 1] = lvl ? tiles_rect(hi.il.nx[d], hi.il.n[d]) : 0;
-                h->tiles[tt_zeb(d)][i + 1] = d < L ? zebra_blocks_lines(hi.il.n[d], hi.il.nx[d], h->ex.zebra_wave_n) : 0;
+                h->tiles[tt_zeb(d)][i + 1] = d < L ? zebra_blocks_lines(hi.il.n[d], hi.il.nx[d], h->ex.zebra_wave_n, h->ex.zebra_quad_n) : 0;
                 continue;
             }
             h->tiles[tt_lvl(d)][i + 1] = lvl ? tiles_of(hi.il.n[d]) : 0;
-            h->tiles[tt_zeb(d)][i + 1] = lvl ? zebra_blocks(hi.il.n[d], h->ex.zebra_wave_n) : 0;
+            h->tiles[tt_zeb(d)][i + 1] = lvl ? zebra_blocks(hi.il.n[d], h->ex.zebra_wave_n, h->ex.zebra_quad_n) : 0;
             if (hi.cut == d && d < L) h->lists[lt_sub(d)].push_back(i);
             if (L - 1 == d) h->lists[lt_coarse(d)].push_back(i);
         }
@@ -1440,6 +1438,7 @@ void kc_exec_default(kc_exec* e)
     e->mid_tile_n = 2047;
     e->tiny_tile_n = 255;
     e->zebra_wave_n = 63;
+    e->zebra_quad_n = 8191;
     e->wave_regs = 1;
     e->fuse_junctions = 1;
 }
@@ -1549,6 +1548,7 @@ static kc_status validate_exec(const kc_exec* e, int prec)
     if (e->mid_tile_n < 0 || e->mid_tile_n > 4095) return fail(KC_ERR_ARG, "mid_tile_n must be in 0..4095");
     if (e->tiny_tile_n < 0 || e->tiny_tile_n > 4095) return fail(KC_ERR_ARG, "tiny_tile_n must be in 0..4095");
     if (e->zebra_wave_n < 0 || e->zebra_wave_n > 16383) return fail(KC_ERR_ARG, "zebra_wave_n must be in 0..16383");
+    if (e->zebra_quad_n < 0 || e->zebra_quad_n > 16383) return fail(KC_ERR_ARG, "zebra_quad_n must be in 0..16383");
     if (e->wave_regs != 0 && e->wave_regs != 1) return fail(KC_ERR_ARG, "wave_regs must be 0 or 1");
     if (e->fuse_junctions != 0 && e->fuse_junctions != 1) return fail(KC_ERR_ARG, "fuse_junctions must be 0 or 1");
     if (e->coarse_threads * 8 < 64 * e->coarse_cutover) return fail(KC_ERR_ARG, "coarse_threads too small for the cutover");
@@ -2193,6 +2193,7 @@ kc_status kc_stats(const kc_hier* h, char* out, size_t cap)
     js += ", \"mid_tile_n\": " + std::to_string(h->ex.mid_tile_n);
     js += ", \"tiny_tile_n\": " + std::to_string(h->ex.tiny_tile_n);
     js += ", \"zebra_wave_n\": " + std::to_string(h->ex.zebra_wave_n);
+    js += ", \"zebra_quad_n\": " + std::to_string(h->ex.zebra_quad_n);
     js += ", \"wave_regs\": " + std::to_string(h->ex.wave_regs);
     js += ", \"fuse_junctions\": " + std::to_string(h->ex.fuse_junctions);
     js += ", \"subtree_lds_bytes\": " + std::to_string(h->sub_lds);

@@ -52,7 +52,7 @@ class Exec(C.Structure):
                 ("small_tile_n", C.c_int32), ("stream_n", C.c_int32),
                 ("wave_regs", C.c_int32), ("fuse_junctions", C.c_int32), ("mid_tile_n", C.c_int32),
                 ("tiny_tile_n", C.c_int32),
-                ("zebra_wave_n", C.c_int32)]
+                ("zebra_wave_n", C.c_int32), ("zebra_quad_n", C.c_int32)]
 
 
 _lib = None
@@ -117,7 +117,7 @@ def exec_options(mode: int | str = 0, use_graph: bool = True, coarse_cutover: in
                  coarse_threads: int = 512, poll_every: int = 0, coarse_wave_n: int = 15,
                  small_tile_n: int = 511, stream_n: int = 2047, wave_regs: int = 1,
                  fuse_junctions: int = 1, mid_tile_n: int = 2047, tiny_tile_n: int = 255,
-                 zebra_wave_n: int = 63) -> Exec:
+                 zebra_wave_n: int = 63, zebra_quad_n: int = 8191) -> Exec:
     e = Exec()
     lib().kc_exec_default(C.byref(e))
     e.mode = {"fused": 0, "paper": 1}.get(mode, mode) if isinstance(mode, str) else int(mode)
@@ -133,6 +133,7 @@ def exec_options(mode: int | str = 0, use_graph: bool = True, coarse_cutover: in
     e.mid_tile_n = int(mid_tile_n)
     e.tiny_tile_n = int(tiny_tile_n)
     e.zebra_wave_n = int(zebra_wave_n)
+    e.zebra_quad_n = int(zebra_quad_n)
     return e
 
 

@@ -28,8 +28,17 @@ Times: stand-alone total = cycles x (median device time per cycle of the
 chunks); MGCG total = wall time of one run of exactly k iterations (setup and
 host polling included, as the paper's totals include theirs).
 
+Timing only (`--solvers timing`): the device time per cycle (three back-to-back
+cycles) and the wall time of CG runs of 2 and 6 iterations, without solving.
+With `--counts FILE` (the JSON lines of an earlier full run of the same
+tables) the totals are rebuilt from its counts: cycles x time per cycle, and
+the 2-iteration run plus (iterations - 2) x time per iteration.  Iterates, and
+so the counts, do not depend on the execution options, which only change the
+time.
+
 Usage: python -m paper_2010_00626_amd.protocol [--tables] [--sweep 9,13] [--zebra-levels 12] [--zebra-exec JSON]
-       [--semi-levels 12] [--angles 10,30,45,60,80] [--solvers standalone,mgcg] [--maxc 40000]
+       [--semi-levels 12] [--angles 10,30,45,60,80] [--solvers standalone,mgcg,timing] [--maxc 40000]
+       [--counts FILE]
 Prints one JSON object per result line and a summary object at the end.
 """
 from __future__ import annotations
@@ -122,8 +131,46 @@ def mgcg(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, kmax: int = 4000, s
     return {"iterations": hi, "total_ms": dt, "ms_per_iteration": dt / hi, "final_error": err(hi)}
 
 
+def timing(H, v0, kappa: int, nu: int = 2, omega: float = 0.8, smoother: str = "jacobi") -> dict:
+    import torch
+    f = torch.zeros_like(v0)
+    v = v0.clone()
+    ms_c = H.time_cycles(v, f, kappa=kappa, nu1=nu, nu2=nu, omega=omega, reps=3, smoother=smoother)
+    b = torch.empty_like(v0)
+    H.apply_A(b, v0)
+    u = torch.zeros_like(v0)
+    wall = {}
+    for m in (2, 6):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.pcg(u, b, kappa=kappa, nu1=nu, nu2=nu, omega=omega, tol=0.0, maxit=m, smoother=smoother)
+        torch.cuda.synchronize()
+        wall[m] = (time.perf_counter() - t0) * 1e3
+    return {"ms_per_cycle": ms_c, "pcg_ms_2": wall[2], "ms_per_iteration": (wall[6] - wall[2]) / 4}
+
+
+def with_counts(r: dict, counts: list) -> dict:
+    """Totals of a timing result from the counts of an earlier full run of the same problem."""
+    def same(c):
+        return all(c.get(k) == r[k] for k in ("levels", "theta", "eps", "kappa", "smoother", "coarsening"))
+    for c in counts:
+        if not same(c):
+            continue
+        if c.get("solver") == "standalone" and c.get("cycles"):
+            r["cycles"] = c["cycles"]
+            r["standalone_total_ms"] = c["cycles"] * r["ms_per_cycle"]
+        elif c.get("solver") == "standalone":
+            r["cycles_cap"] = c.get("cap")
+        if c.get("solver") == "mgcg" and c.get("iterations"):
+            r["iterations"] = c["iterations"]
+            r["mgcg_total_ms"] = r["pcg_ms_2"] + (c["iterations"] - 2) * r["ms_per_iteration"]
+    return r
+
+
 def run(levels: int, theta: float, eps: float, kappas, which: str, seed: int, maxc: int,
-        smoother: str = "jacobi", exec_opts: dict | None = None, coarsening: str = "full") -> list:
+        smoother: str = "jacobi", exec_opts: dict | None = None, coarsening: str = "full",
+        counts: list | None = None) -> list:
     import torch
     n = 2 ** levels - 1
     v0 = torch.from_numpy(inputs.uniform_rhs(np.random.default_rng(seed), n)).to("cuda")
@@ -131,14 +178,20 @@ def run(levels: int, theta: float, eps: float, kappas, which: str, seed: int, ma
     out = []
     for k in kappas:
         t0 = time.perf_counter()
-        r = (standalone(H, v0, k, maxc=maxc, smoother=smoother) if which == "standalone"
-             else mgcg(H, v0, k, smoother=smoother))
+        if which == "timing":
+            r = timing(H, v0, k, smoother=smoother)
+        elif which == "standalone":
+            r = standalone(H, v0, k, maxc=maxc, smoother=smoother)
+        else:
+            r = mgcg(H, v0, k, smoother=smoother)
         r.update({"solver": which, "smoother": smoother, "coarsening": coarsening, "exec": exec_opts or {},
                   "levels": levels, "n": n,
                   "theta": theta, "eps": eps,
                   "kappa": _key(k),
                   "unknowns_per_s": (n * n / (r["total_ms"] * 1e-3)) if r.get("total_ms") else None,
                   "wall_s": round(time.perf_counter() - t0, 2)})
+        if which == "timing" and counts:
+            with_counts(r, counts)
         print(json.dumps(r), flush=True)
         out.append(r)
     H.close()
@@ -159,11 +212,17 @@ def main(argv=None):
                     help='execution options of the zebra runs as JSON, e.g. \'{"mode": "paper"}\' (default: fused)')
     ap.add_argument("--semi-levels", type=int, default=0,
                     help="Tables 7 and 8 (x-line zebra, coarsening along y) at this many levels")
-    ap.add_argument("--solvers", default="standalone,mgcg", help="solvers of the zebra and semi tables")
+    ap.add_argument("--solvers", default="standalone,mgcg",
+                    help="solvers of the zebra and semi tables (timing: times per cycle and CG iteration only)")
+    ap.add_argument("--counts", default="", help="JSON lines of an earlier full run: totals for --solvers timing")
     ap.add_argument("--standalone-kappas", default="", help="kappas of the stand-alone zebra/semi runs (default: --zebra-kappas)")
     ap.add_argument("--mgcg-kappas", default="", help="kappas of the MGCG zebra/semi runs (default: --zebra-kappas)")
     a = ap.parse_args(argv)
     res = {"tables": [], "sweep": [], "zebra": [], "semi": []}
+    counts = []
+    if a.counts:
+        with open(a.counts) as fh:
+            counts = [json.loads(line) for line in fh if line.strip() and '"summary"' not in line[:12]]
     if a.tables:
         for which in ("standalone", "mgcg"):
             res["tables"] += run(12, math.pi / 4, 1e-4, KAPPAS, which, a.seed, a.maxc)
@@ -171,19 +230,19 @@ def main(argv=None):
         for e in [float(x) for x in a.eps.split(",")]:
             res["sweep"] += run(lv, math.pi / 4, e, KAPPAS, "standalone", a.seed, a.maxc)
     def kappas_of(which: str) -> list:
-        spec = {"standalone": a.standalone_kappas, "mgcg": a.mgcg_kappas}[which] or a.zebra_kappas
+        spec = {"standalone": a.standalone_kappas, "mgcg": a.mgcg_kappas}.get(which, "") or a.zebra_kappas
         return [kcycle.KAPPA_W if x == "W" else int(x) for x in spec.split(",")]
 
     if a.zebra_levels:
         for deg in [float(x) for x in a.angles.split(",")]:
             for which in a.solvers.split(","):
                 res["zebra"] += run(a.zebra_levels, math.radians(deg), 1e-5, kappas_of(which), which, a.seed, a.maxc,
-                                    "zebra", json.loads(a.zebra_exec))
+                                    "zebra", json.loads(a.zebra_exec), counts=counts)
     if a.semi_levels:
         for deg in [float(x) for x in a.angles.split(",")]:
             for which in a.solvers.split(","):
                 res["semi"] += run(a.semi_levels, math.radians(deg), 1e-5, kappas_of(which), which, a.seed, a.maxc,
-                                   "zebra", None, "semi")
+                                   "zebra", None, "semi", counts=counts)
     print(json.dumps({"summary": res}))
 
 

@@ -710,19 +710,25 @@ def test_zebra_ir_fp32(n, kappa):
     H.close()
 
 
-ZEBRA_WAVE_CASES = [(63, 2, 1, 1), (127, 2 ** 31 - 1, 1, 1), (255, 3, 3, 127), (511, 2, 1, 511), (255, 1, 1, 0)]
+ZEBRA_WAVE_CASES = [(63, 2, 1, 1, 0), (127, 2 ** 31 - 1, 1, 1, 0), (255, 3, 3, 127, 0), (511, 2, 1, 511, 0),
+                    (255, 1, 1, 0, 0),
+                    # four lines per wave: every level (line lengths 1 to 127, chunk tails of every kind),
+                    # the top levels only above two-line and one-thread levels, and the default thresholds
+                    (127, 2 ** 31 - 1, 1, 1, 1), (255, 3, 3, 63, 127), (511, 2, 1, 127, 255), (63, 2, 1, 63, 63),
+                    (255, 4, 1, 63, 8191)]
 
 
-@pytest.mark.parametrize("n,kappa,nc,wave_n", ZEBRA_WAVE_CASES)
-def test_zebra_line_mappings_bitwise(n, kappa, nc, wave_n):
-    """Both line mappings of the zebra kernel (two lines per wave on levels
-    with n >= zebra_wave_n, one thread per line below; 0 = threads only),
-    with chunk tails of every kind, give the oracle's bits."""
-    banner(f"zebra mappings n={n} kappa={kappa} n_coarsest={nc} zebra_wave_n={wave_n}")
+@pytest.mark.parametrize("n,kappa,nc,wave_n,quad_n", ZEBRA_WAVE_CASES)
+def test_zebra_line_mappings_bitwise(n, kappa, nc, wave_n, quad_n):
+    """Every line mapping of the zebra kernel (four lines per wave on levels
+    with n >= zebra_quad_n, two lines per wave on levels with n >=
+    zebra_wave_n, one thread per line below; 0 = never), with chunk tails of
+    every kind, gives the oracle's bits."""
+    banner(f"zebra mappings n={n} kappa={kappa} n_coarsest={nc} zebra_wave_n={wave_n} zebra_quad_n={quad_n}")
     rng = np.random.default_rng(7 * n + wave_n)
     th, ep = 2.3, 1e-4
     v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
-    H = K().Hierarchy([(n, th, ep, nc)], "f64", exec=dict(mode="paper", zebra_wave_n=wave_n))
+    H = K().Hierarchy([(n, th, ep, nc)], "f64", exec=dict(mode="paper", zebra_wave_n=wave_n, zebra_quad_n=quad_n))
     v = dev(v0)
     H.cycle(v, dev(f), kappa=kappa, nu1=2, nu2=2, smoother="zebra")
     Ho = O.Hierarchy(n, th, ep, nc, smoother="zebra")
@@ -730,14 +736,17 @@ def test_zebra_line_mappings_bitwise(n, kappa, nc, wave_n):
     H.close()
 
 
-def test_zebra_batched_ragged_mappings():
+@pytest.mark.parametrize("quad_n", [8191, 255])
+def test_zebra_batched_ragged_mappings(quad_n):
     """A ragged batch whose instances take different line mappings in the
-    same launches: each instance gets the oracle's iterations and bits."""
-    banner("zebra batched ragged")
+    same launches (with quad_n = 255: four lines per wave on 511^2 and
+    255^2, two on 127^2, one thread per line below): each instance gets the
+    oracle's iterations and bits."""
+    banner(f"zebra batched ragged, zebra_quad_n={quad_n}")
     specs = [(255, 0.4, 1e-3), (63, 1.3, 1e-2), (127, 2.6, 1e-4), (511, 0.05, 1e-5)]
     rng = np.random.default_rng(12)
     fs = [inputs.uniform_rhs(rng, s[0]) for s in specs]
-    H = K().Hierarchy(specs, "f64", exec=dict(mode="paper", zebra_wave_n=127))
+    H = K().Hierarchy(specs, "f64", exec=dict(mode="paper", zebra_wave_n=127, zebra_quad_n=quad_n))
     us = [torch.zeros((s[0], s[0]), dtype=torch.float64, device="cuda") for s in specs]
     iters, relres, status = H.solve(us, [dev(f) for f in fs], kappa=2, tol=1e-8, maxit=400, smoother="zebra")
     assert status == [0] * len(specs)
@@ -755,6 +764,7 @@ ZEBRA_FUSED_CASES = [
     (127, 4, 3, dict(coarse_cutover=15, coarse_threads=256)),              # 3 x 3 coarsest (Cholesky in LDS)
     (255, 1, 1, dict(coarse_cutover=31, coarse_threads=256, coarse_wave_n=0)),
     (511, 2, 1, dict(coarse_cutover=31, coarse_wave_n=7, wave_regs=0)),
+    (511, 3, 1, dict(coarse_cutover=63, zebra_quad_n=127)),                # four lines per wave above the cut
 ]
 
 
@@ -881,6 +891,32 @@ def test_zebra_fused_batched_fp32_refinement():
         assert np.linalg.norm(f - Ho.apply(got)) / np.linalg.norm(f) < 1e-8, k
         assert relmax(got, u_ir) <= 1e-6, k
     H.close()
+
+
+def test_zebra_fp32_step_mapping_independent():
+    """One FP32 zebra-cycle refinement step (maxit = 1) on 511^2 with every
+    line mapping (four lines per wave from 255^2, from 63^2, two lines per
+    wave only, one thread per line only): the four results are bitwise
+    equal, and within FP32 rounding of the oracle's FP32 emulation."""
+    banner("zebra FP32 step, line mappings")
+    n, kappa, th, ep = 511, 2, 0.9, 1e-4
+    f = inputs.uniform_rhs(np.random.default_rng(77), n)
+    Ho = O.Hierarchy(n, th, ep, smoother="zebra")
+    u_ref, rc, it_ref, _ = Ho.ir_solve(f, kappa=kappa, tol=1e-300, maxit=1)
+    assert rc == O.NOT_CONVERGED and it_ref == 1
+    outs = []
+    for wave_n, quad_n in ((63, 255), (1, 63), (63, 0), (0, 0)):
+        H = K().Hierarchy([(n, th, ep)], "f32", exec=dict(mode="paper", zebra_wave_n=wave_n, zebra_quad_n=quad_n))
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        it, rr, st = H.solve(u, dev(f), kappa=kappa, tol=1e-300, maxit=1, smoother="zebra")
+        assert st == [K().KC_NOT_CONVERGED] and it == [1]
+        outs.append(host(u))
+        H.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    print(f"  bitwise equal to the oracle's FP32 emulation: {np.array_equal(outs[0], u_ref)}, "
+          f"relmax {relmax(outs[0], u_ref):.2e}", flush=True)
+    assert relmax(outs[0], u_ref) <= 1e-5
 
 
 @pytest.mark.parametrize("n,nc,mode", [(1, 1, "fused"), (3, 1, "fused"), (3, 1, "paper"), (7, 7, "fused"),

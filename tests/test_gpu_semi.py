@@ -45,14 +45,16 @@ def banner(msg):
     print(f"[gpu-semi] {msg}", flush=True)
 
 
-@pytest.mark.parametrize("n,kappa,wave_n", [(1, 1, 63), (3, 2, 63), (15, 1, 63), (63, 2, 63), (63, 3, 0),
-                                            (127, 2 ** 31 - 1, 63), (255, 3, 0), (255, 1, 63), (511, 4, 63)])
-def test_semi_cycle_bitwise(n, kappa, wave_n):
-    banner(f"cycle n={n} kappa={kappa} zebra_wave_n={wave_n}")
+@pytest.mark.parametrize("n,kappa,wave_n,quad_n", [(1, 1, 63, 8191), (3, 2, 63, 8191), (15, 1, 63, 8191),
+                                                   (63, 2, 63, 8191), (63, 3, 0, 8191), (127, 2 ** 31 - 1, 63, 8191),
+                                                   (255, 3, 0, 8191), (255, 1, 63, 8191), (511, 4, 63, 8191),
+                                                   (255, 2, 63, 127), (127, 3, 1, 1)])
+def test_semi_cycle_bitwise(n, kappa, wave_n, quad_n):
+    banner(f"cycle n={n} kappa={kappa} zebra_wave_n={wave_n} zebra_quad_n={quad_n}")
     rng = np.random.default_rng(3 * n + kappa)
     th, ep = math.pi / 4, 1e-3
     v0, f = rng.uniform(-1, 1, (n, n)), rng.uniform(-1, 1, (n, n))
-    H = K().Hierarchy([(n, th, ep)], exec=dict(zebra_wave_n=wave_n), coarsening="semi")
+    H = K().Hierarchy([(n, th, ep)], exec=dict(zebra_wave_n=wave_n, zebra_quad_n=quad_n), coarsening="semi")
     v = dev(v0)
     H.cycle(v, dev(f), kappa=kappa, nu1=2, nu2=2, smoother="zebra")
     Ho = O.Hierarchy(n, th, ep, coarsening="semi")

@@ -200,7 +200,10 @@ def test_exec_options_validated_without_gpu():
     same check kc_create and kc_set_exec run), and the smoother must be 0 or 1."""
     ok = K.schedule_counts([(255, 0.4, 1e-3)], 2, smoother="zebra", zebra_wave_n=0)
     assert ok["grid_launches"] > 0
-    for bad in (dict(zebra_wave_n=-1), dict(zebra_wave_n=16384), dict(coarse_threads=384),
+    ok = K.schedule_counts([(255, 0.4, 1e-3)], 2, smoother="zebra", zebra_quad_n=63)
+    assert ok["grid_launches"] > 0
+    for bad in (dict(zebra_wave_n=-1), dict(zebra_wave_n=16384), dict(zebra_quad_n=-1),
+                dict(zebra_quad_n=16384), dict(coarse_threads=384),
                 dict(tiny_tile_n=4096), dict(wave_regs=2)):
         with pytest.raises(K.KCycleError) as ei:
             K.schedule_counts([(255, 0.4, 1e-3)], 2, **bad)
@@ -272,3 +275,20 @@ def test_semi_workspace_and_arguments():
         K.workspace_bytes([(255, 0.3, 1e-3, 3)], "f64", coarsening="semi")
     with pytest.raises(K.KCycleError):
         K.workspace_bytes([(32767, 0.3, 1e-3)], "f64", coarsening="semi")
+
+
+def test_protocol_totals_from_counts():
+    """The timing-only protocol rebuilds its totals from an earlier run's
+    counts of the same problem: cycles x time per cycle, and a 2-iteration
+    CG run plus (iterations - 2) x time per iteration; other problems and
+    uncapped runs contribute nothing."""
+    from paper_2010_00626_amd import protocol
+    key = dict(levels=14, theta=0.5, eps=1e-5, kappa="3", smoother="zebra", coarsening="full")
+    counts = [dict(key, solver="standalone", cycles=100), dict(key, solver="mgcg", iterations=12),
+              dict(key, solver="standalone", kappa="4", cycles=7), dict(key, solver="mgcg", eps=1e-4, iterations=3)]
+    r = protocol.with_counts(dict(key, ms_per_cycle=2.5, pcg_ms_2=7.0, ms_per_iteration=3.0), counts)
+    assert r["cycles"] == 100 and r["standalone_total_ms"] == 250.0
+    assert r["iterations"] == 12 and r["mgcg_total_ms"] == 7.0 + 10 * 3.0
+    capped = protocol.with_counts(dict(key, ms_per_cycle=1.0, pcg_ms_2=1.0, ms_per_iteration=1.0),
+                                  [dict(key, solver="standalone", cycles=None, cap=8000)])
+    assert capped["cycles_cap"] == 8000 and "standalone_total_ms" not in capped
