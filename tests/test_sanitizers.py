@@ -98,6 +98,7 @@ def test_host_runtime_under_asan_ubsan(tmp_path):
             for mode in ("fused", "paper"):
                 for sm in ("jacobi", "zebra"):
                     K.schedule_counts(probs, kappa, mode=mode, smoother=sm)
+                K.schedule_counts(probs, kappa, mode=mode, smoother="zebra", zebra_wave_n=1, zebra_quad_n=63)
         for bad in ([(1000, 0.3, 1e-3)], [(63, 0.3, -1.0)], [(63, 0.3, 1e-3, 5)]):
             try:
                 K.workspace_bytes(bad)
